@@ -1,0 +1,98 @@
+"""Planted mistakes: each test swaps a plausible bug into the oracle (on the
+CPU, through monkeypatch) and checks that a pin catches it.  This shows the
+pins are strong enough to trust the oracle they guard."""
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+import oracle.em as em
+import oracle.geometry as geometry
+import oracle.penalty as penalty
+
+import test_oracle_em as T_em
+import test_oracle_penalty as T_pen
+import test_oracle_siddon as T_sid
+
+
+@pytest.fixture(scope="module")
+def small():
+    P = datagen.make_problem(**datagen.CONFIG_SMALL)
+    return P, oracle.system_matrix(P.geom, P.mu)
+
+
+def test_dropped_background_is_caught(small, monkeypatch):
+    def ratio_no_bg(self, f, t):
+        yb = (self.A_t[t] @ np.atleast_2d(f).T).T
+        out = np.zeros_like(yb)
+        np.divide(self.g_t[t], yb, out=out, where=yb > 0)
+        return out
+    monkeypatch.setattr(em.Model, "ratio_t", ratio_no_bg)
+    with pytest.raises(AssertionError):
+        T_em.test_osem_count_preservation(small, 0.1)
+
+
+def test_penalty_sign_is_caught(monkeypatch):
+    orig = penalty.penalty_grad
+    monkeypatch.setattr(penalty, "penalty_grad", lambda *a, **k: -orig(*a, **k))
+    monkeypatch.setattr(oracle, "penalty_grad", penalty.penalty_grad)
+    with pytest.raises(AssertionError):
+        T_pen.test_grad_is_finite_difference(oracle.POT_QUADRATIC, False)
+
+
+def test_wrong_root_branch_is_caught(monkeypatch):
+    def bad_root(a, b, c, sens):
+        a, b, c = np.broadcast_arrays(np.asarray(a, float), np.asarray(b, float), np.asarray(c, float))
+        with np.errstate(all="ignore"):
+            f = np.where(b > 0, (c - np.sqrt(c * c + 8 * a * b)) / (4 * b), -a / c)
+        return f
+    monkeypatch.setattr(oracle, "mstep_root", bad_root)
+    with pytest.raises(AssertionError):
+        T_pen.test_mstep_root_golden()
+
+
+def test_subset_sensitivity_in_mstep_is_caught(monkeypatch):
+    """Using A_t^T 1 instead of A^T 1 in the M-step breaks Appendix B."""
+    def mstep_subset(self, s_hat, f_k):
+        f_k = np.atleast_2d(f_k)
+        return em.mstep_root(np.atleast_2d(s_hat), 0.0, -self.sens_t[0], self.sens_t[0])
+    monkeypatch.setattr(em.Model, "mstep", mstep_subset)
+    with pytest.raises(AssertionError):
+        T_em.test_svrem_appendix_b_direction()
+
+
+def test_missing_ns_factor_is_caught(monkeypatch):
+    monkeypatch.setattr(em.Model, "tau_t", lambda self, f, t: np.atleast_2d(f) * self.back_t(f, t))
+    with pytest.raises(AssertionError):
+        T_em.test_svrem_appendix_b_direction()
+
+
+def test_swapped_pixel_axes_are_caught(monkeypatch):
+    orig = geometry.siddon_rays
+
+    def swapped(geom, v):
+        ray, pix, ln = orig(geom, v)
+        iy, ix = pix // geom.nx, pix % geom.nx
+        return ray, ix * geom.nx + iy, ln
+    monkeypatch.setattr(geometry, "siddon_rays", swapped)
+    with pytest.raises(AssertionError):
+        T_sid.test_siddon_random_rays_brute_force()
+
+
+def test_missing_half_open_rule_is_caught(monkeypatch):
+    """Counting a grid-line ray in both neighbouring pixels breaks the brute force."""
+    orig = geometry.siddon_rays
+
+    def doubled(geom, v):
+        ray, pix, ln = orig(geom, v)
+        c, s = geometry.view_trig(v, geom.n_views, geom.arc_rad)
+        if s == 0.0:  # vertical rays on grid lines: also credit the lower column
+            ix = pix % geom.nx
+            extra = ix > 0
+            return (np.concatenate([ray, ray[extra]]), np.concatenate([pix, pix[extra] - 1]),
+                    np.concatenate([ln, ln[extra]]))
+        return ray, pix, ln
+    monkeypatch.setattr(geometry, "siddon_rays", doubled)
+    with pytest.raises(AssertionError):
+        T_sid.test_vertical_view_gives_pixel_size_per_pixel()
