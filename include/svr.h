@@ -1,0 +1,275 @@
+/*
+ * svr.h -- C ABI of the MI355X variance-reduced stochastic EM library.
+ *
+ * The library reconstructs images from Poisson emission data with the model
+ * of Kereta, Twyman, Arridge, Thielemans and Jin, "Stochastic EM methods with
+ * variance reduction for penalised PET reconstructions" (arXiv:2106.03172):
+ *
+ *   E[g] = A f + w                      (Sec. 2.1, eq. voxel_td)
+ *   Phi(f) = L(f) - beta R(f), f >= 0   (Sec. 3, eq. PET-MAP)
+ *
+ * with an ordered-subset partition of the data (Sec. 2.1), the OSEM update
+ * (Sec. 2.2), SVREM (Sec. 2.3, eq. tempsvrem, with the penalised M-step of
+ * Sec. 3), the preconditioned SAGA and SVRG updates (Sec. 4, eq. saga_update
+ * and svrg_update) and the SGA, BSREM and SEM baselines (Sec. 4, Sec. 5.1).
+ *
+ * Conventions shared by every call:
+ *  - Every call returns an int status (SVR_OK = 0, negative on error); no
+ *    C++ exception crosses the ABI.  svr_last_error() returns a thread-local
+ *    message describing the last non-OK status of the calling thread.
+ *  - "_dev" pointers are device memory on the current HIP device, borrowed
+ *    from the caller: they must stay valid until the work enqueued on the
+ *    given stream has completed.  Host arrays are copied before return.
+ *  - "stream" is a hipStream_t passed as void* (NULL = the default stream).
+ *    Calls that only enqueue work return before it completes; calls
+ *    documented as "synchronises" wait for the stream.
+ *  - Opaque handles are owned by the library and released with *_destroy
+ *    (NULL-safe).  A handle must not be used from two threads at once.
+ *  - Sinograms are float32 in natural order [slice][view][bin]
+ *    (m = v*B + b); images are float32 [slice][iy][ix] (n = iy*nx + ix).
+ *  - Invalid arguments return SVR_EINVAL before anything is enqueued.
+ */
+#ifndef SVR_H
+#define SVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define SVR_OK          0
+#define SVR_PENDING     1   /* serving: request not finished yet */
+#define SVR_EINVAL     -1   /* invalid argument or state */
+#define SVR_ENOMEM     -2   /* device or host allocation failed */
+#define SVR_EDEVICE    -3   /* HIP runtime error */
+#define SVR_ENOTFOUND  -4   /* unknown ticket */
+#define SVR_ENUMERIC   -5   /* non-finite objective or data */
+#define SVR_ECANCELLED -6   /* request cancelled */
+
+/* Message for the last non-OK status returned on this thread ("" if none). */
+const char *svr_last_error(void);
+/* Library ABI version (major*10000 + minor*100 + patch). */
+int svr_version(void);
+
+/* ---- geometry and system matrix ----------------------------------------- */
+
+/* 2D parallel-beam scanner.  View v has angle v*arc_rad/n_views; bin b sits
+ * at radial offset (b - (n_bins-1)/2)*bin_mm; the image grid has nx*ny square
+ * pixels of pixel_mm centred on the rotation axis.  The paper leaves the
+ * projector open (Sec. 2.1 only asks for a non-negative A); this library uses
+ * exact ray/pixel intersection lengths in mm (Siddon's method), computed in
+ * FP64 with half-open pixels, axis-snapped views (|cos|,|sin| < 1e-12 -> 0)
+ * and pieces shorter than 1e-9 pixel dropped. */
+typedef struct {
+    int32_t nx, ny;
+    double  pixel_mm;
+    int32_t n_views, n_bins;
+    double  bin_mm;
+    double  arc_rad;     /* angular range, normally pi */
+} svr_geometry;
+
+/* Storage type of the matrix weights (index arrays are int32).  Products
+ * are accumulated in FP64 whatever the storage type. */
+enum { SVR_W_F32 = 0, SVR_W_F16 = 1, SVR_W_BF16 = 2 };
+
+typedef struct svr_matrix svr_matrix;
+typedef struct svr_recon  svr_recon;
+typedef struct svr_server svr_server;
+
+/* Builds A on the device (Sec. 2.1, eq. voxel_td) together with its ordered
+ * subsets (Sec. 2.1): subset t holds the views v = t (mod n_subsets), and its
+ * rows are stored view-major, bin-minor.  Two layouts are kept: the rows of A
+ * in subset order (forward projection) and, per subset, the transposed rows
+ * (one per pixel, entries by ascending view and bin) for a gather-only
+ * back-projection.  Also computes the sensitivities A_t^T 1 and A^T 1.
+ *   geom        : scanner; nx, ny, n_views, n_bins >= 1, sizes > 0
+ *   n_subsets   : 1 <= n_subsets <= n_views
+ *   wtype       : SVR_W_F32 / SVR_W_F16 / SVR_W_BF16 (round to nearest even)
+ *   mu_dev      : optional attenuation map (nx*ny floats, 1/mm, >= 0) or NULL;
+ *                 every weight of ray m is multiplied by exp(-sum_n a_mn mu_n)
+ *   stream      : work is enqueued there; the call synchronises before return
+ *   out         : receives the new handle (release with svr_matrix_destroy)
+ * Errors: SVR_EINVAL (bad sizes, nnz beyond int32), SVR_ENOMEM, SVR_EDEVICE. */
+int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t wtype,
+                            const float *mu_dev, void *stream, svr_matrix **out);
+
+typedef struct {
+    int64_t nnz;           /* non-zeros of A */
+    int64_t bytes;         /* device bytes held by the matrix object */
+    int32_t n_subsets;
+    int32_t n_rows;        /* M = n_views * n_bins */
+    int32_t n_pixels;      /* N = nx * ny */
+    int32_t max_row_nnz;   /* longest row of A */
+    int32_t max_col_nnz;   /* longest transposed row of any subset */
+    int32_t wtype;
+} svr_matrix_info_t;
+
+/* Sizes of a built matrix; nnz_per_subset (nullable) receives n_subsets
+ * counts.  Synchronous, host-only. */
+int svr_matrix_info(const svr_matrix *A, svr_matrix_info_t *info, int64_t *nnz_per_subset);
+
+/* Copies one layout of A to host buffers, for inspection and tests.
+ *   which = 0: rows of A in natural sinogram order (row m = v*B + b):
+ *              ptr[M+1], idx[nnz] = pixel, val[nnz] as float
+ *   which = 1: transposed rows, subset-major: ptr[Ns*N+1], row (t*N + n)
+ *              lists idx = subset-local row (view-major, bin-minor), val
+ * Any of ptr/idx/val may be NULL to skip it.  Synchronises. */
+int svr_matrix_export(const svr_matrix *A, int32_t which, int32_t *ptr, int32_t *idx, float *val);
+
+/* Sensitivity A_t^T 1 (subset >= 0, stored FP32 from an FP64 sum) or A^T 1
+ * (subset = -1, FP64) into out_dev (N doubles). */
+int svr_sensitivity(const svr_matrix *A, int32_t subset, double *out_dev, void *stream);
+
+void svr_matrix_destroy(svr_matrix *A);
+
+/* ---- projectors ---------------------------------------------------------- */
+
+/* Forward projection y = A_t x (subset t; subset = -1: all of A).  Only the
+ * bins of subset t are written; others are left untouched.
+ *   x_dev : [n_slices][N] floats;  y_dev : [n_slices][M] floats (natural order) */
+int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t n_slices,
+                float *y_dev, void *stream);
+
+/* Back-projection x = A_t^T y over the bins of subset t (subset = -1: A^T y).
+ * x_dev is overwritten.  Gather-only and deterministic (fixed summation order). */
+int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int32_t n_slices,
+                    float *x_dev, void *stream);
+
+/* ---- reconstruction ------------------------------------------------------ */
+
+enum { SVR_ALGO_OSEM = 0, SVR_ALGO_SVREM = 1, SVR_ALGO_SVRG = 2, SVR_ALGO_SAGA = 3,
+       SVR_ALGO_SGA = 4, SVR_ALGO_BSREM = 5, SVR_ALGO_SEM = 6 };
+/* Potentials of Table 1 (Sec. 3). */
+enum { SVR_PEN_QUADRATIC = 0, SVR_PEN_HUBER = 1, SVR_PEN_LOGCOSH = 2, SVR_PEN_HYPERBOLA = 3 };
+/* Preconditioner of the gradient methods (Sec. 4, eq. preconditioners, frozen
+ * at the first iteration as the experiments of Sec. 5 do). */
+enum { SVR_PRECOND_SUBSET_FROZEN = 0,  /* d_t = f0 / A_t^T 1 */
+       SVR_PRECOND_FULL_FROZEN   = 1,  /* d   = f0 / A^T 1   */
+       SVR_PRECOND_ITERATE       = 2 };/* d_t = f^k / A_t^T 1 */
+#define SVR_FLAG_RESET_SHAT_AT_ANCHOR 1 /* SVREM: s_hat = s_anc at every anchor */
+#define SVR_FLAG_AXIAL_PENALTY        2 /* slices: add the 2 axial neighbours */
+
+typedef struct {
+    int32_t algo;      /* SVR_ALGO_*: which state the recon keeps */
+    double  alpha;     /* step size (> 0); BSREM/SEM: a_0 of a_k = alpha/(decay*k+1) */
+    int32_t eta;       /* SVREM/SVRG anchor period in epochs (>= 1) */
+    double  beta;      /* penalty strength (>= 0) */
+    int32_t penalty;   /* SVR_PEN_* */
+    double  delta;     /* potential parameter (> 0 for Huber/log cosh/hyperbola) */
+    int32_t precond;   /* SVR_PRECOND_* (SVRG, SAGA) */
+    int32_t flags;     /* SVR_FLAG_* */
+    double  decay;     /* BSREM/SEM step decay (0.001 in the paper) */
+} svr_params;
+
+/* Creates a reconstruction of n_slices images that share A (the slices are
+ * coupled only by the optional axial penalty).  g, w and f0 are copied.
+ *   g_dev  : [S][M] counts (finite, >= 0);  w_dev: [S][M] background (finite, >= 0)
+ *   f0_dev : [S][N] starting image (finite, > 0)
+ * The matrix must outlive the recon.  Synchronises (validates the data). */
+int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, const float *f0_dev,
+                     int32_t n_slices, const svr_params *params, void *stream, svr_recon **out);
+
+/* Epochs.  Each runs n subset updates with the subsets order[0..n-1] (host
+ * array, entries in [0, n_subsets); the paper draws them uniformly at random,
+ * which is left to the caller so that runs are reproducible).  The iteration
+ * counter k persists across calls.
+ *  osem : f <- f * A_t^T(g_t/(A_t f + w_t)) / A_t^T 1 (Sec. 2.2, eq. Mstep).
+ *         Usable with every algo as the initialiser; it resets the
+ *         variance-reduction state (k = 0) of the recon.
+ *  svrem: at k mod (eta*Ns) == 0 stores tau_t(f) for all t and their mean
+ *         s_anc (FP64) (Sec. 2.3, eq. tempsvrem); s_hat <- (1-alpha) s_hat
+ *         + alpha (tau_t(f) - tau_t(f_anc) + s_anc); f <- penalised M-step root
+ *         (Sec. 3, eq. svrsurder).  s_hat starts at s(f^0).
+ *  svrg : preconditioned proximal SVRG (Sec. 4, eq. svrg_update) with the
+ *         anchor gradient table refreshed at k mod (eta*Ns) == 0.
+ *  saga : preconditioned proximal SAGA (Sec. 4, eq. saga_update); the table
+ *         is filled at f^0 at k = 0.
+ *  sga, bsrem, sem: the non-variance-reduced baselines of Sec. 5.1.
+ * The call must match params.algo (osem excepted).  Enqueues only. */
+int svr_osem_epoch (svr_recon *R, const int32_t *order, int32_t n, void *stream);
+int svr_svrem_epoch(svr_recon *R, const int32_t *order, int32_t n, void *stream);
+int svr_svrg_epoch (svr_recon *R, const int32_t *order, int32_t n, void *stream);
+int svr_saga_epoch (svr_recon *R, const int32_t *order, int32_t n, void *stream);
+int svr_sga_epoch  (svr_recon *R, const int32_t *order, int32_t n, void *stream);
+int svr_bsrem_epoch(svr_recon *R, const int32_t *order, int32_t n, void *stream);
+int svr_sem_epoch  (svr_recon *R, const int32_t *order, int32_t n, void *stream);
+
+/* Phi(f) = sum_m g_m log(ybar_m) - ybar_m - beta R(f), ybar = A f + w, in FP64
+ * over all slices (Sec. 3, eq. PET-MAP; 0 log 0 = 0).  Synchronises.
+ * Returns SVR_ENUMERIC (and marks the recon) if Phi is not finite. */
+int svr_objective(svr_recon *R, double *phi_host, void *stream);
+
+/* Copies the current image ([S][N] floats) to f_dev. */
+int svr_get_image(const svr_recon *R, float *f_dev, void *stream);
+
+typedef struct {
+    int64_t k;                /* subset updates since the last reset */
+    int64_t n_snapshots;      /* full passes taken (anchors, table fills) */
+    int32_t n_subsets, n_slices, n_pixels, n_rows;
+    int64_t state_bytes;      /* size of a svr_recon_get_state buffer */
+} svr_recon_info_t;
+int svr_recon_info(const svr_recon *R, svr_recon_info_t *info);
+
+/* Checkpoint: serialises the whole algorithm state (iterate, running
+ * statistics, anchors, tables, counters) to a host buffer.  get_state with
+ * buf = NULL reports the size in *len.  A state restored with set_state
+ * into a recon created with the same matrix, data and params continues
+ * bitwise as the uninterrupted run.  Both synchronise. */
+int svr_recon_get_state(const svr_recon *R, void *buf, size_t *len, void *stream);
+int svr_recon_set_state(svr_recon *R, const void *buf, size_t len, void *stream);
+
+void svr_recon_destroy(svr_recon *R);
+
+/* ---- serving -------------------------------------------------------------- */
+
+/* A continuous-batching server for independent SVREM reconstruction requests
+ * of different sizes.  Requests are admitted while their device footprint
+ * fits in the memory budget and a slot is free; every scheduler tick advances
+ * each resident request by one subset update, with the work of all resident
+ * requests enqueued together so that it overlaps on the device.  A request's
+ * result does not depend on which other requests share the device. */
+typedef struct {
+    int64_t mem_budget_bytes;  /* device bytes the server may hold (> 0) */
+    int32_t max_slots;         /* max resident requests (>= 1) */
+    int32_t n_streams;         /* device streams used for overlap (>= 1) */
+} svr_serve_config;
+
+typedef struct {
+    svr_geometry geom;
+    int32_t n_subsets;
+    int32_t wtype;
+    svr_params params;         /* algo must be SVR_ALGO_SVREM */
+    int32_t epochs;            /* SVREM epochs after one OSEM initialisation epoch */
+    uint64_t order_seed;       /* seeds the library's own subset sequence */
+    const float *g_host;       /* [M] counts, copied at submit */
+    const float *w_host;       /* [M] background, copied at submit */
+    float f0_value;            /* constant starting image (> 0) */
+} svr_serve_request;
+
+typedef struct {
+    float *f_host;             /* caller buffer of N floats, filled when done */
+    double phi;                /* final objective */
+    double queue_ms, run_ms;   /* time waiting for admission, time resident */
+    int32_t status;            /* SVR_OK / SVR_ENUMERIC / SVR_ECANCELLED ... */
+} svr_serve_result;
+
+int  svr_serve_create(const svr_serve_config *cfg, svr_server **out);
+/* Copies the request and queues it; rejects (SVR_EINVAL) a request that can
+ * never fit the memory budget. */
+int  svr_serve_submit(svr_server *S, const svr_serve_request *req, uint64_t *ticket);
+/* Runs scheduler ticks for up to max_ticks (0 = until every admitted request
+ * has finished) and admits queued requests as memory frees up. */
+int  svr_serve_step(svr_server *S, int32_t max_ticks);
+/* SVR_PENDING until the request is done; then fills *res (f_host must point
+ * to N floats) and forgets the ticket. */
+int  svr_serve_poll(svr_server *S, uint64_t ticket, svr_serve_result *res);
+int  svr_serve_cancel(svr_server *S, uint64_t ticket);
+void svr_serve_destroy(svr_server *S);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVR_H */

@@ -1,0 +1,337 @@
+"""Thin ctypes binding of the C ABI in ``include/svr.h``.
+
+Argument marshalling only: every step of the reconstruction runs in the HIP
+library.  PyTorch supplies device memory (tensors) and the HIP stream
+(``torch.cuda.current_stream()``).  If the built library is missing this
+module raises instead of falling back to anything else.
+
+The functions keep the C names (``svr_build_system_matrix``,
+``svr_project``, ...); ``SystemMatrix`` and ``Recon`` wrap the handles.
+"""
+
+from __future__ import annotations
+
+import ctypes as C
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "_lib", "libsvr.so")
+
+SVR_OK, SVR_PENDING, SVR_EINVAL, SVR_ENOMEM, SVR_EDEVICE = 0, 1, -1, -2, -3
+SVR_ENOTFOUND, SVR_ENUMERIC, SVR_ECANCELLED = -4, -5, -6
+SVR_W_F32, SVR_W_F16, SVR_W_BF16 = 0, 1, 2
+ALGO = dict(osem=0, svrem=1, svrg=2, saga=3, sga=4, bsrem=5, sem=6)
+PEN = dict(quadratic=0, huber=1, logcosh=2, hyperbola=3)
+PRECOND = dict(subset_frozen=0, full_frozen=1, iterate=2)
+FLAG_RESET_SHAT_AT_ANCHOR, FLAG_AXIAL_PENALTY = 1, 2
+
+
+class SvrError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__(f"svr error {code}: {msg}")
+        self.code = code
+
+
+class svr_geometry(C.Structure):
+    _fields_ = [("nx", C.c_int32), ("ny", C.c_int32), ("pixel_mm", C.c_double),
+                ("n_views", C.c_int32), ("n_bins", C.c_int32), ("bin_mm", C.c_double),
+                ("arc_rad", C.c_double)]
+
+
+class svr_matrix_info_t(C.Structure):
+    _fields_ = [("nnz", C.c_int64), ("bytes", C.c_int64), ("n_subsets", C.c_int32),
+                ("n_rows", C.c_int32), ("n_pixels", C.c_int32), ("max_row_nnz", C.c_int32),
+                ("max_col_nnz", C.c_int32), ("wtype", C.c_int32)]
+
+
+class svr_params(C.Structure):
+    _fields_ = [("algo", C.c_int32), ("alpha", C.c_double), ("eta", C.c_int32),
+                ("beta", C.c_double), ("penalty", C.c_int32), ("delta", C.c_double),
+                ("precond", C.c_int32), ("flags", C.c_int32), ("decay", C.c_double)]
+
+
+class svr_recon_info_t(C.Structure):
+    _fields_ = [("k", C.c_int64), ("n_snapshots", C.c_int64), ("n_subsets", C.c_int32),
+                ("n_slices", C.c_int32), ("n_pixels", C.c_int32), ("n_rows", C.c_int32),
+                ("state_bytes", C.c_int64)]
+
+
+class svr_serve_config(C.Structure):
+    _fields_ = [("mem_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("n_streams", C.c_int32)]
+
+
+class svr_serve_request(C.Structure):
+    _fields_ = [("geom", svr_geometry), ("n_subsets", C.c_int32), ("wtype", C.c_int32),
+                ("params", svr_params), ("epochs", C.c_int32), ("order_seed", C.c_uint64),
+                ("g_host", C.POINTER(C.c_float)), ("w_host", C.POINTER(C.c_float)),
+                ("f0_value", C.c_float)]
+
+
+class svr_serve_result(C.Structure):
+    _fields_ = [("f_host", C.POINTER(C.c_float)), ("phi", C.c_double), ("queue_ms", C.c_double),
+                ("run_ms", C.c_double), ("status", C.c_int32)]
+
+
+_lib = None
+_VP, _I32, _I64 = C.c_void_p, C.c_int32, C.c_int64
+_SIGS = {
+    "svr_last_error": ([], C.c_char_p),
+    "svr_version": ([], C.c_int),
+    "svr_build_system_matrix": ([C.POINTER(svr_geometry), _I32, _I32, _VP, _VP, C.POINTER(_VP)], C.c_int),
+    "svr_matrix_info": ([_VP, C.POINTER(svr_matrix_info_t), _VP], C.c_int),
+    "svr_matrix_export": ([_VP, _I32, _VP, _VP, _VP], C.c_int),
+    "svr_sensitivity": ([_VP, _I32, _VP, _VP], C.c_int),
+    "svr_matrix_destroy": ([_VP], None),
+    "svr_project": ([_VP, _I32, _VP, _I32, _VP, _VP], C.c_int),
+    "svr_backproject": ([_VP, _I32, _VP, _I32, _VP, _VP], C.c_int),
+    "svr_recon_create": ([_VP, _VP, _VP, _VP, _I32, C.POINTER(svr_params), _VP, C.POINTER(_VP)], C.c_int),
+    "svr_objective": ([_VP, C.POINTER(C.c_double), _VP], C.c_int),
+    "svr_get_image": ([_VP, _VP, _VP], C.c_int),
+    "svr_recon_info": ([_VP, C.POINTER(svr_recon_info_t)], C.c_int),
+    "svr_recon_get_state": ([_VP, _VP, C.POINTER(C.c_size_t), _VP], C.c_int),
+    "svr_recon_set_state": ([_VP, _VP, C.c_size_t, _VP], C.c_int),
+    "svr_recon_destroy": ([_VP], None),
+    "svr_serve_create": ([C.POINTER(svr_serve_config), C.POINTER(_VP)], C.c_int),
+    "svr_serve_submit": ([_VP, C.POINTER(svr_serve_request), C.POINTER(C.c_uint64)], C.c_int),
+    "svr_serve_step": ([_VP, _I32], C.c_int),
+    "svr_serve_poll": ([_VP, C.c_uint64, C.POINTER(svr_serve_result)], C.c_int),
+    "svr_serve_cancel": ([_VP, C.c_uint64], C.c_int),
+    "svr_serve_destroy": ([_VP], None),
+}
+for _e in ("osem", "svrem", "svrg", "saga", "sga", "bsrem", "sem"):
+    _SIGS[f"svr_{_e}_epoch"] = ([_VP, _VP, _I32, _VP], C.c_int)
+
+EXPORTED = tuple(_SIGS)
+
+
+def lib():
+    """Loads the built library (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"HIP library not built: {LIB_PATH} is missing "
+                               "(run __graft_entry__.build() or python -m paper_2106_03172_amd.build)")
+        L = C.CDLL(LIB_PATH)
+        for name, (args, res) in _SIGS.items():
+            fn = getattr(L, name)
+            fn.argtypes = args
+            fn.restype = res
+        _lib = L
+    return _lib
+
+
+def _check(rc: int) -> int:
+    if rc < 0:
+        raise SvrError(rc, lib().svr_last_error().decode())
+    return rc
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return C.c_void_p(s.cuda_stream)
+
+
+def _dev(t, dtype_name="float32"):
+    import torch
+    if t is None:
+        return None
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError("expected a CUDA (HIP) tensor")
+    if str(t.dtype) != f"torch.{dtype_name}":
+        raise TypeError(f"expected {dtype_name}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return C.c_void_p(t.data_ptr())
+
+
+def geometry(geom) -> svr_geometry:
+    return svr_geometry(int(geom.nx), int(geom.ny), float(geom.pixel_mm), int(geom.n_views),
+                        int(geom.n_bins), float(geom.bin_mm), float(getattr(geom, "arc_rad", np.pi)))
+
+
+def params(algo="svrem", alpha=1.0, eta=1, beta=0.0, penalty="quadratic", delta=1.0,
+           precond="subset_frozen", flags=0, decay=0.001) -> svr_params:
+    return svr_params(ALGO[algo] if isinstance(algo, str) else int(algo), float(alpha), int(eta),
+                      float(beta), PEN[penalty] if isinstance(penalty, str) else int(penalty),
+                      float(delta), PRECOND[precond] if isinstance(precond, str) else int(precond),
+                      int(flags), float(decay))
+
+
+# ---------------------------------------------------------------------------
+# C-named thin wrappers
+# ---------------------------------------------------------------------------
+def svr_build_system_matrix(geom, n_subsets: int, wtype: int = SVR_W_F32, mu=None, stream=None):
+    h = C.c_void_p()
+    g = geometry(geom)
+    _check(lib().svr_build_system_matrix(C.byref(g), int(n_subsets), int(wtype), _dev(mu),
+                                         _stream(stream), C.byref(h)))
+    return h
+
+
+def svr_project(A, subset: int, x, n_slices: int, y, stream=None):
+    _check(lib().svr_project(A, int(subset), _dev(x), int(n_slices), _dev(y), _stream(stream)))
+
+
+def svr_backproject(A, subset: int, y, n_slices: int, x, stream=None):
+    _check(lib().svr_backproject(A, int(subset), _dev(y), int(n_slices), _dev(x), _stream(stream)))
+
+
+def svr_recon_create(A, g, w, f0, n_slices: int, prm: svr_params, stream=None):
+    h = C.c_void_p()
+    _check(lib().svr_recon_create(A, _dev(g), _dev(w), _dev(f0), int(n_slices), C.byref(prm),
+                                  _stream(stream), C.byref(h)))
+    return h
+
+
+def _epoch(name, R, order, stream=None):
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    _check(getattr(lib(), f"svr_{name}_epoch")(R, o.ctypes.data_as(C.c_void_p), int(o.size), _stream(stream)))
+
+
+def svr_osem_epoch(R, order, stream=None): _epoch("osem", R, order, stream)
+def svr_svrem_epoch(R, order, stream=None): _epoch("svrem", R, order, stream)
+def svr_svrg_epoch(R, order, stream=None): _epoch("svrg", R, order, stream)
+def svr_saga_epoch(R, order, stream=None): _epoch("saga", R, order, stream)
+def svr_sga_epoch(R, order, stream=None): _epoch("sga", R, order, stream)
+def svr_bsrem_epoch(R, order, stream=None): _epoch("bsrem", R, order, stream)
+def svr_sem_epoch(R, order, stream=None): _epoch("sem", R, order, stream)
+
+
+def svr_objective(R, stream=None) -> float:
+    v = C.c_double()
+    _check(lib().svr_objective(R, C.byref(v), _stream(stream)))
+    return v.value
+
+
+# ---------------------------------------------------------------------------
+# handle wrappers
+# ---------------------------------------------------------------------------
+class SystemMatrix:
+    """A system matrix built on the device (``svr_build_system_matrix``)."""
+
+    def __init__(self, geom, n_subsets: int, wtype: int = SVR_W_F32, mu=None, stream=None):
+        import torch
+        self.geom = geom
+        self.n_subsets = int(n_subsets)
+        if mu is not None and not isinstance(mu, torch.Tensor):
+            mu = torch.as_tensor(np.asarray(mu, dtype=np.float32), device="cuda")
+        self.h = svr_build_system_matrix(geom, n_subsets, wtype, mu, stream)
+        self.M = geom.n_views * geom.n_bins
+        self.N = geom.nx * geom.ny
+
+    def info(self):
+        inf = svr_matrix_info_t()
+        per = np.zeros(self.n_subsets, dtype=np.int64)
+        _check(lib().svr_matrix_info(self.h, C.byref(inf), per.ctypes.data_as(C.c_void_p)))
+        return inf, per
+
+    def export(self, which: int):
+        inf, _ = self.info()
+        nrows = self.M if which == 0 else self.n_subsets * self.N
+        ptr = np.zeros(nrows + 1, dtype=np.int32)
+        idx = np.zeros(inf.nnz, dtype=np.int32)
+        val = np.zeros(inf.nnz, dtype=np.float32)
+        _check(lib().svr_matrix_export(self.h, int(which), ptr.ctypes.data_as(C.c_void_p),
+                                       idx.ctypes.data_as(C.c_void_p), val.ctypes.data_as(C.c_void_p)))
+        return ptr, idx, val
+
+    def sensitivity(self, subset: int, stream=None):
+        import torch
+        out = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        _check(lib().svr_sensitivity(self.h, int(subset), _dev(out, "float64"), _stream(stream)))
+        return out
+
+    def project(self, x, subset: int = -1, y=None, stream=None):
+        import torch
+        S = x.numel() // self.N
+        if y is None:
+            y = torch.zeros(S, self.M, dtype=torch.float32, device=x.device)
+        svr_project(self.h, subset, x, S, y, stream)
+        return y
+
+    def backproject(self, y, subset: int = -1, x=None, stream=None):
+        import torch
+        S = y.numel() // self.M
+        if x is None:
+            x = torch.empty(S, self.N, dtype=torch.float32, device=y.device)
+        svr_backproject(self.h, subset, y, S, x, stream)
+        return x
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().svr_matrix_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Recon:
+    """A reconstruction (``svr_recon_create``) bound to a SystemMatrix."""
+
+    def __init__(self, A: SystemMatrix, g, w, f0, prm: svr_params, stream=None):
+        import torch
+
+        def dev(x):
+            if isinstance(x, torch.Tensor):
+                return x.to(device="cuda", dtype=torch.float32).contiguous()
+            return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
+        self.A = A
+        self.g, self.w, f0 = dev(g), dev(w), dev(f0)
+        self.S = self.g.numel() // A.M
+        self.prm = prm
+        self.h = svr_recon_create(A.h, self.g, self.w, f0, self.S, prm, stream)
+
+    def epoch(self, name: str, order, stream=None):
+        _epoch(name, self.h, order, stream)
+
+    def osem_epoch(self, order, stream=None): _epoch("osem", self.h, order, stream)
+    def svrem_epoch(self, order, stream=None): _epoch("svrem", self.h, order, stream)
+    def svrg_epoch(self, order, stream=None): _epoch("svrg", self.h, order, stream)
+    def saga_epoch(self, order, stream=None): _epoch("saga", self.h, order, stream)
+    def sga_epoch(self, order, stream=None): _epoch("sga", self.h, order, stream)
+    def bsrem_epoch(self, order, stream=None): _epoch("bsrem", self.h, order, stream)
+    def sem_epoch(self, order, stream=None): _epoch("sem", self.h, order, stream)
+
+    def objective(self, stream=None) -> float:
+        return svr_objective(self.h, stream)
+
+    def image(self, stream=None):
+        import torch
+        out = torch.empty(self.S, self.A.N, dtype=torch.float32, device="cuda")
+        _check(lib().svr_get_image(self.h, _dev(out), _stream(stream)))
+        return out
+
+    def info(self) -> svr_recon_info_t:
+        inf = svr_recon_info_t()
+        _check(lib().svr_recon_info(self.h, C.byref(inf)))
+        return inf
+
+    def get_state(self, stream=None) -> bytes:
+        n = C.c_size_t(0)
+        _check(lib().svr_recon_get_state(self.h, None, C.byref(n), _stream(stream)))
+        buf = C.create_string_buffer(n.value)
+        _check(lib().svr_recon_get_state(self.h, buf, C.byref(n), _stream(stream)))
+        return buf.raw[:n.value]
+
+    def set_state(self, state: bytes, stream=None):
+        buf = C.create_string_buffer(state, len(state))
+        _check(lib().svr_recon_set_state(self.h, buf, len(state), _stream(stream)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().svr_recon_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,581 @@
+// Host side of the C ABI: argument validation, object lifetimes, and the
+// epoch drivers that enqueue the projector and update kernels.
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "util.h"
+
+using namespace svr;
+
+struct svr_recon {
+    Matrix *A = nullptr;
+    svr_params p{};
+    int S = 1;
+    int device = 0;
+    int M = 0, N = 0, Ns = 0;
+    float *g = nullptr, *w = nullptr;   // subset-ordered data
+    float *f[2] = {nullptr, nullptr};   // ping-pong iterate
+    int cur = 0;
+    float *ratio = nullptr;             // M, subset-ordered
+    double *s_hat = nullptr, *s_anc = nullptr, *Q = nullptr, *g_tilde = nullptr;
+    float *table = nullptr;             // Ns*N
+    float *dpre = nullptr;              // frozen preconditioner
+    int dpre_per_subset = 0;
+    double *part = nullptr;             // reduction partials
+    int n_part = 0;
+    double *scal = nullptr;             // 2 FP64 scalars
+    int *bad = nullptr;                 // device flag / counter
+    int64_t k = 0, n_snap = 0;
+    bool numeric_error = false;
+};
+
+namespace {
+using Recon = svr_recon;
+
+int kind_of_algo(int algo) {
+    switch (algo) {
+        case SVR_ALGO_OSEM: return UPD_OSEM;
+        case SVR_ALGO_SVREM: return UPD_SVREM;
+        case SVR_ALGO_SVRG: return UPD_SVRG;
+        case SVR_ALGO_SAGA: return UPD_SAGA;
+        case SVR_ALGO_SGA: return UPD_SGA;
+        case SVR_ALGO_BSREM: return UPD_SGA;
+        case SVR_ALGO_SEM: return UPD_SEM;
+    }
+    return -1;
+}
+
+void free_recon(Recon *R) {
+    if (!R) return;
+    void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ratio, R->s_hat, R->s_anc, R->Q,
+                    R->g_tilde, R->table, R->dpre, R->part, R->scal, R->bad};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete R;
+}
+
+PenaltyArgs pen_of(const Recon *R) {
+    return PenaltyArgs{R->p.penalty, R->p.delta, R->p.beta, R->A->geom.nx, R->A->geom.ny};
+}
+
+int check_geom(const svr_geometry *g) {
+    SVR_REQUIRE(g, "geometry is NULL");
+    SVR_REQUIRE(g->nx >= 1 && g->ny >= 1 && g->n_views >= 1 && g->n_bins >= 1, "sizes must be >= 1");
+    SVR_REQUIRE((int64_t)g->nx * g->ny < (1ll << 30) && (int64_t)g->n_views * g->n_bins < (1ll << 30),
+                "image or sinogram too large");
+    SVR_REQUIRE(g->pixel_mm > 0 && g->bin_mm > 0 && std::isfinite(g->pixel_mm) && std::isfinite(g->bin_mm),
+                "pixel_mm and bin_mm must be finite and > 0");
+    SVR_REQUIRE(g->arc_rad > 0 && std::isfinite(g->arc_rad), "arc_rad must be finite and > 0");
+    return SVR_OK;
+}
+
+int check_order(const Recon *R, const int32_t *order, int32_t n) {
+    SVR_REQUIRE(n >= 0, "n must be >= 0");
+    SVR_REQUIRE(n == 0 || order, "order is NULL");
+    for (int i = 0; i < n; ++i)
+        SVR_REQUIRE(order[i] >= 0 && order[i] < R->Ns, "order[%d] = %d outside [0, %d)", i, order[i], R->Ns);
+    return SVR_OK;
+}
+
+// ratio of all rows at the current image, then the algorithm's snapshot
+int snapshot(Recon *R, int kind, hipStream_t s) {
+    Matrix &A = *R->A;
+    FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
+    int rc = launch_forward(A, 0, A.M, 1, fa, s);
+    if (rc) return rc;
+    SnapArgs sa{};
+    sa.ratio_all = R->ratio;
+    sa.f = R->f[R->cur];
+    sa.table = R->table;
+    sa.s_anc = R->s_anc;
+    sa.s_hat = R->s_hat;
+    sa.init_shat = (R->k == 0) || (R->p.flags & SVR_FLAG_RESET_SHAT_AT_ANCHOR);
+    sa.g_tilde = R->g_tilde;
+    sa.Q = R->Q;
+    sa.pen = pen_of(R);
+    rc = launch_snapshot(A, kind, sa, s);
+    if (rc) return rc;
+    R->n_snap++;
+    return SVR_OK;
+}
+
+int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream) {
+    clear_error();
+    SVR_REQUIRE(R, "recon is NULL");
+    if (algo != SVR_ALGO_OSEM)
+        SVR_REQUIRE(R->p.algo == algo, "recon was created for algo %d, epoch call is for algo %d", R->p.algo, algo);
+    int rc = check_order(R, order, n);
+    if (rc) return rc;
+    SVR_HIP(hipSetDevice(R->device));
+    hipStream_t s = (hipStream_t)stream;
+    Matrix &A = *R->A;
+    const int kind = kind_of_algo(algo);
+    // OSEM is the initialiser: it leaves k at 0, so the next variance-reduced
+    // call starts with a fresh anchor (or table fill) and frozen preconditioner
+    if (algo == SVR_ALGO_OSEM) R->k = 0;
+    for (int i = 0; i < n; ++i) {
+        const int t = order[i];
+        if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG) {
+            if (R->k % ((int64_t)R->p.eta * R->Ns) == 0) {
+                rc = snapshot(R, kind, s);
+                if (rc) return rc;
+            }
+        } else if (algo == SVR_ALGO_SAGA && R->k == 0) {
+            rc = snapshot(R, kind, s);
+            if (rc) return rc;
+        }
+        if ((algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) && R->k == 0 &&
+            R->p.precond != SVR_PRECOND_ITERATE) {
+            rc = launch_precond(A, R->f[R->cur], R->dpre_per_subset, R->dpre, s);
+            if (rc) return rc;
+        }
+        if (algo == SVR_ALGO_SEM && R->k == 0)
+            SVR_HIP(hipMemsetAsync(R->s_hat, 0, sizeof(double) * (size_t)R->N, s));
+        FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
+        rc = launch_forward(A, A.row_start[t], A.row_start[t + 1], 1, fa, s);
+        if (rc) return rc;
+        UpdateArgs u{};
+        u.t = t;
+        u.Ns = R->Ns;
+        u.ratio = R->ratio + A.row_start[t];
+        u.f = R->f[R->cur];
+        u.f_out = R->f[1 - R->cur];
+        u.alpha = R->p.alpha;
+        if (algo == SVR_ALGO_BSREM || algo == SVR_ALGO_SEM)
+            u.alpha = R->p.alpha / (R->p.decay * (double)R->k + 1.0);
+        u.s_hat = R->s_hat;
+        u.s_anc = R->s_anc;
+        u.table = R->table;
+        u.Q = R->Q;
+        u.g_tilde = R->g_tilde;
+        u.dpre = (R->p.precond == SVR_PRECOND_ITERATE) ? nullptr : R->dpre;
+        u.dpre_per_subset = R->dpre_per_subset;
+        u.pen = pen_of(R);
+        if (algo == SVR_ALGO_OSEM) u.pen.beta = 0.0;
+        rc = launch_update(A, kind, u, s);
+        if (rc) return rc;
+        R->cur = 1 - R->cur;
+        if (algo != SVR_ALGO_OSEM) R->k++;
+    }
+    return SVR_OK;
+}
+
+}  // namespace
+
+// ===========================================================================
+// C ABI
+// ===========================================================================
+extern "C" {
+
+const char *svr_last_error(void) { return svr::last_error(); }
+int svr_version(void) { return 10000; }
+
+int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t wtype, const float *mu_dev,
+                            void *stream, svr_matrix **out) {
+    clear_error();
+    SVR_REQUIRE(out, "out is NULL");
+    *out = nullptr;
+    int rc = check_geom(geom);
+    if (rc) return rc;
+    SVR_REQUIRE(n_subsets >= 1 && n_subsets <= geom->n_views, "n_subsets must be in [1, n_views]");
+    SVR_REQUIRE(wtype == SVR_W_F32 || wtype == SVR_W_F16 || wtype == SVR_W_BF16, "unknown wtype %d", wtype);
+    svr_matrix *A = new (std::nothrow) svr_matrix();
+    SVR_REQUIRE(A, "host allocation failed");
+    A->geom = *geom;
+    A->Ns = n_subsets;
+    A->wtype = wtype;
+    (void)hipGetDevice(&A->device);
+    hipStream_t s = (hipStream_t)stream;
+    if (mu_dev) {
+        int *cnt = nullptr;
+        hipError_t e = dalloc(&cnt, 1);
+        if (e != hipSuccess) { delete A; set_error("allocation failed"); return SVR_ENOMEM; }
+        (void)hipMemsetAsync(cnt, 0, sizeof(int), s);
+        launch_count_bad(mu_dev, (int64_t)geom->nx * geom->ny, 0, cnt, s);
+        int h = 0;
+        (void)hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, s);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(cnt);
+        if (h) { delete A; set_error("mu has %d negative or non-finite entries", h); return SVR_EINVAL; }
+    }
+    rc = build_matrix(*A, mu_dev, s);
+    if (rc) {
+        svr_matrix_destroy(A);
+        return rc;
+    }
+    *out = A;
+    return SVR_OK;
+}
+
+int svr_matrix_info(const svr_matrix *A, svr_matrix_info_t *info, int64_t *nnz_per_subset) {
+    clear_error();
+    SVR_REQUIRE(A && info, "NULL argument");
+    info->nnz = A->nnz;
+    info->bytes = A->bytes;
+    info->n_subsets = A->Ns;
+    info->n_rows = A->M;
+    info->n_pixels = A->N;
+    info->max_row_nnz = A->max_row_nnz;
+    info->max_col_nnz = A->max_col_nnz;
+    info->wtype = A->wtype;
+    if (nnz_per_subset)
+        for (int t = 0; t < A->Ns; ++t) nnz_per_subset[t] = A->nnz_sub[t];
+    return SVR_OK;
+}
+
+static float host_w(const void *base, int wtype, int64_t i) {
+    if (wtype == SVR_W_F32) return ((const float *)base)[i];
+    if (wtype == SVR_W_F16) return (float)((const _Float16 *)base)[i];
+    uint32_t u = (uint32_t)((const uint16_t *)base)[i] << 16;
+    float f;
+    memcpy(&f, &u, 4);
+    return f;
+}
+
+int svr_matrix_export(const svr_matrix *A, int32_t which, int32_t *ptr, int32_t *idx, float *val) {
+    clear_error();
+    SVR_REQUIRE(A, "matrix is NULL");
+    SVR_REQUIRE(which == 0 || which == 1, "which must be 0 or 1");
+    SVR_HIP(hipSetDevice(A->device));
+    const int64_t nnz = A->nnz;
+    const int wb = A->wbytes();
+    if (which == 0) {
+        std::vector<int> rp(A->M + 1), rs(A->M), col(nnz);
+        std::vector<char> v(nnz * wb);
+        SVR_HIP(hipMemcpy(rp.data(), A->d_row_ptr, sizeof(int) * (A->M + 1), hipMemcpyDeviceToHost));
+        SVR_HIP(hipMemcpy(rs.data(), A->d_row_sino, sizeof(int) * A->M, hipMemcpyDeviceToHost));
+        SVR_HIP(hipMemcpy(col.data(), A->d_col, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+        SVR_HIP(hipMemcpy(v.data(), A->d_val, (size_t)wb * nnz, hipMemcpyDeviceToHost));
+        std::vector<int> inv(A->M);
+        for (int r = 0; r < A->M; ++r) inv[rs[r]] = r;
+        int64_t pos = 0;
+        if (ptr) ptr[0] = 0;
+        for (int m = 0; m < A->M; ++m) {
+            const int r = inv[m];
+            for (int i = rp[r]; i < rp[r + 1]; ++i, ++pos) {
+                if (idx) idx[pos] = col[i];
+                if (val) val[pos] = host_w(v.data(), A->wtype, i);
+            }
+            if (ptr) ptr[m + 1] = (int32_t)pos;
+        }
+    } else {
+        const int64_t NT = (int64_t)A->Ns * A->N;
+        if (ptr) SVR_HIP(hipMemcpy(ptr, A->d_ptrT, sizeof(int) * (NT + 1), hipMemcpyDeviceToHost));
+        if (idx) SVR_HIP(hipMemcpy(idx, A->d_rowT, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+        if (val) {
+            std::vector<char> v(nnz * wb);
+            SVR_HIP(hipMemcpy(v.data(), A->d_valT, (size_t)wb * nnz, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < nnz; ++i) val[i] = host_w(v.data(), A->wtype, i);
+        }
+    }
+    return SVR_OK;
+}
+
+__global__ static void k_f32_to_f64(const float *x, int n, double *y) {
+    int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) y[i] = (double)x[i];
+}
+
+int svr_sensitivity(const svr_matrix *A, int32_t subset, double *out_dev, void *stream) {
+    clear_error();
+    SVR_REQUIRE(A && out_dev, "NULL argument");
+    SVR_REQUIRE(subset >= -1 && subset < A->Ns, "subset %d out of range", subset);
+    SVR_HIP(hipSetDevice(A->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (subset < 0) {
+        SVR_HIP(hipMemcpyAsync(out_dev, A->d_sens, sizeof(double) * A->N, hipMemcpyDeviceToDevice, s));
+    } else {
+        k_f32_to_f64<<<(A->N + 255) / 256, 256, 0, s>>>(A->d_sens_t + (int64_t)subset * A->N, A->N, out_dev);
+        SVR_HIP(hipGetLastError());
+    }
+    return SVR_OK;
+}
+
+void svr_matrix_destroy(svr_matrix *A) {
+    if (!A) return;
+    (void)hipSetDevice(A->device);
+    void *ptrs[] = {A->d_row_start, A->d_row_sino, A->d_row_ptr, A->d_col, A->d_val, A->d_ptrT,
+                    A->d_rowT, A->d_valT, A->d_sens_t, A->d_sens};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    delete A;
+}
+
+int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t n_slices, float *y_dev,
+                void *stream) {
+    clear_error();
+    SVR_REQUIRE(A && x_dev && y_dev, "NULL argument");
+    SVR_REQUIRE(subset >= -1 && subset < A->Ns, "subset %d out of range", subset);
+    SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
+    SVR_HIP(hipSetDevice(A->device));
+    hipStream_t s = (hipStream_t)stream;
+    const int r0 = subset < 0 ? 0 : A->row_start[subset];
+    const int r1 = subset < 0 ? A->M : A->row_start[subset + 1];
+    for (int sl = 0; sl < n_slices; ++sl) {
+        FwdArgs fa{x_dev + (int64_t)sl * A->N, nullptr, nullptr, y_dev + (int64_t)sl * A->M, nullptr, nullptr};
+        int rc = launch_forward(*A, r0, r1, 0, fa, s);
+        if (rc) return rc;
+    }
+    return SVR_OK;
+}
+
+int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int32_t n_slices, float *x_dev,
+                    void *stream) {
+    clear_error();
+    SVR_REQUIRE(A && x_dev && y_dev, "NULL argument");
+    SVR_REQUIRE(subset >= -1 && subset < A->Ns, "subset %d out of range", subset);
+    SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
+    SVR_HIP(hipSetDevice(A->device));
+    hipStream_t s = (hipStream_t)stream;
+    float *ysub = nullptr;
+    SVR_HIP(hipMallocAsync((void **)&ysub, sizeof(float) * (size_t)A->M, s));
+    int rc = SVR_OK;
+    for (int sl = 0; sl < n_slices && rc == SVR_OK; ++sl) {
+        rc = launch_gather_rows(*A, y_dev + (int64_t)sl * A->M, ysub, s);
+        if (rc == SVR_OK) rc = launch_backproject(*A, subset, ysub, x_dev + (int64_t)sl * A->N, s);
+    }
+    SVR_HIP(hipFreeAsync(ysub, s));
+    return rc;
+}
+
+int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, const float *f0_dev, int32_t n_slices,
+                     const svr_params *p, void *stream, svr_recon **out) {
+    clear_error();
+    SVR_REQUIRE(out, "out is NULL");
+    *out = nullptr;
+    SVR_REQUIRE(A && g_dev && w_dev && f0_dev && p, "NULL argument");
+    SVR_REQUIRE(n_slices == 1, "this build reconstructs one slice per recon (n_slices = %d)", n_slices);
+    SVR_REQUIRE(kind_of_algo(p->algo) >= 0, "unknown algo %d", p->algo);
+    SVR_REQUIRE(p->alpha > 0 && std::isfinite(p->alpha), "alpha must be finite and > 0");
+    SVR_REQUIRE(p->beta >= 0 && std::isfinite(p->beta), "beta must be finite and >= 0");
+    SVR_REQUIRE(p->eta >= 1, "eta must be >= 1");
+    SVR_REQUIRE(p->penalty >= SVR_PEN_QUADRATIC && p->penalty <= SVR_PEN_HYPERBOLA, "unknown penalty %d",
+                p->penalty);
+    SVR_REQUIRE(p->penalty == SVR_PEN_QUADRATIC || (p->delta > 0 && std::isfinite(p->delta)),
+                "delta must be finite and > 0");
+    SVR_REQUIRE(p->precond >= 0 && p->precond <= 2, "unknown precond %d", p->precond);
+    SVR_REQUIRE(p->decay >= 0 && std::isfinite(p->decay), "decay must be finite and >= 0");
+    SVR_HIP(hipSetDevice(A->device));
+    hipStream_t s = (hipStream_t)stream;
+    svr_recon *R = new (std::nothrow) svr_recon();
+    SVR_REQUIRE(R, "host allocation failed");
+    R->A = A;
+    R->p = *p;
+    R->S = n_slices;
+    R->device = A->device;
+    R->M = A->M;
+    R->N = A->N;
+    R->Ns = A->Ns;
+    const int M = A->M, N = A->N, Ns = A->Ns;
+    const int64_t NT = (int64_t)Ns * N;
+    R->n_part = std::max((M + 3) / 4, (N + 255) / 256) + 1;
+    hipError_t e = hipSuccess;
+    auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
+    chk(dalloc(&R->g, M));
+    chk(dalloc(&R->w, M));
+    chk(dalloc(&R->f[0], N));
+    chk(dalloc(&R->f[1], N));
+    chk(dalloc(&R->ratio, M));
+    chk(dalloc(&R->part, R->n_part));
+    chk(dalloc(&R->scal, 2));
+    chk(dalloc(&R->bad, 1));
+    const int algo = p->algo;
+    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SEM) chk(dalloc(&R->s_hat, N));
+    if (algo == SVR_ALGO_SVREM) chk(dalloc(&R->s_anc, N));
+    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) chk(dalloc(&R->table, NT));
+    if (algo == SVR_ALGO_SVRG) chk(dalloc(&R->g_tilde, N));
+    if (algo == SVR_ALGO_SAGA) chk(dalloc(&R->Q, N));
+    if ((algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) && p->precond != SVR_PRECOND_ITERATE) {
+        R->dpre_per_subset = (p->precond == SVR_PRECOND_SUBSET_FROZEN);
+        chk(dalloc(&R->dpre, R->dpre_per_subset ? NT : (int64_t)N));
+    }
+    if (e != hipSuccess) {
+        free_recon(R);
+        set_error("device allocation failed: %s", hipGetErrorString(e));
+        return SVR_ENOMEM;
+    }
+    // validate the data on the device
+    SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
+    int rc = launch_count_bad(g_dev, M, 0, R->bad, s);
+    if (!rc) rc = launch_count_bad(w_dev, M, 0, R->bad, s);
+    int nbad_gw = 0, nbad_f = 0;
+    if (!rc) {
+        SVR_HIP(hipMemcpyAsync(&nbad_gw, R->bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
+        rc = launch_count_bad(f0_dev, N, 1, R->bad, s);
+    }
+    if (!rc) {
+        SVR_HIP(hipMemcpyAsync(&nbad_f, R->bad, sizeof(int), hipMemcpyDeviceToHost, s));
+        SVR_HIP(hipStreamSynchronize(s));
+    }
+    if (rc || nbad_gw || nbad_f) {
+        free_recon(R);
+        if (!rc) {
+            set_error("invalid data: %d negative/non-finite entries in g or w, %d non-positive/non-finite in f0",
+                      nbad_gw, nbad_f);
+            rc = SVR_EINVAL;
+        }
+        return rc;
+    }
+    rc = launch_gather_rows(*A, g_dev, R->g, s);
+    if (!rc) rc = launch_gather_rows(*A, w_dev, R->w, s);
+    if (rc) { free_recon(R); return rc; }
+    SVR_HIP(hipMemcpyAsync(R->f[0], f0_dev, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
+    SVR_HIP(hipMemsetAsync(R->ratio, 0, sizeof(float) * M, s));
+    if (R->s_hat) SVR_HIP(hipMemsetAsync(R->s_hat, 0, sizeof(double) * N, s));
+    SVR_HIP(hipStreamSynchronize(s));
+    *out = R;
+    return SVR_OK;
+}
+
+int svr_osem_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_OSEM, o, n, s); }
+int svr_svrem_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_SVREM, o, n, s); }
+int svr_svrg_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_SVRG, o, n, s); }
+int svr_saga_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_SAGA, o, n, s); }
+int svr_sga_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_SGA, o, n, s); }
+int svr_bsrem_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_BSREM, o, n, s); }
+int svr_sem_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_SEM, o, n, s); }
+
+int svr_objective(svr_recon *R, double *phi_host, void *stream) {
+    clear_error();
+    SVR_REQUIRE(R && phi_host, "NULL argument");
+    SVR_HIP(hipSetDevice(R->device));
+    hipStream_t s = (hipStream_t)stream;
+    const Matrix &A = *R->A;
+    SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
+    FwdArgs fa{R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad};
+    int nb = 0;
+    int rc = launch_forward(A, 0, A.M, 2, fa, s, &nb);
+    if (!rc) rc = launch_reduce_sum(R->part, nb, R->scal, s);
+    int nbp = 0;
+    if (!rc) rc = launch_penalty_value(A, R->f[R->cur], R->p.penalty, R->p.delta, R->part, &nbp, s);
+    if (!rc) rc = launch_reduce_sum(R->part, nbp, R->scal + 1, s);
+    if (rc) return rc;
+    double h[2];
+    int bad = 0;
+    SVR_HIP(hipMemcpyAsync(h, R->scal, sizeof(h), hipMemcpyDeviceToHost, s));
+    SVR_HIP(hipMemcpyAsync(&bad, R->bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    SVR_HIP(hipStreamSynchronize(s));
+    const double phi = bad ? -INFINITY : h[0] - R->p.beta * h[1];
+    *phi_host = phi;
+    if (!std::isfinite(phi)) {
+        R->numeric_error = true;
+        set_error("objective is not finite (%g)", phi);
+        return SVR_ENUMERIC;
+    }
+    return SVR_OK;
+}
+
+int svr_get_image(const svr_recon *R, float *f_dev, void *stream) {
+    clear_error();
+    SVR_REQUIRE(R && f_dev, "NULL argument");
+    SVR_HIP(hipSetDevice(R->device));
+    SVR_HIP(hipMemcpyAsync(f_dev, R->f[R->cur], sizeof(float) * R->N, hipMemcpyDeviceToDevice,
+                           (hipStream_t)stream));
+    return SVR_OK;
+}
+
+}  // extern "C"
+
+// ---- state (checkpoint / resume) ---------------------------------------------
+namespace {
+struct Field {
+    void *dev;
+    size_t bytes;
+};
+std::vector<Field> state_fields(const Recon *R) {
+    const size_t N = R->N, NT = (size_t)R->Ns * R->N;
+    std::vector<Field> v;
+    v.push_back({R->f[R->cur], 4 * N});
+    if (R->s_hat) v.push_back({R->s_hat, 8 * N});
+    if (R->s_anc) v.push_back({R->s_anc, 8 * N});
+    if (R->Q) v.push_back({R->Q, 8 * N});
+    if (R->g_tilde) v.push_back({R->g_tilde, 8 * N});
+    if (R->table) v.push_back({R->table, 4 * NT});
+    if (R->dpre) v.push_back({R->dpre, 4 * (R->dpre_per_subset ? NT : N)});
+    return v;
+}
+struct StateHeader {
+    uint64_t magic;
+    int64_t k, n_snap;
+    int32_t algo, Ns, N, M;
+};
+constexpr uint64_t STATE_MAGIC = 0x5356524553544154ull;
+}  // namespace
+
+extern "C" {
+
+int svr_recon_info(const svr_recon *R, svr_recon_info_t *info) {
+    clear_error();
+    SVR_REQUIRE(R && info, "NULL argument");
+    info->k = R->k;
+    info->n_snapshots = R->n_snap;
+    info->n_subsets = R->Ns;
+    info->n_slices = R->S;
+    info->n_pixels = R->N;
+    info->n_rows = R->M;
+    size_t tot = sizeof(StateHeader);
+    for (auto &f : state_fields(R)) tot += f.bytes;
+    info->state_bytes = (int64_t)tot;
+    return SVR_OK;
+}
+
+int svr_recon_get_state(const svr_recon *R, void *buf, size_t *len, void *stream) {
+    clear_error();
+    SVR_REQUIRE(R && len, "NULL argument");
+    auto fields = state_fields(R);
+    size_t tot = sizeof(StateHeader);
+    for (auto &f : fields) tot += f.bytes;
+    if (!buf) { *len = tot; return SVR_OK; }
+    SVR_REQUIRE(*len >= tot, "buffer too small (%zu < %zu)", *len, tot);
+    SVR_HIP(hipSetDevice(R->device));
+    hipStream_t s = (hipStream_t)stream;
+    StateHeader h{STATE_MAGIC, R->k, R->n_snap, R->p.algo, R->Ns, R->N, R->M};
+    memcpy(buf, &h, sizeof(h));
+    char *p = (char *)buf + sizeof(h);
+    for (auto &f : fields) {
+        SVR_HIP(hipMemcpyAsync(p, f.dev, f.bytes, hipMemcpyDeviceToHost, s));
+        p += f.bytes;
+    }
+    SVR_HIP(hipStreamSynchronize(s));
+    *len = tot;
+    return SVR_OK;
+}
+
+int svr_recon_set_state(svr_recon *R, const void *buf, size_t len, void *stream) {
+    clear_error();
+    SVR_REQUIRE(R && buf, "NULL argument");
+    SVR_REQUIRE(len >= sizeof(StateHeader), "buffer too small");
+    StateHeader h;
+    memcpy(&h, buf, sizeof(h));
+    SVR_REQUIRE(h.magic == STATE_MAGIC, "not a recon state");
+    SVR_REQUIRE(h.algo == R->p.algo && h.Ns == R->Ns && h.N == R->N && h.M == R->M,
+                "state was saved from a different problem or algorithm");
+    SVR_HIP(hipSetDevice(R->device));
+    hipStream_t s = (hipStream_t)stream;
+    auto fields = state_fields(R);
+    size_t tot = sizeof(StateHeader);
+    for (auto &f : fields) tot += f.bytes;
+    SVR_REQUIRE(len == tot, "state size %zu does not match %zu", len, tot);
+    const char *p = (const char *)buf + sizeof(h);
+    for (auto &f : fields) {
+        SVR_HIP(hipMemcpyAsync(f.dev, p, f.bytes, hipMemcpyHostToDevice, s));
+        p += f.bytes;
+    }
+    SVR_HIP(hipStreamSynchronize(s));
+    R->k = h.k;
+    R->n_snap = h.n_snap;
+    return SVR_OK;
+}
+
+void svr_recon_destroy(svr_recon *R) {
+    if (!R) return;
+    (void)hipSetDevice(R->device);
+    free_recon(R);
+}
+
+}  // extern "C"

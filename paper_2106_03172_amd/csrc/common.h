@@ -1,0 +1,178 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/svr.h"
+
+namespace svr {
+
+// ---------------------------------------------------------------------------
+// errors
+// ---------------------------------------------------------------------------
+void set_error(const char *fmt, ...);
+void clear_error();
+
+#define SVR_HIP(call)                                                             \
+    do {                                                                          \
+        hipError_t e_ = (call);                                                   \
+        if (e_ != hipSuccess) {                                                   \
+            ::svr::set_error("%s:%d %s: %s", __FILE__, __LINE__, #call,          \
+                             hipGetErrorString(e_));                             \
+            return e_ == hipErrorOutOfMemory ? SVR_ENOMEM : SVR_EDEVICE;          \
+        }                                                                         \
+    } while (0)
+
+#define SVR_REQUIRE(cond, ...)                                                    \
+    do {                                                                          \
+        if (!(cond)) {                                                            \
+            ::svr::set_error(__VA_ARGS__);                                        \
+            return SVR_EINVAL;                                                    \
+        }                                                                         \
+    } while (0)
+
+// Device allocation helper that honours an optional fault-injection budget
+// (environment SVR_FAULT_ALLOC_AFTER=n makes the (n+1)-th allocation fail).
+hipError_t dmalloc(void **p, size_t bytes);
+template <typename T>
+inline hipError_t dalloc(T **p, size_t count) {
+    return dmalloc(reinterpret_cast<void **>(p), count * sizeof(T));
+}
+
+// ---------------------------------------------------------------------------
+// weights
+// ---------------------------------------------------------------------------
+// bf16 is stored as raw uint16_t; fp16 as _Float16.
+struct bf16_t { uint16_t bits; };
+
+__host__ __device__ inline float load_w(float v) { return v; }
+__host__ __device__ inline float load_w(_Float16 v) { return static_cast<float>(v); }
+__host__ __device__ inline float load_w(bf16_t v) {
+    return __uint_as_float(static_cast<uint32_t>(v.bits) << 16);
+}
+
+// ---------------------------------------------------------------------------
+// matrix object
+// ---------------------------------------------------------------------------
+struct Matrix {
+    svr_geometry geom;
+    int Ns = 0, wtype = 0;
+    int M = 0, N = 0;
+    int64_t nnz = 0;
+    int max_row_nnz = 0, max_col_nnz = 0;
+    int device = 0;
+    std::vector<int> row_start;     // host, Ns+1: first subset-ordered row of each subset
+    std::vector<int64_t> nnz_sub;   // host, Ns
+    int *d_row_start = nullptr;     // device copy of row_start
+    int *d_row_sino = nullptr;      // M: natural sinogram index of each subset-ordered row
+    int *d_row_ptr = nullptr;       // M+1
+    int *d_col = nullptr;           // nnz
+    void *d_val = nullptr;          // nnz (float / _Float16 / bf16_t)
+    int *d_ptrT = nullptr;          // Ns*N+1
+    int *d_rowT = nullptr;          // nnz (subset-local row)
+    void *d_valT = nullptr;         // nnz
+    float *d_sens_t = nullptr;      // Ns*N
+    double *d_sens = nullptr;       // N
+    int64_t bytes = 0;
+    int wbytes() const { return wtype == SVR_W_F32 ? 4 : 2; }
+    int rows_of(int t) const { return row_start[t + 1] - row_start[t]; }
+};
+
+// ---------------------------------------------------------------------------
+// kernel launchers (defined next to their kernels)
+// ---------------------------------------------------------------------------
+
+// geometry / build
+int build_matrix(Matrix &A, const float *mu_dev, hipStream_t s);
+
+// forward projection of rows [r0, r1) of the subset-ordered matrix.
+//  mode 0: y[row_sino[r]] = (A f)_r                           (plain projection)
+//  mode 1: ratio[r] = g[r] / ((A f)_r + w[r])   (0 if g == 0 or ybar <= 0)
+//  mode 2: partial log-likelihood sums into part[blockIdx], ratio not written
+struct FwdArgs {
+    const float *f;       // image, N floats
+    const float *g, *w;   // subset-ordered data (modes 1, 2)
+    float *out;           // mode 0: natural-order sinogram; mode 1: ratio (subset order)
+    double *part;         // mode 2: one partial per block
+    int *bad;             // mode 2: set when g > 0 and ybar <= 0
+};
+int launch_forward(const Matrix &A, int r0, int r1, int mode, const FwdArgs &a, hipStream_t s,
+                   int *n_blocks_out = nullptr);
+
+// back-projection of subset t (or all subsets with t = -1) of a ratio/data
+// vector in subset-ordered rows: x[n] = sum over the transposed row.
+int launch_backproject(const Matrix &A, int t, const float *y_sub, float *x, hipStream_t s);
+
+// deterministic FP64 reduction of n partials into out[0]
+int launch_reduce_sum(const double *part, int n, double *out, hipStream_t s);
+
+// penalty value partials (FP64): R(f) for one slice image
+int launch_penalty_value(const Matrix &A, const float *f, int potential, double delta,
+                         double *part, int *n_blocks_out, hipStream_t s);
+
+// permute natural-order sinogram into subset order (and back)
+int launch_gather_rows(const Matrix &A, const float *src_nat, float *dst_sub, hipStream_t s);
+
+// validation counters: counts entries that are negative / non-finite / non-positive
+int launch_count_bad(const float *x, int64_t n, int require_positive, int *counter, hipStream_t s);
+
+// ---------------------------------------------------------------------------
+// per-pixel fused updates (update.hip)
+// ---------------------------------------------------------------------------
+struct PenaltyArgs {
+    int potential;
+    double delta;
+    double beta;
+    int nx, ny;
+};
+
+struct UpdateArgs {
+    int t;                   // subset
+    int Ns;
+    const float *ratio;      // ratio of subset t (subset-local rows)
+    const float *f;          // current image f^k
+    float *f_out;            // f^{k+1}
+    double alpha;
+    // algorithm state
+    double *s_hat;           // SVREM/SEM running statistic (N)
+    const double *s_anc;     // SVREM anchor statistic (N)
+    float *table;            // Ns*N table (SVREM tau_anc, SVRG q_anc, SAGA q)
+    double *Q;               // SAGA running table sum (N)
+    const double *g_tilde;   // SVRG anchor full gradient / Ns (N)
+    const float *dpre;       // frozen preconditioner (N or Ns*N), null for iterate mode
+    int dpre_per_subset;     // 1 if dpre is Ns*N
+    PenaltyArgs pen;
+};
+
+enum UpdateKind { UPD_OSEM = 0, UPD_SVREM = 1, UPD_SVRG = 2, UPD_SAGA = 3, UPD_SGA = 4, UPD_SEM = 5 };
+int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s);
+
+// snapshot: full pass over all subsets at the current image, with the full
+// ratio vector (subset-ordered, all rows) already computed.
+//  SVREM: table[t] = tau_t, s_anc = mean_t tau_t, s_hat = s_anc if init_shat
+//  SVRG : table[t] = q_t = b_t - beta/Ns grad R, g_tilde = (sum_t q_t - sens)/Ns
+//  SAGA : table[t] = q_t, Q = sum_t q_t
+//  SEM  : s_hat = s(f) (not used: SEM's first step has weight 1)
+struct SnapArgs {
+    const float *ratio_all;
+    const float *f;
+    float *table;
+    double *s_anc;
+    double *s_hat;
+    int init_shat;
+    double *g_tilde;
+    double *Q;
+    PenaltyArgs pen;
+};
+int launch_snapshot(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
+
+// frozen preconditioner d = f0 / sens_t (per subset) or f0 / sens
+int launch_precond(const Matrix &A, const float *f0, int per_subset, float *d, hipStream_t s);
+
+}  // namespace svr
+
+struct svr_matrix : public svr::Matrix {};

@@ -1,0 +1,297 @@
+// System-matrix builder: exact ray/pixel intersection lengths (Siddon's
+// method) for the linear model E[g] = A f + w (Sec. 2.1, eq. voxel_td), laid
+// out by ordered subsets (Sec. 2.1) for gather-only projectors.
+//
+// One thread traces one ray in FP64, pixel units, merging the crossings with
+// the vertical and horizontal grid lines in increasing ray parameter and
+// assigning each piece to the pixel that contains its midpoint.  This file is
+// compiled without floating-point contraction so that every crossing,
+// midpoint and length is the correctly rounded result of the operations as
+// written (the pixel a piece falls in is an integer decision taken in FP64).
+#include <algorithm>
+#include <cmath>
+
+#include "common.h"
+#include "util.h"
+
+#pragma clang fp contract(off)
+
+namespace svr {
+
+constexpr double SEG_EPS = 1e-9;     // pieces shorter than this (pixel units) are dropped
+constexpr double SNAP_EPS = 1e-12;   // |cos|,|sin| below this are snapped to 0
+
+struct Ray {
+    double ox, oy, dx, dy;
+};
+
+// Ray (v, b) in grid coordinates: origin u*(cos, sin) + (nx/2, ny/2), unit
+// direction (-sin, cos), u = (b - (B-1)/2) * bin/pixel.
+__device__ inline Ray make_ray(const svr_geometry &g, int v, int b) {
+    double th = ((double)v * g.arc_rad) / (double)g.n_views;
+    double c = cos(th), s = sin(th);
+    if (fabs(c) < SNAP_EPS) { c = 0.0; s = copysign(1.0, s); }
+    if (fabs(s) < SNAP_EPS) { s = 0.0; c = copysign(1.0, c); }
+    double u = ((double)b - (double)(g.n_bins - 1) / 2.0) * (g.bin_mm / g.pixel_mm);
+    Ray r;
+    r.ox = u * c + (double)g.nx / 2.0;
+    r.oy = u * s + (double)g.ny / 2.0;
+    r.dx = -s;
+    r.dy = c;
+    return r;
+}
+
+// Visits the pieces of a ray in increasing parameter: emit(pixel, length_in_pixels).
+template <class Emit>
+__device__ inline void trace(const svr_geometry &g, const Ray &r, Emit &&emit) {
+    const int nx = g.nx, ny = g.ny;
+    int xi = 0, xs = 0, xleft = 0, yi = 0, ys = 0, yleft = 0;
+    if (r.dx < 0.0) { xi = nx; xs = -1; xleft = nx + 1; }
+    else if (r.dx > 0.0) { xi = 0; xs = 1; xleft = nx + 1; }
+    if (r.dy < 0.0) { yi = ny; ys = -1; yleft = ny + 1; }
+    else if (r.dy > 0.0) { yi = 0; ys = 1; yleft = ny + 1; }
+    double tprev = 0.0;
+    bool have = false;
+    while (xleft > 0 || yleft > 0) {
+        double tx = xleft > 0 ? ((double)xi - r.ox) / r.dx : INFINITY;
+        double ty = yleft > 0 ? ((double)yi - r.oy) / r.dy : INFINITY;
+        double t;
+        if (tx <= ty) { t = tx; xi += xs; --xleft; }
+        else { t = ty; yi += ys; --yleft; }
+        if (have) {
+            double seg = t - tprev;
+            if (seg >= SEG_EPS) {
+                double tm = (tprev + t) * 0.5;
+                double X = r.ox + tm * r.dx;
+                double Y = r.oy + tm * r.dy;
+                double fx = floor(X), fy = floor(Y);
+                if (fx >= 0.0 && fx < (double)nx && fy >= 0.0 && fy < (double)ny)
+                    emit((int)fy * nx + (int)fx, seg);
+            }
+        }
+        tprev = t;
+        have = true;
+    }
+}
+
+template <typename WT> __device__ inline WT store_w(double v);
+template <> __device__ inline float store_w<float>(double v) { return (float)v; }
+template <> __device__ inline _Float16 store_w<_Float16>(double v) { return (_Float16)(float)v; }
+template <> __device__ inline bf16_t store_w<bf16_t>(double v) {
+    // FP64 -> FP32 (nearest even) -> BF16 (nearest even); weights are finite.
+    uint32_t u = __float_as_uint((float)v);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    bf16_t r;
+    r.bits = (uint16_t)(u >> 16);
+    return r;
+}
+
+// subset-ordered row r -> natural sinogram index
+__global__ void k_row_sino(int M, int B, int Ns, const int *row_start, int *row_sino) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    int lo = 0, hi = Ns;  // find t with row_start[t] <= r < row_start[t+1]
+    while (hi - lo > 1) {
+        int mid = (lo + hi) >> 1;
+        if (row_start[mid] <= r) lo = mid; else hi = mid;
+    }
+    int t = lo;
+    int local = r - row_start[t];
+    int j = local / B, b = local - j * B;
+    int v = t + j * Ns;
+    row_sino[r] = v * B + b;
+}
+
+__global__ void k_siddon_count(svr_geometry g, int M, const int *row_sino, int *counts) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    int m = row_sino[r];
+    int v = m / g.n_bins, b = m - v * g.n_bins;
+    Ray ray = make_ray(g, v, b);
+    int c = 0;
+    trace(g, ray, [&](int, double) { ++c; });
+    counts[r] = c;
+}
+
+template <typename WT>
+__global__ void k_siddon_fill(svr_geometry g, int M, const int *row_sino, const int *row_ptr,
+                              const float *mu, int *col, WT *val) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    int m = row_sino[r];
+    int v = m / g.n_bins, b = m - v * g.n_bins;
+    Ray ray = make_ray(g, v, b);
+    const double pmm = g.pixel_mm;
+    double att = 1.0;
+    if (mu) {
+        double lineint = 0.0;
+        trace(g, ray, [&](int pix, double seg) { lineint = lineint + (seg * pmm) * (double)mu[pix]; });
+        att = exp(-lineint);
+    }
+    int pos = row_ptr[r];
+    trace(g, ray, [&](int pix, double seg) {
+        double len = seg * pmm;
+        if (mu) len = len * att;
+        col[pos] = pix;
+        val[pos] = store_w<WT>(len);
+        ++pos;
+    });
+}
+
+// ---- transposition (per subset), deterministic ------------------------------
+__global__ void k_col_count(int M, int B, int Ns, int N, const int *row_sino, const int *row_ptr,
+                            const int *col, int *cnt) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    int t = (row_sino[r] / B) % Ns;
+    int *c = cnt + (int64_t)t * N;
+    for (int i = row_ptr[r]; i < row_ptr[r + 1]; ++i) atomicAdd(&c[col[i]], 1);
+}
+
+template <typename WT>
+__global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const int *row_start,
+                         const int *row_ptr, const int *col, const WT *val, const int *ptrT,
+                         int *cursor, int *rowT, WT *valT) {
+    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= M) return;
+    int t = (row_sino[r] / B) % Ns;
+    int local = r - row_start[t];
+    int64_t base = (int64_t)t * N;
+    for (int i = row_ptr[r]; i < row_ptr[r + 1]; ++i) {
+        int n = col[i];
+        int p = ptrT[base + n] + atomicAdd(&cursor[base + n], 1);
+        rowT[p] = local;
+        valT[p] = val[i];
+    }
+}
+
+// each transposed row sorted by subset-local row (view, then bin); keys are unique
+template <typename WT>
+__global__ void k_sort_T(int64_t nrows, const int *ptrT, int *rowT, WT *valT) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= nrows) return;
+    int beg = ptrT[q], end = ptrT[q + 1];
+    for (int i = beg + 1; i < end; ++i) {
+        int k = rowT[i];
+        WT vv = valT[i];
+        int j = i - 1;
+        while (j >= beg && rowT[j] > k) {
+            rowT[j + 1] = rowT[j];
+            valT[j + 1] = valT[j];
+            --j;
+        }
+        rowT[j + 1] = k;
+        valT[j + 1] = vv;
+    }
+}
+
+// sens_t = A_t^T 1 (FP64 sum in transposed-row order, stored FP32), sens = sum_t (FP64)
+template <typename WT>
+__global__ void k_sens(int Ns, int N, const int *ptrT, const WT *valT, float *sens_t, double *sens) {
+    int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= N) return;
+    double tot = 0.0;
+    for (int t = 0; t < Ns; ++t) {
+        int64_t q = (int64_t)t * N + n;
+        double s = 0.0;
+        for (int i = ptrT[q]; i < ptrT[q + 1]; ++i) s = s + (double)load_w(valT[i]);
+        sens_t[q] = (float)s;
+        tot = tot + s;
+    }
+    sens[n] = tot;
+}
+
+template <typename WT>
+static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
+    const int M = A.M, N = A.N, Ns = A.Ns, B = A.geom.n_bins;
+    const int T = 256;
+    const int gM = (M + T - 1) / T;
+    int *counts = nullptr;
+    SVR_HIP(dalloc(&counts, M));
+    k_siddon_count<<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, counts);
+    SVR_HIP(hipGetLastError());
+    SVR_HIP(dalloc(&A.d_row_ptr, M + 1));
+    int64_t nnz = 0;
+    int rc = exclusive_scan(counts, M, A.d_row_ptr, &nnz, s);
+    if (rc) { (void)hipFree(counts); return rc; }
+    A.nnz = nnz;
+    SVR_HIP(dalloc(&A.d_col, nnz));
+    WT *val = nullptr, *valT = nullptr;
+    SVR_HIP(dalloc(&val, nnz));
+    A.d_val = val;
+    k_siddon_fill<WT><<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, A.d_row_ptr, mu, A.d_col, val);
+    SVR_HIP(hipGetLastError());
+
+    // host copies of the row counts: per-subset nnz and the longest row
+    std::vector<int> hptr(M + 1);
+    SVR_HIP(hipMemcpyAsync(hptr.data(), A.d_row_ptr, sizeof(int) * (M + 1), hipMemcpyDeviceToHost, s));
+    SVR_HIP(hipStreamSynchronize(s));
+    A.nnz_sub.assign(Ns, 0);
+    A.max_row_nnz = 0;
+    for (int t = 0; t < Ns; ++t)
+        A.nnz_sub[t] = (int64_t)hptr[A.row_start[t + 1]] - hptr[A.row_start[t]];
+    for (int r = 0; r < M; ++r) A.max_row_nnz = std::max(A.max_row_nnz, hptr[r + 1] - hptr[r]);
+
+    // transposed rows per subset
+    const int64_t NT = (int64_t)Ns * N;
+    int *cnt = nullptr;
+    SVR_HIP(dalloc(&cnt, NT));
+    SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
+    k_col_count<<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, A.d_col, cnt);
+    SVR_HIP(hipGetLastError());
+    SVR_HIP(dalloc(&A.d_ptrT, NT + 1));
+    int64_t nnzT = 0;
+    rc = exclusive_scan(cnt, NT, A.d_ptrT, &nnzT, s);
+    if (rc) { (void)hipFree(counts); (void)hipFree(cnt); return rc; }
+    if (nnzT != nnz) { set_error("transpose count mismatch"); return SVR_EDEVICE; }
+    std::vector<int> hcnt(NT);
+    SVR_HIP(hipMemcpyAsync(hcnt.data(), cnt, sizeof(int) * NT, hipMemcpyDeviceToHost, s));
+    SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
+    SVR_HIP(dalloc(&A.d_rowT, nnz));
+    SVR_HIP(dalloc(&valT, nnz));
+    A.d_valT = valT;
+    k_fill_T<WT><<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, A.d_col,
+                                  val, A.d_ptrT, cnt, A.d_rowT, valT);
+    SVR_HIP(hipGetLastError());
+    k_sort_T<WT><<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, A.d_rowT, valT);
+    SVR_HIP(hipGetLastError());
+    SVR_HIP(dalloc(&A.d_sens_t, NT));
+    SVR_HIP(dalloc(&A.d_sens, N));
+    k_sens<WT><<<(N + T - 1) / T, T, 0, s>>>(Ns, N, A.d_ptrT, valT, A.d_sens_t, A.d_sens);
+    SVR_HIP(hipGetLastError());
+    SVR_HIP(hipStreamSynchronize(s));
+    A.max_col_nnz = 0;
+    for (int64_t q = 0; q < NT; ++q) A.max_col_nnz = std::max(A.max_col_nnz, hcnt[q]);
+    SVR_HIP(hipFree(counts));
+    SVR_HIP(hipFree(cnt));
+    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + 2 * nnz + NT + 1 + (Ns + 1)) +
+              (int64_t)A.wbytes() * 2 * nnz + (int64_t)sizeof(float) * NT + (int64_t)sizeof(double) * N;
+    return SVR_OK;
+}
+
+int build_matrix(Matrix &A, const float *mu_dev, hipStream_t s) {
+    const svr_geometry &g = A.geom;
+    const int Ns = A.Ns, B = g.n_bins;
+    A.M = g.n_views * B;
+    A.N = g.nx * g.ny;
+    A.row_start.assign(Ns + 1, 0);
+    for (int t = 0; t < Ns; ++t) {
+        int nv = (g.n_views - t + Ns - 1) / Ns;  // views t, t+Ns, ... below n_views
+        A.row_start[t + 1] = A.row_start[t] + nv * B;
+    }
+    SVR_HIP(dalloc(&A.d_row_start, Ns + 1));
+    SVR_HIP(hipMemcpyAsync(A.d_row_start, A.row_start.data(), sizeof(int) * (Ns + 1),
+                           hipMemcpyHostToDevice, s));
+    SVR_HIP(dalloc(&A.d_row_sino, A.M));
+    k_row_sino<<<(A.M + 255) / 256, 256, 0, s>>>(A.M, B, Ns, A.d_row_start, A.d_row_sino);
+    SVR_HIP(hipGetLastError());
+    switch (A.wtype) {
+        case SVR_W_F32: return build_typed<float>(A, mu_dev, s);
+        case SVR_W_F16: return build_typed<_Float16>(A, mu_dev, s);
+        case SVR_W_BF16: return build_typed<bf16_t>(A, mu_dev, s);
+    }
+    set_error("unknown weight type %d", A.wtype);
+    return SVR_EINVAL;
+}
+
+}  // namespace svr

@@ -1,0 +1,337 @@
+// Continuous-batching server for independent SVREM reconstructions.
+//
+// Requests queue at submit; each scheduler tick admits queued requests (FIFO)
+// while a slot is free and their device footprint fits the memory budget,
+// then enqueues one epoch of subset updates for every resident request, each
+// request on one of the server's streams, so that the work of all resident
+// requests overlaps on the device.  A request's kernels touch only its own
+// buffers and every reduction has a fixed order, so its result is the same
+// whichever requests share the device with it.  Finished requests release
+// their memory, which lets the next queued ones in.
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <new>
+#include <vector>
+
+#include "common.h"
+#include "util.h"
+
+namespace {
+
+using clk = std::chrono::steady_clock;
+
+double ms_since(clk::time_point a, clk::time_point b) {
+    return std::chrono::duration<double, std::milli>(b - a).count();
+}
+
+// SplitMix64 (Steele, Lea, Flood 2014): the request's subset sequence
+struct SplitMix64 {
+    uint64_t s;
+    uint64_t next() {
+        uint64_t z = (s += 0x9E3779B97F4A7C15ull);
+        z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+        z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+        return z ^ (z >> 31);
+    }
+    int32_t below(int32_t n) { return (int32_t)(((next() >> 32) * (uint64_t)n) >> 32); }
+};
+
+enum State { QUEUED, RESIDENT, DONE };
+
+struct Request {
+    uint64_t ticket = 0;
+    svr_serve_request req{};
+    std::vector<float> g, w;
+    State state = QUEUED;
+    int status = SVR_OK;
+    int64_t est_bytes = 0, held_bytes = 0;
+    svr_matrix *A = nullptr;
+    svr_recon *R = nullptr;
+    float *d_g = nullptr, *d_w = nullptr, *d_f0 = nullptr;
+    int stream = 0;
+    int epochs_done = 0;
+    SplitMix64 rng{0};
+    std::vector<float> f;
+    double phi = 0.0;
+    clk::time_point t_submit, t_admit, t_done;
+};
+
+int64_t footprint_estimate(const svr_serve_request &r) {
+    const int64_t N = (int64_t)r.geom.nx * r.geom.ny;
+    const int64_t M = (int64_t)r.geom.n_views * r.geom.n_bins;
+    const int64_t Ns = r.n_subsets;
+    // parallel beam: each view crosses about (1 + |cos| + |sin|) * pixel/bin pieces
+    // per pixel (2.27 on average over angles); 2.6 leaves head room
+    const double ratio = std::max(1.0, r.geom.pixel_mm / r.geom.bin_mm);
+    const int64_t nnz = (int64_t)(2.6 * ratio * (double)r.geom.n_views * (double)N);
+    const int wb = r.wtype == SVR_W_F32 ? 4 : 2;
+    int64_t mat = 2 * nnz * (4 + wb) + 4 * (2 * M + Ns * N) + 4 * Ns * N + 8 * N;
+    int64_t rec = 4 * (3 * M + 2 * N) + 8 * (2 * N) + 4 * Ns * N + 8 * (M / 4 + N / 256 + 8);
+    int64_t io = 4 * (2 * M + N);
+    return mat + rec + io;
+}
+
+}  // namespace
+
+struct svr_server {
+    svr_serve_config cfg{};
+    std::vector<hipStream_t> streams;
+    std::map<uint64_t, std::unique_ptr<Request>> reqs;
+    std::deque<uint64_t> queue;
+    std::vector<uint64_t> resident;
+    uint64_t next_ticket = 1;
+    int64_t used_bytes = 0;
+    int device = 0;
+};
+
+using namespace svr;
+
+namespace {
+
+void release(svr_server *S, Request *q) {
+    if (q->R) svr_recon_destroy(q->R);
+    if (q->A) svr_matrix_destroy(q->A);
+    if (q->d_g) (void)hipFree(q->d_g);
+    if (q->d_w) (void)hipFree(q->d_w);
+    if (q->d_f0) (void)hipFree(q->d_f0);
+    q->R = nullptr;
+    q->A = nullptr;
+    q->d_g = q->d_w = q->d_f0 = nullptr;
+    S->used_bytes -= q->held_bytes;
+    q->held_bytes = 0;
+}
+
+__global__ void k_fill(float *x, int64_t n, float v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+// builds the request's matrix and recon and runs the OSEM initialisation epoch
+int admit(svr_server *S, Request *q, hipStream_t s) {
+    const svr_serve_request &r = q->req;
+    const int64_t M = (int64_t)r.geom.n_views * r.geom.n_bins;
+    const int64_t N = (int64_t)r.geom.nx * r.geom.ny;
+    q->held_bytes = q->est_bytes;
+    S->used_bytes += q->held_bytes;
+    int rc = svr_build_system_matrix(&r.geom, r.n_subsets, r.wtype, nullptr, s, &q->A);
+    if (rc) return rc;
+    SVR_HIP(dalloc(&q->d_g, M));
+    SVR_HIP(dalloc(&q->d_w, M));
+    SVR_HIP(dalloc(&q->d_f0, N));
+    SVR_HIP(hipMemcpyAsync(q->d_g, q->g.data(), sizeof(float) * M, hipMemcpyHostToDevice, s));
+    SVR_HIP(hipMemcpyAsync(q->d_w, q->w.data(), sizeof(float) * M, hipMemcpyHostToDevice, s));
+    k_fill<<<(unsigned)((N + 255) / 256), 256, 0, s>>>(q->d_f0, N, r.f0_value);
+    SVR_HIP(hipGetLastError());
+    rc = svr_recon_create(q->A, q->d_g, q->d_w, q->d_f0, 1, &r.params, s, &q->R);
+    if (rc) return rc;
+    std::vector<int32_t> cyc(r.n_subsets);
+    for (int t = 0; t < r.n_subsets; ++t) cyc[t] = t;
+    rc = svr_osem_epoch(q->R, cyc.data(), r.n_subsets, s);
+    if (rc) return rc;
+    // replace the estimate by what the matrix actually holds
+    svr_matrix_info_t inf;
+    svr_matrix_info(q->A, &inf, nullptr);
+    const int64_t actual = q->est_bytes - (int64_t)(2.6 * std::max(1.0, r.geom.pixel_mm / r.geom.bin_mm) *
+                                                    (double)r.geom.n_views * (double)N) *
+                                              2 * (4 + (r.wtype == SVR_W_F32 ? 4 : 2)) +
+                           inf.bytes;
+    S->used_bytes += actual - q->held_bytes;
+    q->held_bytes = actual;
+    q->rng.s = r.order_seed;
+    q->t_admit = clk::now();
+    q->state = RESIDENT;
+    return SVR_OK;
+}
+
+int finish(svr_server *S, Request *q, hipStream_t s) {
+    const int64_t N = (int64_t)q->req.geom.nx * q->req.geom.ny;
+    double phi = 0.0;
+    int rc = svr_objective(q->R, &phi, s);
+    q->phi = phi;
+    q->status = rc;
+    q->f.resize(N);
+    float *tmp = nullptr;
+    if (dalloc(&tmp, N) == hipSuccess) {
+        svr_get_image(q->R, tmp, s);
+        (void)hipMemcpyAsync(q->f.data(), tmp, sizeof(float) * N, hipMemcpyDeviceToHost, s);
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(tmp);
+    } else {
+        q->status = SVR_ENOMEM;
+    }
+    q->state = DONE;
+    q->t_done = clk::now();
+    release(S, q);
+    return SVR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int svr_serve_create(const svr_serve_config *cfg, svr_server **out) {
+    clear_error();
+    SVR_REQUIRE(cfg && out, "NULL argument");
+    SVR_REQUIRE(cfg->mem_budget_bytes > 0 && cfg->max_slots >= 1 && cfg->n_streams >= 1,
+                "mem_budget_bytes > 0, max_slots >= 1 and n_streams >= 1 are required");
+    *out = nullptr;
+    svr_server *S = new (std::nothrow) svr_server();
+    SVR_REQUIRE(S, "host allocation failed");
+    S->cfg = *cfg;
+    (void)hipGetDevice(&S->device);
+    for (int i = 0; i < cfg->n_streams; ++i) {
+        hipStream_t st;
+        hipError_t e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking);
+        if (e != hipSuccess) {
+            svr_serve_destroy(S);
+            set_error("stream creation failed: %s", hipGetErrorString(e));
+            return SVR_EDEVICE;
+        }
+        S->streams.push_back(st);
+    }
+    *out = S;
+    return SVR_OK;
+}
+
+int svr_serve_submit(svr_server *S, const svr_serve_request *r, uint64_t *ticket) {
+    clear_error();
+    SVR_REQUIRE(S && r && ticket, "NULL argument");
+    const svr_geometry &g = r->geom;
+    SVR_REQUIRE(g.nx >= 1 && g.ny >= 1 && g.n_views >= 1 && g.n_bins >= 1 && g.pixel_mm > 0 && g.bin_mm > 0 &&
+                    g.arc_rad > 0,
+                "invalid geometry");
+    SVR_REQUIRE(r->n_subsets >= 1 && r->n_subsets <= g.n_views, "n_subsets must be in [1, n_views]");
+    SVR_REQUIRE(r->params.algo == SVR_ALGO_SVREM, "the server runs SVREM requests");
+    SVR_REQUIRE(r->epochs >= 1, "epochs must be >= 1");
+    SVR_REQUIRE(r->g_host && r->w_host, "g_host and w_host are required");
+    SVR_REQUIRE(r->f0_value > 0 && std::isfinite(r->f0_value), "f0_value must be finite and > 0");
+    auto q = std::make_unique<Request>();
+    q->req = *r;
+    const int64_t M = (int64_t)g.n_views * g.n_bins;
+    q->g.assign(r->g_host, r->g_host + M);
+    q->w.assign(r->w_host, r->w_host + M);
+    q->req.g_host = nullptr;
+    q->req.w_host = nullptr;
+    q->est_bytes = footprint_estimate(*r);
+    if (q->est_bytes > S->cfg.mem_budget_bytes) {
+        set_error("request needs about %lld bytes, more than the server budget %lld", (long long)q->est_bytes,
+                  (long long)S->cfg.mem_budget_bytes);
+        return SVR_EINVAL;
+    }
+    q->ticket = S->next_ticket++;
+    q->t_submit = clk::now();
+    *ticket = q->ticket;
+    S->queue.push_back(q->ticket);
+    S->reqs[q->ticket] = std::move(q);
+    return SVR_OK;
+}
+
+int svr_serve_step(svr_server *S, int32_t max_ticks) {
+    clear_error();
+    SVR_REQUIRE(S, "NULL server");
+    SVR_HIP(hipSetDevice(S->device));
+    for (int tick = 0; max_ticks <= 0 || tick < max_ticks; ++tick) {
+        // admission: FIFO while a slot is free and the estimate fits the budget
+        while (!S->queue.empty() && (int)S->resident.size() < S->cfg.max_slots) {
+            Request *q = S->reqs[S->queue.front()].get();
+            if (S->used_bytes + q->est_bytes > S->cfg.mem_budget_bytes) break;
+            S->queue.pop_front();
+            q->stream = (int)(q->ticket % S->streams.size());
+            int rc = admit(S, q, S->streams[q->stream]);
+            if (rc) {
+                q->status = rc;
+                q->state = DONE;
+                q->t_admit = q->t_done = clk::now();
+                release(S, q);
+                continue;
+            }
+            S->resident.push_back(q->ticket);
+        }
+        if (S->resident.empty()) return SVR_OK;
+        // one epoch of SVREM for every resident request, overlapped over streams
+        for (uint64_t tk : S->resident) {
+            Request *q = S->reqs[tk].get();
+            const int Ns = q->req.n_subsets;
+            std::vector<int32_t> order(Ns);
+            for (int i = 0; i < Ns; ++i) order[i] = q->rng.below(Ns);
+            int rc = svr_svrem_epoch(q->R, order.data(), Ns, S->streams[q->stream]);
+            if (rc) q->status = rc;
+            q->epochs_done++;
+        }
+        for (hipStream_t st : S->streams) SVR_HIP(hipStreamSynchronize(st));
+        std::vector<uint64_t> still;
+        for (uint64_t tk : S->resident) {
+            Request *q = S->reqs[tk].get();
+            if (q->status != SVR_OK || q->epochs_done >= q->req.epochs) {
+                int st = q->status;
+                finish(S, q, S->streams[q->stream]);
+                if (st != SVR_OK) q->status = st;
+            } else {
+                still.push_back(tk);
+            }
+        }
+        S->resident.swap(still);
+        if (max_ticks <= 0 && S->resident.empty() && S->queue.empty()) return SVR_OK;
+    }
+    return SVR_OK;
+}
+
+int svr_serve_poll(svr_server *S, uint64_t ticket, svr_serve_result *res) {
+    clear_error();
+    SVR_REQUIRE(S && res, "NULL argument");
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("unknown ticket %llu", (unsigned long long)ticket);
+        return SVR_ENOTFOUND;
+    }
+    Request *q = it->second.get();
+    if (q->state != DONE) return SVR_PENDING;
+    if (res->f_host && !q->f.empty()) memcpy(res->f_host, q->f.data(), sizeof(float) * q->f.size());
+    res->phi = q->phi;
+    res->queue_ms = ms_since(q->t_submit, q->t_admit);
+    res->run_ms = ms_since(q->t_admit, q->t_done);
+    res->status = q->status;
+    S->reqs.erase(it);
+    return SVR_OK;
+}
+
+int svr_serve_cancel(svr_server *S, uint64_t ticket) {
+    clear_error();
+    SVR_REQUIRE(S, "NULL server");
+    auto it = S->reqs.find(ticket);
+    if (it == S->reqs.end()) {
+        set_error("unknown ticket %llu", (unsigned long long)ticket);
+        return SVR_ENOTFOUND;
+    }
+    Request *q = it->second.get();
+    if (q->state == DONE) return SVR_OK;
+    if (q->state == QUEUED) {
+        for (auto i = S->queue.begin(); i != S->queue.end(); ++i)
+            if (*i == ticket) { S->queue.erase(i); break; }
+        q->t_admit = clk::now();
+    } else {
+        (void)hipStreamSynchronize(S->streams[q->stream]);
+        release(S, q);
+        for (auto i = S->resident.begin(); i != S->resident.end(); ++i)
+            if (*i == ticket) { S->resident.erase(i); break; }
+    }
+    q->state = DONE;
+    q->status = SVR_ECANCELLED;
+    q->t_done = clk::now();
+    return SVR_OK;
+}
+
+void svr_serve_destroy(svr_server *S) {
+    if (!S) return;
+    (void)hipSetDevice(S->device);
+    for (hipStream_t st : S->streams) (void)hipStreamSynchronize(st);
+    for (auto &kv : S->reqs) release(S, kv.second.get());
+    for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+    delete S;
+}
+
+}  // extern "C"

@@ -1,0 +1,304 @@
+"""GPU parity: the HIP library against the FP64 oracle, through the C ABI.
+
+Tolerances: matrix structure and transposition exact; stored FP32 weights
+within 2.5e-7 relative of the FP64 lengths (round to nearest plus a few ulp
+of exp); projections 1e-6 relative; FP32 iterates within a relative L2 of
+1e-5 of the FP64 oracle after every epoch; the FP64 objective within 1e-6
+relative.  The subset sequence is an explicit input shared by both sides.
+"""
+
+import struct
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2106_03172_amd as pkg  # noqa: E402
+from paper_2106_03172_amd import binding  # noqa: E402
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
+
+
+@pytest.fixture(scope="module")
+def small():
+    P = datagen.make_problem(**datagen.CONFIG_SMALL)
+    Ao = oracle.system_matrix(P.geom, P.mu)
+    A = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32, mu=P.mu)
+    return P, Ao, A
+
+
+@pytest.fixture(scope="module")
+def medium():
+    """128^2, 90 views x 173 bins (ties at axis views), 9 subsets, no attenuation."""
+    P = datagen.make_problem(128, 128, 2.0, 90, 173, 2.0, 9, 3e5, attenuation=False, seed=11)
+    Ao = oracle.system_matrix(P.geom)
+    A = pkg.SystemMatrix(P.geom, 9, pkg.SVR_W_F32)
+    return P, Ao, A
+
+
+def test_matrix_matches_oracle(small):
+    P, Ao, A = small
+    ptr, idx, val = A.export(0)
+    np.testing.assert_array_equal(ptr, Ao.indptr)
+    np.testing.assert_array_equal(idx, Ao.indices)
+    np.testing.assert_allclose(val, Ao.data, rtol=2.5e-7, atol=0)
+    inf, per = A.info()
+    assert inf.nnz == Ao.nnz and inf.max_row_nnz == np.diff(Ao.indptr).max()
+    rows = oracle.subset_rows(P.geom, P.n_subsets)
+    assert [int(x) for x in per] == [Ao[r].nnz for r in rows]
+
+
+def test_transpose_matches_oracle(small):
+    P, Ao, A = small
+    ptr, idx, val = A.export(1)
+    N = P.geom.n_pixels
+    for t, r in enumerate(oracle.subset_rows(P.geom, P.n_subsets)):
+        T = Ao[r].T.tocsr()
+        T.sort_indices()
+        seg = slice(ptr[t * N], ptr[(t + 1) * N])
+        np.testing.assert_array_equal(ptr[t * N:(t + 1) * N + 1] - ptr[t * N], T.indptr)
+        np.testing.assert_array_equal(idx[seg], T.indices)
+        np.testing.assert_allclose(val[seg], T.data, rtol=2.5e-7, atol=0)
+
+
+def test_sensitivities(small):
+    P, Ao, A = small
+    m = oracle.Model(Ao, P.g, P.w, P.geom, P.n_subsets)
+    np.testing.assert_allclose(A.sensitivity(-1).cpu().numpy(), m.sens, rtol=1e-6, atol=1e-9)
+    for t in range(P.n_subsets):
+        np.testing.assert_allclose(A.sensitivity(t).cpu().numpy(), m.sens_t[t], rtol=1e-6, atol=1e-9)
+
+
+def test_project_backproject_and_adjoint(small):
+    P, Ao, A = small
+    rng = np.random.default_rng(0)
+    x = rng.uniform(0, 2, P.geom.n_pixels).astype(np.float32)
+    y = rng.uniform(0, 2, P.geom.n_rays).astype(np.float32)
+    Ax = A.project(dev(x)).cpu().numpy()[0]
+    assert rel(Ax, Ao @ x.astype(np.float64)) < 1e-6
+    ATy = A.backproject(dev(y)).cpu().numpy()[0]
+    assert rel(ATy, Ao.T @ y.astype(np.float64)) < 1e-6
+    rows = oracle.subset_rows(P.geom, P.n_subsets)
+    for t in range(P.n_subsets):
+        yt = A.project(dev(x), subset=t).cpu().numpy()[0]
+        np.testing.assert_array_equal(yt[np.setdiff1d(np.arange(P.geom.n_rays), rows[t])], 0.0)
+        xt = A.backproject(dev(y), subset=t).cpu().numpy()[0]
+        lhs = float(np.dot(yt[rows[t]].astype(np.float64), y[rows[t]]))
+        rhs = float(np.dot(x.astype(np.float64), xt))
+        assert abs(lhs - rhs) <= 2e-6 * abs(lhs)
+
+
+def _run_pair(P, Ao, A, algo, epochs, beta=0.0, alpha=1.0, eta=1, precond="subset_frozen", init_osem=True,
+              order_seed=0, obj_every=False, penalty="quadratic", delta=1.0):
+    """Runs the GPU and the oracle side by side; returns per-epoch rel errors."""
+    Ns = P.n_subsets
+    m = oracle.Model(Ao, P.g, P.w, P.geom, Ns, beta=beta, potential=binding.PEN[penalty], delta=delta)
+    f0 = np.ones((1, P.geom.n_pixels))
+    prm = pkg.params(algo, alpha=alpha, eta=eta, beta=beta, precond=precond, penalty=penalty, delta=delta)
+    R = pkg.Recon(A, P.g, P.w, f0, prm)
+    if init_osem:
+        cyc = list(range(Ns))
+        R.osem_epoch(cyc)
+        f_or = oracle.osem_epoch(m, f0, cyc)
+    else:
+        f_or = f0.copy()
+    mk = {
+        "osem": None,
+        "svrem": lambda f: oracle.SVREM(m, f, alpha, eta),
+        "svrg": lambda f: oracle.SVRG(m, f, alpha, eta, precond=binding.PRECOND[precond]),
+        "saga": lambda f: oracle.SAGA(m, f, alpha, precond=binding.PRECOND[precond]),
+        "sga": lambda f: oracle.SGA(m, f, alpha),
+        "bsrem": lambda f: oracle.BSREM(m, f, alpha),
+        "sem": lambda f: oracle.SEM(m, f, alpha),
+    }[algo]
+    alg = mk(f_or) if mk else None
+    errs, objs = [], []
+    for e in range(epochs):
+        order = datagen.make_order(Ns, Ns, seed=order_seed * 1000 + e)
+        R.epoch(algo, order)
+        if alg is None:
+            f_or = oracle.osem_epoch(m, f_or, order)
+        else:
+            alg.run(order)
+            f_or = alg.f
+        fg = R.image().cpu().numpy()
+        errs.append(rel(fg, f_or))
+        if obj_every or e == epochs - 1:
+            phi_g = R.objective()
+            phi_o = m.objective(fg.astype(np.float64))
+            objs.append(abs(phi_g - phi_o) / abs(phi_o))
+    return errs, objs, R, m
+
+
+def test_osem_matches_oracle(small):
+    P, Ao, A = small
+    errs, objs, _, _ = _run_pair(P, Ao, A, "osem", 20, init_osem=False, obj_every=True)
+    assert max(errs) <= 1e-5, errs
+    assert max(objs) <= 1e-6, objs
+
+
+def test_mlem_one_subset_matches_oracle(small):
+    P, Ao, _ = small
+    A1 = pkg.SystemMatrix(P.geom, 1, pkg.SVR_W_F32, mu=P.mu)
+    P1 = datagen.Problem(P.geom, 1, P.g, P.w, P.f_true, P.mu, P.ybar_true, P.meta)
+    errs, objs, R, m = _run_pair(P1, Ao, A1, "osem", 20, init_osem=False, obj_every=True)
+    assert max(errs) <= 1e-5, errs
+    # MLEM never decreases the likelihood: check on the GPU objective values too
+    f = np.ones((1, P.geom.n_pixels))
+    R2 = pkg.Recon(A1, P.g, P.w, f, pkg.params("osem"))
+    vals = []
+    for _ in range(10):
+        R2.osem_epoch([0])
+        vals.append(R2.objective())
+    assert np.all(np.diff(vals) >= -1e-9 * np.abs(vals[1:]))
+
+
+def _beta_for(P, Ao, frac=0.1):
+    """A beta at which the penalty gradient at the truth is ``frac`` of the
+    data-term scale (so the penalised code paths matter)."""
+    m = oracle.Model(Ao, P.g, P.w, P.geom, P.n_subsets)
+    g = m.grad_R(P.f_true)
+    return float(frac * np.linalg.norm(m.sens) / max(np.linalg.norm(g), 1e-30))
+
+
+@pytest.mark.parametrize("algo,alpha,eta,precond", [
+    ("svrem", 0.7, 1, "subset_frozen"),
+    ("svrem", 1.5, 2, "subset_frozen"),
+    ("svrg", 1.0, 2, "subset_frozen"),
+    ("svrg", 2.0, 1, "full_frozen"),
+    ("saga", 0.5, 1, "subset_frozen"),
+    ("saga", 2.0, 1, "full_frozen"),
+    # SGA and BSREM at alpha = 1 are chaotic on this problem: the oracle's own
+    # trajectory moves by 4e-2 after 6 epochs from a 1e-7 perturbation of its
+    # start (thousands of pixels hit the non-negativity clamp), so their
+    # parity is checked in the stable regime alpha = 0.5.
+    ("sga", 0.5, 1, "subset_frozen"),
+    ("bsrem", 0.5, 1, "subset_frozen"),
+    ("sem", 1.0, 1, "subset_frozen"),
+])
+def test_vr_methods_match_oracle(medium, algo, alpha, eta, precond):
+    P, Ao, A = medium
+    beta = _beta_for(P, Ao)
+    errs, objs, _, _ = _run_pair(P, Ao, A, algo, 6, beta=beta, alpha=alpha, eta=eta, precond=precond)
+    assert max(errs) <= 1e-5, errs
+    assert max(objs) <= 1e-6, objs
+
+
+@pytest.mark.parametrize("penalty,delta", [("huber", 0.05), ("logcosh", 0.05), ("hyperbola", 0.05)])
+def test_edge_preserving_penalties_match_oracle(medium, penalty, delta):
+    P, Ao, A = medium
+    scale = float(np.abs(np.diff(P.f_true[0])).mean())
+    # SVRG with a subset-frozen preconditioner at 3x this beta and alpha = 0.8
+    # is unstable: the oracle's own trajectory amplifies a 1e-7 perturbation of
+    # its start to 7e-4 within 3 epochs, so SVRG is checked at 1x and alpha = 0.5.
+    beta = _beta_for(P, Ao)
+    for algo, bmul, alpha in (("svrem", 3.0, 0.8), ("svrg", 1.0, 0.5)):
+        errs, objs, _, _ = _run_pair(P, Ao, A, algo, 3, beta=beta * bmul, alpha=alpha, eta=1,
+                                     penalty=penalty, delta=delta * scale * 10)
+        assert max(errs) <= 1e-5, (algo, errs)
+        assert max(objs) <= 1e-6, (algo, objs)
+
+
+def test_svrem_anchor_cancels_exactly(medium):
+    """At k = 0, alpha = 1: s_hat^1 = (tau_t - tau_anc_t) + s_anc = s_anc bitwise."""
+    P, Ao, A = medium
+    f0 = np.ones((1, P.geom.n_pixels))
+    R = pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem", alpha=1.0, eta=1, beta=1e-3))
+    R.osem_epoch(list(range(P.n_subsets)))
+    R.svrem_epoch([3])
+    st = R.get_state()
+    N = P.geom.n_pixels
+    off = 40 + 4 * N
+    s_hat = np.frombuffer(st, dtype=np.float64, count=N, offset=off)
+    s_anc = np.frombuffer(st, dtype=np.float64, count=N, offset=off + 8 * N)
+    np.testing.assert_array_equal(s_hat, s_anc)
+
+
+def test_determinism_and_checkpoint(medium):
+    P, Ao, A = medium
+    beta = _beta_for(P, Ao)
+    f0 = np.ones((1, P.geom.n_pixels))
+    orders = [datagen.make_order(P.n_subsets, P.n_subsets, seed=50 + e) for e in range(4)]
+
+    def run(stop_at=None):
+        R = pkg.Recon(A, P.g, P.w, f0, pkg.params("saga", alpha=1.0, beta=beta))
+        R.osem_epoch(list(range(P.n_subsets)))
+        for e, o in enumerate(orders):
+            if stop_at is not None and e == stop_at:
+                st = R.get_state()
+                R2 = pkg.Recon(A, P.g, P.w, f0, pkg.params("saga", alpha=1.0, beta=beta))
+                R2.set_state(st)
+                R = R2
+            R.saga_epoch(o)
+        return R.image().cpu().numpy()
+
+    a, b, c = run(), run(), run(stop_at=2)
+    np.testing.assert_array_equal(a, b)
+    np.testing.assert_array_equal(a, c)
+
+
+def test_invalid_inputs_are_rejected(medium):
+    P, Ao, A = medium
+    f0 = np.ones((1, P.geom.n_pixels))
+    g = P.g.copy()
+    g[0, 5] = np.nan
+    with pytest.raises(pkg.SvrError) as ei:
+        pkg.Recon(A, g, P.w, f0, pkg.params("svrem"))
+    assert ei.value.code == binding.SVR_EINVAL
+    with pytest.raises(pkg.SvrError):
+        pkg.Recon(A, P.g, -P.w, f0, pkg.params("svrem"))
+    with pytest.raises(pkg.SvrError):
+        pkg.Recon(A, P.g, P.w, 0 * f0, pkg.params("svrem"))
+    R = pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem"))
+    with pytest.raises(pkg.SvrError):
+        R.svrem_epoch([0, P.n_subsets])
+    with pytest.raises(pkg.SvrError):
+        R.saga_epoch([0])
+    with pytest.raises(pkg.SvrError):
+        pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem", alpha=0.0))
+
+
+def test_ragged_subsets_and_extreme_partitions():
+    """Views not divisible by Ns (unbalanced subsets), Ns = 1 and Ns = V,
+    odd grid, bins narrower than pixels."""
+    P = datagen.make_problem(33, 29, 3.0, 17, 41, 2.2, 5, 5e4, attenuation=True, seed=21)
+    Ao = oracle.system_matrix(P.geom, P.mu)
+    for Ns in (5, 1, 17):
+        P2 = datagen.Problem(P.geom, Ns, P.g, P.w, P.f_true, P.mu, P.ybar_true, P.meta)
+        A = pkg.SystemMatrix(P.geom, Ns, pkg.SVR_W_F32, mu=P.mu)
+        ptr, idx, val = A.export(0)
+        np.testing.assert_array_equal(idx, Ao.indices)
+        errs, objs, _, _ = _run_pair(P2, Ao, A, "svrem", 3, beta=1e-2, alpha=0.7)
+        assert max(errs) <= 1e-5, (Ns, errs)
+
+
+def test_tiny_grids():
+    for nx, ny, V, B in ((1, 1, 1, 1), (2, 1, 3, 3), (4, 4, 4, 5)):
+        geom = datagen.Geometry(nx, ny, 1.0, V, B, 1.0)
+        Ao = oracle.system_matrix(geom)
+        A = pkg.SystemMatrix(geom, 1, pkg.SVR_W_F32)
+        ptr, idx, val = A.export(0)
+        np.testing.assert_array_equal(ptr, Ao.indptr)
+        np.testing.assert_array_equal(idx, Ao.indices)
+        np.testing.assert_allclose(val, Ao.data, rtol=2.5e-7)
+
+
+def test_empty_epoch_is_a_no_op(medium):
+    P, Ao, A = medium
+    f0 = np.ones((1, P.geom.n_pixels))
+    R = pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem"))
+    R.svrem_epoch([])
+    assert R.info().k == 0
+    np.testing.assert_array_equal(R.image().cpu().numpy(), f0.astype(np.float32))
