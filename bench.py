@@ -1,0 +1,251 @@
+#!/usr/bin/env python3
+"""Throughput of the variance-reduced EM hot path on one MI355X.
+
+Workload (default): SVREM on a 256 x 256 image (2 mm pixels), 252 views x
+344 bins, 21 interleaved subsets, 1e6 counts with a 10% uniform background,
+quadratic 8-neighbour penalty with beta = 1e-2, alpha = 0.7, eta = 1, FP32
+weights.  Seeded synthetic data (ellipse phantom, Poisson counts).
+
+One step = one SVREM outer loop: an anchor pass over all subsets followed by
+eta*Ns subset updates, which the paper's accounting counts as eta + 1 epochs.
+``value`` is epochs per second with all inputs resident in HBM.
+
+The dominant kernel's duration is measured with HIP events recorded by the
+library on the stream its kernels run on, over a second pass of the same
+steps (events between kernels would perturb the step time of the first).
+
+``python bench.py [--gpus 1] [--steps K] [--warmup W]``
+"""
+
+import argparse
+import hashlib
+import json
+import os
+import re
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "SVREM epochs/s + projector HBM GB/s (256², 21 subsets); p50/p99 recon latency"
+HBM_PEAK_GBS = 8000.0
+KERNEL_SOURCES = ("kernels.h", "proj.hip", "update.hip", "penalty.h")
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, "paper_2106_03172_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def traffic_from_profile(kernel_kind, wtype):
+    """HBM bytes per launch from the committed rocprofv3 counter summary, if it
+    was taken on the current kernel sources; else None."""
+    path = os.path.join(ROOT, "profiles", f"hbm_traffic_{kernel_kind}_{wtype}.md")
+    if not os.path.exists(path):
+        return None
+    txt = open(path).read()
+    m_hash = re.search(r"kernel-source-hash:\s*([0-9a-f]+)", txt)
+    m_val = re.search(r"hbm-bytes-per-launch:\s*([0-9.eE+]+)", txt)
+    if not m_hash or not m_val or m_hash.group(1) != kernel_source_hash():
+        return None
+    return float(m_val.group(1))
+
+
+def algorithmic_bytes(kind, A_info, nnz_t_mean, M, Mt_mean, N, Ns, wb):
+    """Bytes each launch of a kernel must move at minimum."""
+    if kind == "forward":  # index + weight stream, row pointers, image, g, w, ratio
+        return nnz_t_mean * (4 + wb) + 4 * (Mt_mean + 1) + 4 * N + 12 * Mt_mean
+    if kind == "update":   # transposed stream, pointers, ratio, per-pixel SVREM state
+        return nnz_t_mean * (4 + wb) + 4 * (N + 1) + 4 * Mt_mean + 44 * N
+    if kind == "anchor_forward":
+        return A_info.nnz * (4 + wb) + 4 * (M + 1) + 4 * N + 12 * M
+    if kind == "anchor_table":  # all transposed rows, their pointers, ratio, f, table write
+        return A_info.nnz * (4 + wb) + 4 * (Ns * N + 1) + 4 * M + 4 * N + 4 * Ns * N
+    if kind == "anchor_sum":    # table read, A^T 1 (SVRG) or s_hat/s_anc writes
+        return 4 * Ns * N + 8 * N
+    raise ValueError(kind)
+
+
+def cpu_baseline(P, beta, alpha, eta, seconds):
+    """The FP64 oracle (as it stands) on the same workload, for ~``seconds``."""
+    import numpy as np
+
+    import datagen
+    import oracle
+    log("cpu baseline: building the oracle model")
+    Ao = oracle.system_matrix(P.geom)
+    m = oracle.Model(Ao, P.g, P.w, P.geom, P.n_subsets, beta=beta)
+    f0 = oracle.osem_epoch(m, np.ones((1, P.geom.n_pixels)), range(P.n_subsets))
+    alg = oracle.SVREM(m, f0, alpha, eta)
+    per = eta * P.n_subsets
+    loops = 0
+    c0, t0 = time.process_time(), time.perf_counter()
+    while True:
+        alg.run(datagen.make_order(P.n_subsets, per, seed=9000 + loops))
+        loops += 1
+        el = time.perf_counter() - t0
+        if el >= seconds or loops >= 200:
+            break
+    cpu = time.process_time() - c0
+    cores = max(1, int(round(cpu / el)))
+    log(f"cpu baseline: {loops} outer loops in {el:.1f} s")
+    return {"value": loops * (eta + 1) / el, "unit": "epochs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{loops} SVREM outer loops (anchor + {per} subset updates each) of the same "
+                      f"256x256 / 252x344 / 21-subset workload, FP64 NumPy+SciPy, {el:.1f} s wall"}
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--wtype", choices=("f32", "f16", "bf16"), default="f32")
+    ap.add_argument("--counts", type=float, default=1e6)
+    ap.add_argument("--beta", type=float, default=1e-2)
+    ap.add_argument("--alpha", type=float, default=0.7)
+    ap.add_argument("--eta", type=int, default=1)
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(f"bench.py measures a single GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: "
+              "the reconstruction path runs on one GPU and shards across GPUs only by whole requests "
+              "or slice slabs (see DESIGN.md)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2106_03172_amd as pkg
+
+    torch.cuda.set_device(0)
+    wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
+    wb = 4 if args.wtype == "f32" else 2
+    cfg = dict(datagen.CONFIG_HEADLINE)
+    cfg["counts"] = args.counts
+    P = datagen.make_problem(**cfg)
+    Ns, N, M = P.n_subsets, P.geom.n_pixels, P.geom.n_rays
+    log("building the system matrix on the device")
+    torch.cuda.synchronize()
+    tb = time.perf_counter()
+    A = pkg.SystemMatrix(P.geom, Ns, wt)
+    torch.cuda.synchronize()
+    build_s = time.perf_counter() - tb
+    inf, per_subset = A.info()
+    log(f"nnz = {inf.nnz}, build {build_s:.3f} s")
+
+    f0 = np.ones((1, N), dtype=np.float32)
+    R = pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem", alpha=args.alpha, eta=args.eta, beta=args.beta))
+    R.osem_epoch(list(range(Ns)))
+    per = args.eta * Ns
+    total = args.warmup + 2 * args.steps
+    orders = [datagen.make_order(Ns, per, seed=100 + i) for i in range(total)]
+
+    for i in range(args.warmup):
+        R.svrem_epoch(orders[i])
+    torch.cuda.synchronize()
+    log("timed region")
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        R.svrem_epoch(orders[args.warmup + i])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    epochs_per_step = args.eta + 1
+    value = args.steps * epochs_per_step / el
+    log(f"{value:.1f} epochs/s ({1e3 * el / args.steps:.3f} ms per step)")
+
+    # second pass with per-kernel HIP events
+    R.set_profiling(True)
+    used = []
+    for i in range(args.steps):
+        o = orders[args.warmup + args.steps + i]
+        used.extend(int(t) for t in o)
+        R.svrem_epoch(o)
+    kt = R.kernel_times()
+    R.set_profiling(False)
+    phi = R.objective()
+    nnz_t_mean = float(np.mean([per_subset[t] for t in used]))
+    rows_t = [(len(range(t, P.geom.n_views, Ns)) * P.geom.n_bins) for t in range(Ns)]
+    Mt_mean = float(np.mean([rows_t[t] for t in used]))
+    kernels = {}
+    for name, (n, ms) in kt.items():
+        if n == 0:
+            continue
+        avg_s = ms / n / 1e3
+        b = algorithmic_bytes(name, inf, nnz_t_mean, M, Mt_mean, N, Ns, wb)
+        kernels[name] = {"launches": n, "avg_us": avg_s * 1e6, "share": 0.0,
+                         "algorithmic_bytes": b, "gbs": b / avg_s / 1e9}
+    tot_ms = sum(v[1] for v in kt.values())
+    for name, (n, ms) in kt.items():
+        if name in kernels:
+            kernels[name]["share"] = ms / tot_ms
+    dom = max(kernels, key=lambda k: kernels[k]["share"])
+    d = kernels[dom]
+    traffic = traffic_from_profile(dom, args.wtype)
+    roofline = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
+                "avg_us": round(d["avg_us"], 3), "bytes_per_launch": int(d["algorithmic_bytes"])}
+
+    # standalone projectors over the whole matrix
+    x = torch.rand(1, N, device="cuda")
+    y = torch.rand(1, M, device="cuda")
+    yo = torch.empty(1, M, device="cuda")
+    xo = torch.empty(1, N, device="cuda")
+    for _ in range(3):
+        A.project(x, -1, yo)
+        A.backproject(y, -1, xo)
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+    reps = 20
+    ev[0].record()
+    for _ in range(reps):
+        A.project(x, -1, yo)
+    ev[1].record()
+    for _ in range(reps):
+        A.backproject(y, -1, xo)
+    ev[2].record()
+    torch.cuda.synchronize()
+    fwd_s = ev[0].elapsed_time(ev[1]) / reps / 1e3
+    bwd_s = ev[1].elapsed_time(ev[2]) / reps / 1e3
+    fwd_b = inf.nnz * (4 + wb) + 4 * (M + 1) + 4 * N + 4 * M
+    bwd_b = inf.nnz * (4 + wb) + 4 * (Ns * N + 1) + 4 * N + 12 * M
+    projector = {"forward_gbs": round(fwd_b / fwd_s / 1e9, 1), "back_gbs": round(bwd_b / bwd_s / 1e9, 1),
+                 "forward_us": round(fwd_s * 1e6, 2), "back_us": round(bwd_s * 1e6, 2),
+                 "matrix_mb": round(inf.nnz * (4 + wb) / 1e6, 1)}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        cpu = cpu_baseline(P, args.beta, args.alpha, args.eta, args.cpu_seconds)
+
+    out = {
+        "metric": METRIC, "value": round(value, 2), "unit": "epochs/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": f"SVREM 256x256 (2 mm), 252 views x 344 bins, 21 interleaved subsets, "
+                               f"counts {args.counts:.0e}, 10% background, quadratic 8-neighbour beta={args.beta}, "
+                               f"alpha={args.alpha}, eta={args.eta}; {args.wtype} weights and FP32 iterate, "
+                               f"FP64 products, sums and statistics",
+                   "epochs_per_step": epochs_per_step, "nnz": int(inf.nnz), "build_s": round(build_s, 4),
+                   "objective_after": phi, "parallelism": "single GPU",
+                   "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                               for k, v in kernels.items()},
+                   "projector": projector, "kernel_source_hash": kernel_source_hash()},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -223,6 +223,25 @@ int svr_recon_set_state(svr_recon *R, const void *buf, size_t len, void *stream)
 
 void svr_recon_destroy(svr_recon *R);
 
+/* Kernel timing (measurement aid).  While enabled, every kernel launch of the
+ * epoch calls is bracketed by two HIP events recorded on the caller's stream;
+ * svr_recon_kernel_times synchronises, reports per-kernel launch counts and
+ * summed durations since the last report, and resets them.  Kinds:
+ *   0 forward projection + EM ratio of one subset
+ *   1 fused back-projection + update of one subset
+ *   2 forward projection + EM ratio of all rows (anchor / table fill)
+ *   3 anchor back-projection of every (subset, pixel) into the table
+ *   4 anchor FP64 sums over the table (s_anc, g_tilde or Q)
+ * The events are attached to the kernel dispatch itself, so they time the
+ * kernel's execution as a profiler does. */
+#define SVR_NUM_KERNEL_KINDS 5
+typedef struct {
+    int64_t launches[SVR_NUM_KERNEL_KINDS];
+    double  total_ms[SVR_NUM_KERNEL_KINDS];
+} svr_kernel_times_t;
+int svr_recon_set_profiling(svr_recon *R, int32_t enable);
+int svr_recon_kernel_times(svr_recon *R, svr_kernel_times_t *out);
+
 /* ---- serving -------------------------------------------------------------- */
 
 /* A continuous-batching server for independent SVREM reconstruction requests

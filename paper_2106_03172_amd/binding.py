@@ -59,6 +59,10 @@ class svr_recon_info_t(C.Structure):
                 ("state_bytes", C.c_int64)]
 
 
+class svr_kernel_times_t(C.Structure):
+    _fields_ = [("launches", C.c_int64 * 5), ("total_ms", C.c_double * 5)]
+
+
 class svr_serve_config(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("n_streams", C.c_int32)]
 
@@ -94,6 +98,8 @@ _SIGS = {
     "svr_recon_get_state": ([_VP, _VP, C.POINTER(C.c_size_t), _VP], C.c_int),
     "svr_recon_set_state": ([_VP, _VP, C.c_size_t, _VP], C.c_int),
     "svr_recon_destroy": ([_VP], None),
+    "svr_recon_set_profiling": ([_VP, _I32], C.c_int),
+    "svr_recon_kernel_times": ([_VP, C.POINTER(svr_kernel_times_t)], C.c_int),
     "svr_serve_create": ([C.POINTER(svr_serve_config), C.POINTER(_VP)], C.c_int),
     "svr_serve_submit": ([_VP, C.POINTER(svr_serve_request), C.POINTER(C.c_uint64)], C.c_int),
     "svr_serve_step": ([_VP, _I32], C.c_int),
@@ -324,6 +330,16 @@ class Recon:
     def set_state(self, state: bytes, stream=None):
         buf = C.create_string_buffer(state, len(state))
         _check(lib().svr_recon_set_state(self.h, buf, len(state), _stream(stream)))
+
+    def set_profiling(self, enable: bool):
+        _check(lib().svr_recon_set_profiling(self.h, int(bool(enable))))
+
+    def kernel_times(self):
+        """{kind: (launches, total_ms)} since the last call (synchronises)."""
+        kt = svr_kernel_times_t()
+        _check(lib().svr_recon_kernel_times(self.h, C.byref(kt)))
+        names = ("forward", "update", "anchor_forward", "anchor_table", "anchor_sum")
+        return {names[i]: (int(kt.launches[i]), float(kt.total_ms[i])) for i in range(5)}
 
     def close(self):
         if getattr(self, "h", None):

@@ -7,6 +7,7 @@
 #include <vector>
 
 #include "common.h"
+#include "kernels.h"
 #include "util.h"
 
 using namespace svr;
@@ -31,6 +32,11 @@ struct svr_recon {
     int *bad = nullptr;                 // device flag / counter
     int64_t k = 0, n_snap = 0;
     bool numeric_error = false;
+    // kernel timing: pairs of events bracketing launches, with their kind
+    bool prof = false;
+    std::vector<hipEvent_t> ev;
+    std::vector<int> ev_kind;
+    size_t ev_used = 0;
 };
 
 namespace {
@@ -51,11 +57,41 @@ int kind_of_algo(int algo) {
 
 void free_recon(Recon *R) {
     if (!R) return;
+    for (hipEvent_t e : R->ev) (void)hipEventDestroy(e);
     void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ratio, R->s_hat, R->s_anc, R->Q,
                     R->g_tilde, R->table, R->dpre, R->part, R->scal, R->bad};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete R;
+}
+
+// Arms the next kernel launch of this thread to carry a pair of timing events
+// (start and end of the dispatch itself); no-op unless profiling.
+int prof_begin(Recon *R, int kind, hipStream_t) {
+    if (!R->prof) return SVR_OK;
+    if (R->ev_used + 2 > R->ev.size()) {
+        for (int i = 0; i < 2; ++i) {
+            hipEvent_t e;
+            SVR_HIP(hipEventCreate(&e));
+            R->ev.push_back(e);
+        }
+        R->ev_kind.resize(R->ev.size() / 2);
+    }
+    R->ev_kind[R->ev_used / 2] = kind;
+    LaunchEvents &t = pending_timing();
+    t.start = R->ev[R->ev_used];
+    t.stop = R->ev[R->ev_used + 1];
+    return SVR_OK;
+}
+int prof_end(Recon *R, hipStream_t) {
+    if (!R->prof) return SVR_OK;
+    LaunchEvents &t = pending_timing();
+    if (t.start) {  // the armed launch did not happen (nothing to time)
+        t.start = t.stop = nullptr;
+        return SVR_OK;
+    }
+    R->ev_used += 2;
+    return SVR_OK;
 }
 
 PenaltyArgs pen_of(const Recon *R) {
@@ -85,7 +121,9 @@ int check_order(const Recon *R, const int32_t *order, int32_t n) {
 int snapshot(Recon *R, int kind, hipStream_t s) {
     Matrix &A = *R->A;
     FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
-    int rc = launch_forward(A, 0, A.M, 1, fa, s);
+    int rc = prof_begin(R, 2, s);
+    if (!rc) rc = launch_forward(A, 0, A.M, 1, fa, s);
+    if (!rc) rc = prof_end(R, s);
     if (rc) return rc;
     SnapArgs sa{};
     sa.ratio_all = R->ratio;
@@ -97,7 +135,12 @@ int snapshot(Recon *R, int kind, hipStream_t s) {
     sa.g_tilde = R->g_tilde;
     sa.Q = R->Q;
     sa.pen = pen_of(R);
-    rc = launch_snapshot(A, kind, sa, s);
+    rc = prof_begin(R, 3, s);
+    if (!rc) rc = launch_anchor_table(A, kind, sa, s);
+    if (!rc) rc = prof_end(R, s);
+    if (!rc) rc = prof_begin(R, 4, s);
+    if (!rc) rc = launch_anchor_sum(A, kind, sa, s);
+    if (!rc) rc = prof_end(R, s);
     if (rc) return rc;
     R->n_snap++;
     return SVR_OK;
@@ -136,7 +179,9 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
         if (algo == SVR_ALGO_SEM && R->k == 0)
             SVR_HIP(hipMemsetAsync(R->s_hat, 0, sizeof(double) * (size_t)R->N, s));
         FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
-        rc = launch_forward(A, A.row_start[t], A.row_start[t + 1], 1, fa, s);
+        rc = prof_begin(R, 0, s);
+        if (!rc) rc = launch_forward(A, A.row_start[t], A.row_start[t + 1], 1, fa, s);
+        if (!rc) rc = prof_end(R, s);
         if (rc) return rc;
         UpdateArgs u{};
         u.t = t;
@@ -156,7 +201,9 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
         u.dpre_per_subset = R->dpre_per_subset;
         u.pen = pen_of(R);
         if (algo == SVR_ALGO_OSEM) u.pen.beta = 0.0;
-        rc = launch_update(A, kind, u, s);
+        rc = prof_begin(R, 1, s);
+        if (!rc) rc = launch_update(A, kind, u, s);
+        if (!rc) rc = prof_end(R, s);
         if (rc) return rc;
         R->cur = 1 - R->cur;
         if (algo != SVR_ALGO_OSEM) R->k++;
@@ -569,6 +616,30 @@ int svr_recon_set_state(svr_recon *R, const void *buf, size_t len, void *stream)
     SVR_HIP(hipStreamSynchronize(s));
     R->k = h.k;
     R->n_snap = h.n_snap;
+    return SVR_OK;
+}
+
+int svr_recon_set_profiling(svr_recon *R, int32_t enable) {
+    clear_error();
+    SVR_REQUIRE(R, "recon is NULL");
+    R->prof = enable != 0;
+    return SVR_OK;
+}
+
+int svr_recon_kernel_times(svr_recon *R, svr_kernel_times_t *out) {
+    clear_error();
+    SVR_REQUIRE(R && out, "NULL argument");
+    SVR_HIP(hipSetDevice(R->device));
+    memset(out, 0, sizeof(*out));
+    for (size_t i = 0; i < R->ev_used; i += 2) {
+        SVR_HIP(hipEventSynchronize(R->ev[i + 1]));
+        float ms = 0.0f;
+        SVR_HIP(hipEventElapsedTime(&ms, R->ev[i], R->ev[i + 1]));
+        const int k = R->ev_kind[i / 2];
+        out->launches[k] += 1;
+        out->total_ms[k] += ms;
+    }
+    R->ev_used = 0;
     return SVR_OK;
 }
 

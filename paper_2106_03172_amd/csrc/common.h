@@ -151,12 +151,14 @@ struct UpdateArgs {
 enum UpdateKind { UPD_OSEM = 0, UPD_SVREM = 1, UPD_SVRG = 2, UPD_SAGA = 3, UPD_SGA = 4, UPD_SEM = 5 };
 int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s);
 
-// snapshot: full pass over all subsets at the current image, with the full
-// ratio vector (subset-ordered, all rows) already computed.
-//  SVREM: table[t] = tau_t, s_anc = mean_t tau_t, s_hat = s_anc if init_shat
-//  SVRG : table[t] = q_t = b_t - beta/Ns grad R, g_tilde = (sum_t q_t - sens)/Ns
-//  SAGA : table[t] = q_t, Q = sum_t q_t
-//  SEM  : s_hat = s(f) (not used: SEM's first step has weight 1)
+// anchor (snapshot) pass at the current image, with the ratio of every row
+// (subset-ordered) already computed.
+//  table kernel: one entry per (subset t, pixel n):
+//    SVREM: tau_t[n] = Ns f_n b_t[n];  SVRG/SAGA: q_t[n] = b_t[n] - beta/Ns grad R(f)_n
+//  sum kernel (fixed t order, FP64):
+//    SVREM: s_anc = mean_t tau_t (and s_hat = s_anc if init_shat)
+//    SVRG : g_tilde = (sum_t q_t - A^T 1) / Ns
+//    SAGA : Q = sum_t q_t
 struct SnapArgs {
     const float *ratio_all;
     const float *f;
@@ -168,7 +170,8 @@ struct SnapArgs {
     double *Q;
     PenaltyArgs pen;
 };
-int launch_snapshot(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
+int launch_anchor_table(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
+int launch_anchor_sum(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
 
 // frozen preconditioner d = f0 / sens_t (per subset) or f0 / sens
 int launch_precond(const Matrix &A, const float *f0, int per_subset, float *d, hipStream_t s);

@@ -57,20 +57,21 @@ k_forward(const int *__restrict__ row_ptr, const int *__restrict__ col, const WT
 
 template <int MODE>
 static int launch_forward_t(const Matrix &A, int r0, int r1, const FwdArgs &a, hipStream_t s, int nb) {
+    hipError_t e;
     switch (A.wtype) {
         case SVR_W_F32:
-            k_forward<MODE, float><<<nb, FWD_THREADS, 0, s>>>(A.d_row_ptr, A.d_col, (const float *)A.d_val,
-                                                              A.d_row_sino, r0, r1, a);
+            e = launch_k(k_forward<MODE, float>, nb, FWD_THREADS, s, A.d_row_ptr, A.d_col,
+                         (const float *)A.d_val, A.d_row_sino, r0, r1, a);
             break;
         case SVR_W_F16:
-            k_forward<MODE, _Float16><<<nb, FWD_THREADS, 0, s>>>(A.d_row_ptr, A.d_col, (const _Float16 *)A.d_val,
-                                                                 A.d_row_sino, r0, r1, a);
+            e = launch_k(k_forward<MODE, _Float16>, nb, FWD_THREADS, s, A.d_row_ptr, A.d_col,
+                         (const _Float16 *)A.d_val, A.d_row_sino, r0, r1, a);
             break;
         default:
-            k_forward<MODE, bf16_t><<<nb, FWD_THREADS, 0, s>>>(A.d_row_ptr, A.d_col, (const bf16_t *)A.d_val,
-                                                               A.d_row_sino, r0, r1, a);
+            e = launch_k(k_forward<MODE, bf16_t>, nb, FWD_THREADS, s, A.d_row_ptr, A.d_col,
+                         (const bf16_t *)A.d_val, A.d_row_sino, r0, r1, a);
     }
-    SVR_HIP(hipGetLastError());
+    SVR_HIP(e);
     return SVR_OK;
 }
 

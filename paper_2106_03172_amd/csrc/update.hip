@@ -43,44 +43,50 @@ k_update(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *_
     const int n = gid / BP_G, lig = gid % BP_G;
     if (n >= N) return;
     const int64_t q = (int64_t)u.t * N + n;
+    const PenaltyArgs &p = u.pen;
+    // per-pixel operands first: they do not depend on the gather below, so
+    // their loads overlap with it
+    const float f = u.f[n];
+    constexpr bool EM = (KIND == UPD_SVREM || KIND == UPD_SEM);
+    const float st = (KIND != UPD_SVREM && KIND != UPD_SEM) ? sens_t[q] : 0.0f;
+    const double sh0 = EM ? u.s_hat[n] : 0.0;
+    const float tab = (KIND == UPD_SVREM || KIND == UPD_SVRG || KIND == UPD_SAGA) ? u.table[q] : 0.0f;
+    const double sanc = (KIND == UPD_SVREM) ? u.s_anc[n] : 0.0;
+    const double sn = (EM || KIND == UPD_SAGA) ? sens[n] : 0.0;
+    const double gt = (KIND == UPD_SVRG) ? u.g_tilde[n] : 0.0;
+    const double Qn = (KIND == UPD_SAGA) ? u.Q[n] : 0.0;
+    double D = 0.0, E = 0.0, gr = 0.0;
+    if (lig == 0 && p.beta > 0.0) {
+        if (EM) surrogate_at(u.f, n, p, D, E);
+        else if (KIND != UPD_OSEM) gr = penalty_grad_at(u.f, n, p);
+    }
     const double b = bp_group(ptrT, rowT, valT, q, u.ratio, lig);
     if (lig != 0) return;
-    const float f = u.f[n];
-    const PenaltyArgs &p = u.pen;
     float out;
     if (KIND == UPD_OSEM) {
-        const float st = sens_t[q];
         out = st > 0.0f ? (float)(((double)f * b) / (double)st) : 0.0f;
-    } else if (KIND == UPD_SVREM || KIND == UPD_SEM) {
+    } else if (EM) {
         const float tau = tau_of(u.Ns, f, b);
         double sh;
         if (KIND == UPD_SVREM)
-            sh = (1.0 - u.alpha) * u.s_hat[n] + u.alpha * (((double)tau - (double)u.table[q]) + u.s_anc[n]);
+            sh = (1.0 - u.alpha) * sh0 + u.alpha * (((double)tau - (double)tab) + sanc);
         else
-            sh = (1.0 - u.alpha) * u.s_hat[n] + u.alpha * (double)tau;
+            sh = (1.0 - u.alpha) * sh0 + u.alpha * (double)tau;
         u.s_hat[n] = sh;
-        double D = 0.0, E = 0.0;
-        if (p.beta > 0.0) surrogate_at(u.f, n, p, D, E);
-        const double sn = sens[n];
         const double bb = p.beta * D;
         const double cc = (p.beta * (double)f * D + p.beta * E) - sn;
         out = (float)mstep_root(sh, bb, cc, sn);
     } else {
-        const float st = sens_t[q];
-        const double gr = p.beta > 0.0 ? penalty_grad_at(u.f, n, p) : 0.0;
-        double dir;
-        double d;
+        double dir, d;
         if (KIND == UPD_SVRG) {
             const float qn = q_of(b, gr, p.beta, u.Ns);
-            dir = ((double)qn - (double)u.table[q]) + u.g_tilde[n];
+            dir = ((double)qn - (double)tab) + gt;
             d = precond_of(u, q, n, f, st);
         } else if (KIND == UPD_SAGA) {
             const float qn = q_of(b, gr, p.beta, u.Ns);
-            const float qo = u.table[q];
-            const double Qn = u.Q[n];
-            dir = ((double)qn - (double)qo) + (Qn - sens[n]) / (double)u.Ns;
+            dir = ((double)qn - (double)tab) + (Qn - sn) / (double)u.Ns;
             d = precond_of(u, q, n, f, st);
-            u.Q[n] = Qn + ((double)qn - (double)qo);
+            u.Q[n] = Qn + ((double)qn - (double)tab);
             u.table[q] = qn;
         } else {  // SGA / BSREM: iteration-dependent subset preconditioner
             dir = (b - (double)st) - (p.beta / (double)u.Ns) * gr;
@@ -94,20 +100,21 @@ k_update(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *_
 template <int KIND>
 static int launch_update_k(const Matrix &A, const UpdateArgs &u, hipStream_t s) {
     const int nb = (int)(((int64_t)A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
+    hipError_t e;
     switch (A.wtype) {
         case SVR_W_F32:
-            k_update<KIND, float><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const float *)A.d_valT,
-                                                           A.d_sens_t, A.d_sens, A.N, u);
+            e = launch_k(k_update<KIND, float>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT, (const float *)A.d_valT,
+                         A.d_sens_t, A.d_sens, A.N, u);
             break;
         case SVR_W_F16:
-            k_update<KIND, _Float16><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const _Float16 *)A.d_valT,
-                                                              A.d_sens_t, A.d_sens, A.N, u);
+            e = launch_k(k_update<KIND, _Float16>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT,
+                         (const _Float16 *)A.d_valT, A.d_sens_t, A.d_sens, A.N, u);
             break;
         default:
-            k_update<KIND, bf16_t><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const bf16_t *)A.d_valT,
-                                                            A.d_sens_t, A.d_sens, A.N, u);
+            e = launch_k(k_update<KIND, bf16_t>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT, (const bf16_t *)A.d_valT,
+                         A.d_sens_t, A.d_sens, A.N, u);
     }
-    SVR_HIP(hipGetLastError());
+    SVR_HIP(e);
     return SVR_OK;
 }
 
@@ -124,29 +131,35 @@ int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s)
     return SVR_EINVAL;
 }
 
-// ---- snapshot: every subset at the current image -----------------------------
+// ---- anchor pass ---------------------------------------------------------------
+// table kernel: one BP_G-lane group per (subset, pixel), the same gather and
+// the same tau / q expressions as the iteration kernel
 template <int KIND, typename WT>
 __global__ void __launch_bounds__(BP_THREADS)
-k_snapshot(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *__restrict__ valT,
-           const int *__restrict__ row_start, const double *__restrict__ sens, int Ns, int N, SnapArgs a) {
-    const int gid = blockIdx.x * BP_THREADS + threadIdx.x;
-    const int n = gid / BP_G, lig = gid % BP_G;
-    if (n >= N) return;
+k_anchor_table(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *__restrict__ valT,
+               const int *__restrict__ row_start, int Ns, int N, SnapArgs a) {
+    const int64_t gid = (int64_t)blockIdx.x * BP_THREADS + threadIdx.x;
+    const int64_t q = gid / BP_G;
+    const int lig = (int)(gid % BP_G);
+    if (q >= (int64_t)Ns * N) return;
+    const int t = (int)(q / N), n = (int)(q - (int64_t)t * N);
     const float f = a.f[n];
     const PenaltyArgs &p = a.pen;
     double gr = 0.0;
-    if (KIND != UPD_SVREM && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
-    double sum = 0.0;
-    for (int t = 0; t < Ns; ++t) {
-        const int64_t q = (int64_t)t * N + n;
-        const double b = bp_group(ptrT, rowT, valT, q, a.ratio_all + row_start[t], lig);
-        float v;
-        if (KIND == UPD_SVREM) v = tau_of(Ns, f, b);
-        else v = q_of(b, gr, p.beta, Ns);
-        if (lig == 0) a.table[q] = v;
-        sum = sum + (double)v;
-    }
+    if (KIND != UPD_SVREM && lig == 0 && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
+    const double b = bp_group(ptrT, rowT, valT, q, a.ratio_all + row_start[t], lig);
     if (lig != 0) return;
+    a.table[q] = (KIND == UPD_SVREM) ? tau_of(Ns, f, b) : q_of(b, gr, p.beta, Ns);
+}
+
+// sum kernel: FP64 sums over t in increasing order
+template <int KIND>
+__global__ void __launch_bounds__(256)
+k_anchor_sum(const double *__restrict__ sens, int Ns, int N, SnapArgs a) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    double sum = 0.0;
+    for (int t = 0; t < Ns; ++t) sum = sum + (double)a.table[(int64_t)t * N + n];
     if (KIND == UPD_SVREM) {
         const double sa = sum / (double)Ns;
         a.s_anc[n] = sa;
@@ -159,33 +172,47 @@ k_snapshot(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT 
 }
 
 template <int KIND>
-static int launch_snapshot_k(const Matrix &A, const SnapArgs &a, hipStream_t s) {
-    const int nb = (int)(((int64_t)A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
+static int launch_anchor_table_k(const Matrix &A, const SnapArgs &a, hipStream_t s) {
+    const int nb = (int)(((int64_t)A.Ns * A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
+    hipError_t e;
     switch (A.wtype) {
         case SVR_W_F32:
-            k_snapshot<KIND, float><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const float *)A.d_valT,
-                                                             A.d_row_start, A.d_sens, A.Ns, A.N, a);
+            e = launch_k(k_anchor_table<KIND, float>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT,
+                         (const float *)A.d_valT, A.d_row_start, A.Ns, A.N, a);
             break;
         case SVR_W_F16:
-            k_snapshot<KIND, _Float16><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const _Float16 *)A.d_valT,
-                                                                A.d_row_start, A.d_sens, A.Ns, A.N, a);
+            e = launch_k(k_anchor_table<KIND, _Float16>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT,
+                         (const _Float16 *)A.d_valT, A.d_row_start, A.Ns, A.N, a);
             break;
         default:
-            k_snapshot<KIND, bf16_t><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const bf16_t *)A.d_valT,
-                                                              A.d_row_start, A.d_sens, A.Ns, A.N, a);
+            e = launch_k(k_anchor_table<KIND, bf16_t>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT,
+                         (const bf16_t *)A.d_valT, A.d_row_start, A.Ns, A.N, a);
     }
-    SVR_HIP(hipGetLastError());
+    SVR_HIP(e);
     return SVR_OK;
 }
 
-int launch_snapshot(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s) {
+int launch_anchor_table(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s) {
     switch (kind) {
-        case UPD_SVREM: return launch_snapshot_k<UPD_SVREM>(A, a, s);
-        case UPD_SVRG: return launch_snapshot_k<UPD_SVRG>(A, a, s);
-        case UPD_SAGA: return launch_snapshot_k<UPD_SAGA>(A, a, s);
+        case UPD_SVREM: return launch_anchor_table_k<UPD_SVREM>(A, a, s);
+        case UPD_SVRG: return launch_anchor_table_k<UPD_SVRG>(A, a, s);
+        case UPD_SAGA: return launch_anchor_table_k<UPD_SAGA>(A, a, s);
     }
-    set_error("snapshot not defined for kind %d", kind);
+    set_error("no anchor pass for kind %d", kind);
     return SVR_EINVAL;
+}
+
+int launch_anchor_sum(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s) {
+    const int nb = (A.N + 255) / 256;
+    hipError_t e;
+    switch (kind) {
+        case UPD_SVREM: e = launch_k(k_anchor_sum<UPD_SVREM>, nb, 256, s, A.d_sens, A.Ns, A.N, a); break;
+        case UPD_SVRG: e = launch_k(k_anchor_sum<UPD_SVRG>, nb, 256, s, A.d_sens, A.Ns, A.N, a); break;
+        case UPD_SAGA: e = launch_k(k_anchor_sum<UPD_SAGA>, nb, 256, s, A.d_sens, A.Ns, A.N, a); break;
+        default: set_error("no anchor pass for kind %d", kind); return SVR_EINVAL;
+    }
+    SVR_HIP(e);
+    return SVR_OK;
 }
 
 // ---- frozen preconditioner --------------------------------------------------

@@ -6,6 +6,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "kernels.h"
 #include "util.h"
 
 namespace svr {
@@ -25,6 +26,11 @@ void set_error(const char *fmt, ...) {
 }
 void clear_error() { g_err.clear(); }
 const char *last_error() { return g_err.c_str(); }
+
+LaunchEvents &pending_timing() {
+    static thread_local LaunchEvents t;
+    return t;
+}
 
 static long g_alloc_budget = -2;  // -2: not read yet, -1: unlimited
 
