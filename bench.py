@@ -30,7 +30,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "SVREM epochs/s + projector HBM GB/s (256², 21 subsets); p50/p99 recon latency"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SOURCES = ("kernels.h", "proj.hip", "update.hip", "penalty.h")
+KERNEL_SOURCES = ("kernels.h", "phases.h", "persist.hip", "proj.hip", "update.hip", "penalty.h")
 
 
 def log(msg):
@@ -74,6 +74,15 @@ def algorithmic_bytes(kind, A_info, nnz_t_mean, M, Mt_mean, N, Ns, wb):
     raise ValueError(kind)
 
 
+def epoch_bytes(A_info, nnz_t_mean, M, Mt_mean, N, Ns, wb, per):
+    """Algorithmic bytes of one persistent epoch kernel: one anchor pass and
+    ``per`` subset iterations (forward + fused update)."""
+    args = (A_info, nnz_t_mean, M, Mt_mean, N, Ns, wb)
+    return (algorithmic_bytes("anchor_forward", *args) + algorithmic_bytes("anchor_table", *args)
+            + algorithmic_bytes("anchor_sum", *args)
+            + per * (algorithmic_bytes("forward", *args) + algorithmic_bytes("update", *args)))
+
+
 def cpu_baseline(P, beta, alpha, eta, seconds):
     """The FP64 oracle (as it stands) on the same workload, for ~``seconds``."""
     import numpy as np
@@ -114,6 +123,8 @@ def main():
     ap.add_argument("--eta", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--persistent", action="store_true",
+                    help="one persistent cooperative kernel per epoch call instead of one kernel per phase")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -146,7 +157,9 @@ def main():
     log(f"nnz = {inf.nnz}, build {build_s:.3f} s")
 
     f0 = np.ones((1, N), dtype=np.float32)
-    R = pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem", alpha=args.alpha, eta=args.eta, beta=args.beta))
+    flags = pkg.binding.FLAG_PERSISTENT_EPOCH if args.persistent else 0
+    R = pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem", alpha=args.alpha, eta=args.eta, beta=args.beta,
+                                                flags=flags))
     R.osem_epoch(list(range(Ns)))
     per = args.eta * Ns
     total = args.warmup + 2 * args.steps
@@ -183,7 +196,10 @@ def main():
         if n == 0:
             continue
         avg_s = ms / n / 1e3
-        b = algorithmic_bytes(name, inf, nnz_t_mean, M, Mt_mean, N, Ns, wb)
+        if name == "epoch":
+            b = epoch_bytes(inf, nnz_t_mean, M, Mt_mean, N, Ns, wb, per)
+        else:
+            b = algorithmic_bytes(name, inf, nnz_t_mean, M, Mt_mean, N, Ns, wb)
         kernels[name] = {"launches": n, "avg_us": avg_s * 1e6, "share": 0.0,
                          "algorithmic_bytes": b, "gbs": b / avg_s / 1e9}
     tot_ms = sum(v[1] for v in kt.values())

@@ -151,6 +151,9 @@ enum { SVR_PRECOND_SUBSET_FROZEN = 0,  /* d_t = f0 / A_t^T 1 */
        SVR_PRECOND_ITERATE       = 2 };/* d_t = f^k / A_t^T 1 */
 #define SVR_FLAG_RESET_SHAT_AT_ANCHOR 1 /* SVREM: s_hat = s_anc at every anchor */
 #define SVR_FLAG_AXIAL_PENALTY        2 /* slices: add the 2 axial neighbours */
+#define SVR_FLAG_PERSISTENT_EPOCH     4 /* run each epoch call as one persistent cooperative
+                                           kernel with grid barriers instead of one kernel
+                                           per phase (bitwise the same results) */
 
 typedef struct {
     int32_t algo;      /* SVR_ALGO_*: which state the recon keeps */
@@ -232,9 +235,11 @@ void svr_recon_destroy(svr_recon *R);
  *   2 forward projection + EM ratio of all rows (anchor / table fill)
  *   3 anchor back-projection of every (subset, pixel) into the table
  *   4 anchor FP64 sums over the table (s_anc, g_tilde or Q)
- * The events are attached to the kernel dispatch itself, so they time the
- * kernel's execution as a profiler does. */
-#define SVR_NUM_KERNEL_KINDS 5
+ *   5 persistent epoch kernel (one per epoch call; kinds 0-4 then stay 0)
+ * For kinds 0-4 the events are attached to the kernel dispatch itself, so
+ * they time the kernel's execution as a profiler does; kind 5 is bracketed
+ * by events recorded on the stream just before and after its launch. */
+#define SVR_NUM_KERNEL_KINDS 6
 typedef struct {
     int64_t launches[SVR_NUM_KERNEL_KINDS];
     double  total_ms[SVR_NUM_KERNEL_KINDS];

@@ -18,7 +18,7 @@ from typing import Optional
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "_lib", "libsvr.so")
+LIB_PATH = os.environ.get("SVR_LIBRARY", os.path.join(_HERE, "_lib", "libsvr.so"))
 
 SVR_OK, SVR_PENDING, SVR_EINVAL, SVR_ENOMEM, SVR_EDEVICE = 0, 1, -1, -2, -3
 SVR_ENOTFOUND, SVR_ENUMERIC, SVR_ECANCELLED = -4, -5, -6
@@ -26,7 +26,7 @@ SVR_W_F32, SVR_W_F16, SVR_W_BF16 = 0, 1, 2
 ALGO = dict(osem=0, svrem=1, svrg=2, saga=3, sga=4, bsrem=5, sem=6)
 PEN = dict(quadratic=0, huber=1, logcosh=2, hyperbola=3)
 PRECOND = dict(subset_frozen=0, full_frozen=1, iterate=2)
-FLAG_RESET_SHAT_AT_ANCHOR, FLAG_AXIAL_PENALTY = 1, 2
+FLAG_RESET_SHAT_AT_ANCHOR, FLAG_AXIAL_PENALTY, FLAG_PERSISTENT_EPOCH = 1, 2, 4
 
 
 class SvrError(RuntimeError):
@@ -60,7 +60,7 @@ class svr_recon_info_t(C.Structure):
 
 
 class svr_kernel_times_t(C.Structure):
-    _fields_ = [("launches", C.c_int64 * 5), ("total_ms", C.c_double * 5)]
+    _fields_ = [("launches", C.c_int64 * 6), ("total_ms", C.c_double * 6)]
 
 
 class svr_serve_config(C.Structure):
@@ -338,8 +338,8 @@ class Recon:
         """{kind: (launches, total_ms)} since the last call (synchronises)."""
         kt = svr_kernel_times_t()
         _check(lib().svr_recon_kernel_times(self.h, C.byref(kt)))
-        names = ("forward", "update", "anchor_forward", "anchor_table", "anchor_sum")
-        return {names[i]: (int(kt.launches[i]), float(kt.total_ms[i])) for i in range(5)}
+        names = ("forward", "update", "anchor_forward", "anchor_table", "anchor_sum", "epoch")
+        return {names[i]: (int(kt.launches[i]), float(kt.total_ms[i])) for i in range(6)}
 
     def close(self):
         if getattr(self, "h", None):

@@ -21,7 +21,7 @@ LIBDIR = os.path.join(HERE, "_lib")
 BUILDDIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(LIBDIR, "libsvr.so")
 
-SOURCES = ["util.hip", "geom.hip", "proj.hip", "update.hip", "api.hip", "serve.hip"]
+SOURCES = ["util.hip", "geom.hip", "proj.hip", "update.hip", "persist.hip", "api.hip", "serve.hip"]
 ARCH = os.environ.get("SVR_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
@@ -37,9 +37,9 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILDDIR, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+def _compile(src: str, defines=(), builddir=BUILDDIR) -> str:
+    obj = os.path.join(builddir, os.path.splitext(src)[0] + ".o")
+    cmd = [_hipcc(), *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -49,22 +49,24 @@ def _compile(src: str) -> str:
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    """Compiles every source and links the shared library; returns its path."""
-    os.makedirs(BUILDDIR, exist_ok=True)
-    os.makedirs(LIBDIR, exist_ok=True)
+def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
+    """Compiles every source and links the shared library; returns its path.
+    ``defines`` (e.g. ``["SVR_BP_G=8"]``) override the kernels' tuning constants."""
+    builddir = BUILDDIR if not defines else os.path.join(BUILDDIR, "_".join(defines).replace("=", ""))
+    os.makedirs(builddir, exist_ok=True)
+    os.makedirs(os.path.dirname(out), exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(_compile, srcs))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda s: _compile(s, defines, builddir), srcs))
+    tmp = out + ".tmp"
     cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
 
 
 if __name__ == "__main__":

@@ -33,6 +33,11 @@ struct svr_recon {
     int64_t k = 0, n_snap = 0;
     bool numeric_error = false;
     // kernel timing: pairs of events bracketing launches, with their kind
+    int *d_order = nullptr;             // device copy of an epoch's subset sequence
+    int order_cap = 0;
+    unsigned *d_sync = nullptr;         // grid barrier words of the persistent kernel
+    int *d_status = nullptr;            // set by a persistent kernel that aborted
+    int grid_cache[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     bool prof = false;
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_kind;
@@ -58,8 +63,8 @@ int kind_of_algo(int algo) {
 void free_recon(Recon *R) {
     if (!R) return;
     for (hipEvent_t e : R->ev) (void)hipEventDestroy(e);
-    void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ratio, R->s_hat, R->s_anc, R->Q,
-                    R->g_tilde, R->table, R->dpre, R->part, R->scal, R->bad};
+    void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ratio, R->s_hat, R->s_anc, R->Q, R->g_tilde,
+                    R->table, R->dpre, R->part, R->scal, R->bad, R->d_order, R->d_sync, R->d_status};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     delete R;
@@ -146,6 +151,90 @@ int snapshot(Recon *R, int kind, hipStream_t s) {
     return SVR_OK;
 }
 
+// number of anchor (or table-fill) passes among iterations k0 .. k0+n-1
+int64_t anchors_in(const Recon *R, int algo, int64_t k0, int n) {
+    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG) {
+        const int64_t P = (int64_t)R->p.eta * R->Ns;
+        return (k0 + n - 1) / P - (k0 - 1 >= 0 ? (k0 - 1) / P : -1);
+    }
+    if (algo == SVR_ALGO_SAGA) return k0 == 0 ? 1 : 0;
+    return 0;
+}
+
+int run_epoch_persistent(Recon *R, int algo, int kind, const int32_t *order, int32_t n, hipStream_t s) {
+    Matrix &A = *R->A;
+    if (n > R->order_cap) {
+        if (R->d_order) SVR_HIP(hipFree(R->d_order));
+        R->d_order = nullptr;
+        R->order_cap = 0;
+        SVR_HIP(dalloc(&R->d_order, n));
+        R->order_cap = n;
+    }
+    // pageable source: the copy has consumed order[] when the call returns, and
+    // it is stream-ordered after any earlier epoch still reading d_order
+    SVR_HIP(hipMemcpyAsync(R->d_order, order, sizeof(int32_t) * n, hipMemcpyHostToDevice, s));
+    SVR_HIP(hipMemsetAsync(R->d_sync, 0, sizeof(unsigned) * persistent_sync_words(), s));
+    EpochArgs e{};
+    e.row_ptr = A.d_row_ptr;
+    e.col = A.d_col;
+    e.val = A.d_val;
+    e.ptrT = A.d_ptrT;
+    e.rowT = A.d_rowT;
+    e.valT = A.d_valT;
+    e.row_start = A.d_row_start;
+    e.sens_t = A.d_sens_t;
+    e.sens = A.d_sens;
+    e.M = A.M;
+    e.N = A.N;
+    e.Ns = A.Ns;
+    e.g = R->g;
+    e.w = R->w;
+    e.ratio = R->ratio;
+    e.f0 = R->f[0];
+    e.f1 = R->f[1];
+    e.cur0 = R->cur;
+    e.s_hat = R->s_hat;
+    e.s_anc = R->s_anc;
+    e.Q = R->Q;
+    e.g_tilde = R->g_tilde;
+    e.table = R->table;
+    e.dpre = (R->p.precond == SVR_PRECOND_ITERATE) ? nullptr : R->dpre;
+    e.dpre_per_subset = R->dpre_per_subset;
+    e.pen = pen_of(R);
+    if (algo == SVR_ALGO_OSEM) e.pen.beta = 0.0;
+    e.alpha = R->p.alpha;
+    e.decay = R->p.decay;
+    e.decaying = (algo == SVR_ALGO_BSREM || algo == SVR_ALGO_SEM);
+    e.eta = R->p.eta;
+    e.flags = R->p.flags;
+    e.order = R->d_order;
+    e.n = n;
+    e.k0 = R->k;
+    e.sync = R->d_sync;
+    e.status = R->d_status;
+    int rc = prof_begin(R, 5, s);
+    if (!rc) rc = launch_epoch(A, kind, e, s, &R->grid_cache[kind]);
+    if (!rc) rc = prof_end(R, s);
+    if (rc) return rc;
+    R->n_snap += anchors_in(R, algo, R->k, n);
+    if (n & 1) R->cur = 1 - R->cur;
+    if (algo != SVR_ALGO_OSEM) R->k += n;
+    return SVR_OK;
+}
+
+// reports (once) a persistent kernel that left through its barrier time-out
+int check_status(Recon *R, hipStream_t s) {
+    int st = 0;
+    SVR_HIP(hipMemcpyAsync(&st, R->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+    SVR_HIP(hipStreamSynchronize(s));
+    if (st) {
+        (void)hipMemsetAsync(R->d_status, 0, sizeof(int), s);
+        set_error("a persistent epoch kernel aborted at a grid barrier (time-out); results are invalid");
+        return SVR_EDEVICE;
+    }
+    return SVR_OK;
+}
+
 int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream) {
     clear_error();
     SVR_REQUIRE(R, "recon is NULL");
@@ -160,6 +249,7 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
     // OSEM is the initialiser: it leaves k at 0, so the next variance-reduced
     // call starts with a fresh anchor (or table fill) and frozen preconditioner
     if (algo == SVR_ALGO_OSEM) R->k = 0;
+    if (n > 0 && (R->p.flags & SVR_FLAG_PERSISTENT_EPOCH)) return run_epoch_persistent(R, algo, kind, order, n, s);
     for (int i = 0; i < n; ++i) {
         const int t = order[i];
         if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG) {
@@ -176,8 +266,6 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
             rc = launch_precond(A, R->f[R->cur], R->dpre_per_subset, R->dpre, s);
             if (rc) return rc;
         }
-        if (algo == SVR_ALGO_SEM && R->k == 0)
-            SVR_HIP(hipMemsetAsync(R->s_hat, 0, sizeof(double) * (size_t)R->N, s));
         FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
         rc = prof_begin(R, 0, s);
         if (!rc) rc = launch_forward(A, A.row_start[t], A.row_start[t + 1], 1, fa, s);
@@ -199,6 +287,7 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
         u.g_tilde = R->g_tilde;
         u.dpre = (R->p.precond == SVR_PRECOND_ITERATE) ? nullptr : R->dpre;
         u.dpre_per_subset = R->dpre_per_subset;
+        u.shat_zero = (algo == SVR_ALGO_SEM && R->k == 0);
         u.pen = pen_of(R);
         if (algo == SVR_ALGO_OSEM) u.pen.beta = 0.0;
         rc = prof_begin(R, 1, s);
@@ -430,6 +519,8 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     chk(dalloc(&R->part, R->n_part));
     chk(dalloc(&R->scal, 2));
     chk(dalloc(&R->bad, 1));
+    chk(dalloc(&R->d_sync, persistent_sync_words()));
+    chk(dalloc(&R->d_status, 1));
     const int algo = p->algo;
     if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SEM) chk(dalloc(&R->s_hat, N));
     if (algo == SVR_ALGO_SVREM) chk(dalloc(&R->s_anc, N));
@@ -473,6 +564,7 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     if (rc) { free_recon(R); return rc; }
     SVR_HIP(hipMemcpyAsync(R->f[0], f0_dev, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
     SVR_HIP(hipMemsetAsync(R->ratio, 0, sizeof(float) * M, s));
+    SVR_HIP(hipMemsetAsync(R->d_status, 0, sizeof(int), s));
     if (R->s_hat) SVR_HIP(hipMemsetAsync(R->s_hat, 0, sizeof(double) * N, s));
     SVR_HIP(hipStreamSynchronize(s));
     *out = R;
@@ -507,6 +599,8 @@ int svr_objective(svr_recon *R, double *phi_host, void *stream) {
     SVR_HIP(hipMemcpyAsync(h, R->scal, sizeof(h), hipMemcpyDeviceToHost, s));
     SVR_HIP(hipMemcpyAsync(&bad, R->bad, sizeof(int), hipMemcpyDeviceToHost, s));
     SVR_HIP(hipStreamSynchronize(s));
+    rc = check_status(R, s);
+    if (rc) return rc;
     const double phi = bad ? -INFINITY : h[0] - R->p.beta * h[1];
     *phi_host = phi;
     if (!std::isfinite(phi)) {
@@ -581,6 +675,8 @@ int svr_recon_get_state(const svr_recon *R, void *buf, size_t *len, void *stream
     SVR_REQUIRE(*len >= tot, "buffer too small (%zu < %zu)", *len, tot);
     SVR_HIP(hipSetDevice(R->device));
     hipStream_t s = (hipStream_t)stream;
+    int rc = check_status(const_cast<Recon *>(R), s);
+    if (rc) return rc;
     StateHeader h{STATE_MAGIC, R->k, R->n_snap, R->p.algo, R->Ns, R->N, R->M};
     memcpy(buf, &h, sizeof(h));
     char *p = (char *)buf + sizeof(h);

@@ -145,6 +145,7 @@ struct UpdateArgs {
     const double *g_tilde;   // SVRG anchor full gradient / Ns (N)
     const float *dpre;       // frozen preconditioner (N or Ns*N), null for iterate mode
     int dpre_per_subset;     // 1 if dpre is Ns*N
+    int shat_zero;           // SEM first step: the previous s_hat is taken as 0
     PenaltyArgs pen;
 };
 
@@ -172,6 +173,37 @@ struct SnapArgs {
 };
 int launch_anchor_table(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
 int launch_anchor_sum(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
+
+// persistent epoch kernel (persist.hip): a whole epoch call in one
+// cooperative launch
+struct EpochArgs {
+    const int *row_ptr, *col;
+    const void *val;
+    const int *ptrT, *rowT;
+    const void *valT;
+    const int *row_start;
+    const float *sens_t;
+    const double *sens;
+    int M, N, Ns;
+    const float *g, *w;
+    float *ratio;
+    float *f0, *f1;
+    int cur0;
+    double *s_hat, *s_anc, *Q, *g_tilde;
+    float *table;
+    float *dpre;
+    int dpre_per_subset;
+    PenaltyArgs pen;
+    double alpha, decay;
+    int decaying, eta, flags;
+    const int *order;
+    int n;
+    long long k0;
+    unsigned *sync;
+    int *status;
+};
+int launch_epoch(const Matrix &A, int kind, const EpochArgs &e, hipStream_t s, int *grid_cache);
+int persistent_sync_words();
 
 // frozen preconditioner d = f0 / sens_t (per subset) or f0 / sens
 int launch_precond(const Matrix &A, const float *f0, int per_subset, float *d, hipStream_t s);

@@ -18,11 +18,20 @@
 
 namespace svr {
 
+#ifndef SVR_FWD_U
+#define SVR_FWD_U 8
+#endif
+#ifndef SVR_BP_G
+#define SVR_BP_G 4
+#endif
+#ifndef SVR_BP_U
+#define SVR_BP_U 8
+#endif
 constexpr int FWD_THREADS = 256;               // forward: 4 wavefronts per block
 constexpr int FWD_ROWS_PER_BLOCK = FWD_THREADS / 64;
-constexpr int FWD_U = 8;                       // loads in flight per lane (64*8 = 512 nnz per batch)
-constexpr int BP_G = 4;                        // back-projection lanes per pixel
-constexpr int BP_U = 8;                        // loads in flight per lane (4*8 = 32 nnz per batch)
+constexpr int FWD_U = SVR_FWD_U;               // loads in flight per lane (64*8 = 512 nnz per batch)
+constexpr int BP_G = SVR_BP_G;                 // back-projection lanes per pixel
+constexpr int BP_U = SVR_BP_U;                 // loads in flight per lane (4*8 = 32 nnz per batch)
 constexpr int BP_THREADS = 256;
 
 // ---- launches, optionally timed by events attached to the dispatch itself ----
@@ -75,6 +84,19 @@ __device__ inline double row_dot(const int *__restrict__ row_ptr, const int *__r
 // EM ratio g / ybar with the zero-denominator rule (0 if g == 0 or ybar <= 0)
 __device__ inline float em_ratio(float g, double yb) {
     return (g > 0.0f && yb > 0.0) ? (float)((double)g / yb) : 0.0f;
+}
+
+// Forward row r with the EM ratio written to ratio[r]; every lane of the
+// wavefront calls it with the same r.
+template <typename WT>
+__device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const int *__restrict__ col,
+                                     const WT *__restrict__ val, const float *__restrict__ f,
+                                     const float *__restrict__ g, const float *__restrict__ w,
+                                     float *__restrict__ ratio, int r, int lane) {
+    const float gv = g[r], wv = w[r];
+    double acc = row_dot(row_ptr, col, val, f, r, lane);
+    acc = wave_sum(acc);
+    if (lane == 0) ratio[r] = em_ratio(gv, acc + (double)wv);
 }
 
 // sum over transposed row q of val * y[row], BP_G lanes per row; every lane

@@ -1,0 +1,127 @@
+// Per-pixel and per-(subset, pixel) bodies of the fused update and anchor
+// kernels, shared by the one-kernel-per-phase path (update.hip) and the
+// persistent epoch kernel (persist.hip), so both compute bitwise the same.
+#pragma once
+
+#include "common.h"
+#include "kernels.h"
+#include "penalty.h"
+
+namespace svr {
+
+__device__ inline float tau_of(int Ns, float f, double b) { return (float)(((double)Ns * (double)f) * b); }
+
+__device__ inline float q_of(double b, double gradR, double beta, int Ns) {
+    return (float)(b - (beta / (double)Ns) * gradR);
+}
+
+__device__ inline double precond_of(const UpdateArgs &u, int64_t q, int n, float f, float st) {
+    if (u.dpre) return (double)u.dpre[u.dpre_per_subset ? q : (int64_t)n];
+    return st > 0.0f ? (double)f / (double)st : 0.0;
+}
+
+// One pixel's fused back-projection and update; the BP_G lanes of the
+// pixel's group call it together.
+template <int KIND, typename WT>
+__device__ inline void update_pixel(const int *__restrict__ ptrT, const int *__restrict__ rowT,
+                                    const WT *__restrict__ valT, const float *__restrict__ sens_t,
+                                    const double *__restrict__ sens, int N, const UpdateArgs &u, int n, int lig) {
+    const int64_t q = (int64_t)u.t * N + n;
+    const PenaltyArgs &p = u.pen;
+    // per-pixel operands first: they do not depend on the gather below, so
+    // their loads overlap with it
+    const float f = u.f[n];
+    constexpr bool EM = (KIND == UPD_SVREM || KIND == UPD_SEM);
+    const float st = (KIND != UPD_SVREM && KIND != UPD_SEM) ? sens_t[q] : 0.0f;
+    const double sh0 = (EM && !u.shat_zero) ? u.s_hat[n] : 0.0;
+    const float tab = (KIND == UPD_SVREM || KIND == UPD_SVRG || KIND == UPD_SAGA) ? u.table[q] : 0.0f;
+    const double sanc = (KIND == UPD_SVREM) ? u.s_anc[n] : 0.0;
+    const double sn = (EM || KIND == UPD_SAGA) ? sens[n] : 0.0;
+    const double gt = (KIND == UPD_SVRG) ? u.g_tilde[n] : 0.0;
+    const double Qn = (KIND == UPD_SAGA) ? u.Q[n] : 0.0;
+    double D = 0.0, E = 0.0, gr = 0.0;
+    if (lig == 0 && p.beta > 0.0) {
+        if (EM) surrogate_at(u.f, n, p, D, E);
+        else if (KIND != UPD_OSEM) gr = penalty_grad_at(u.f, n, p);
+    }
+    const double b = bp_group(ptrT, rowT, valT, q, u.ratio, lig);
+    if (lig != 0) return;
+    float out;
+    if (KIND == UPD_OSEM) {
+        out = st > 0.0f ? (float)(((double)f * b) / (double)st) : 0.0f;
+    } else if (EM) {
+        const float tau = tau_of(u.Ns, f, b);
+        double sh;
+        if (KIND == UPD_SVREM)
+            sh = (1.0 - u.alpha) * sh0 + u.alpha * (((double)tau - (double)tab) + sanc);
+        else
+            sh = (1.0 - u.alpha) * sh0 + u.alpha * (double)tau;
+        u.s_hat[n] = sh;
+        const double bb = p.beta * D;
+        const double cc = (p.beta * (double)f * D + p.beta * E) - sn;
+        out = (float)mstep_root(sh, bb, cc, sn);
+    } else {
+        double dir, d;
+        if (KIND == UPD_SVRG) {
+            const float qn = q_of(b, gr, p.beta, u.Ns);
+            dir = ((double)qn - (double)tab) + gt;
+            d = precond_of(u, q, n, f, st);
+        } else if (KIND == UPD_SAGA) {
+            const float qn = q_of(b, gr, p.beta, u.Ns);
+            dir = ((double)qn - (double)tab) + (Qn - sn) / (double)u.Ns;
+            d = precond_of(u, q, n, f, st);
+            u.Q[n] = Qn + ((double)qn - (double)tab);
+            u.table[q] = qn;
+        } else {  // SGA / BSREM: iteration-dependent subset preconditioner
+            dir = (b - (double)st) - (p.beta / (double)u.Ns) * gr;
+            d = st > 0.0f ? (double)f / (double)st : 0.0;
+        }
+        out = (float)fmax(0.0, (double)f + (u.alpha * d) * dir);
+    }
+    u.f_out[n] = out;
+}
+
+template <int KIND, typename WT>
+__device__ inline void anchor_entry(const int *__restrict__ ptrT, const int *__restrict__ rowT,
+                                    const WT *__restrict__ valT, const int *__restrict__ row_start, int Ns, int N,
+                                    const SnapArgs &a, int64_t q, int lig) {
+    const int t = (int)(q / N), n = (int)(q - (int64_t)t * N);
+    const float f = a.f[n];
+    const PenaltyArgs &p = a.pen;
+    double gr = 0.0;
+    if (KIND != UPD_SVREM && lig == 0 && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
+    const double b = bp_group(ptrT, rowT, valT, q, a.ratio_all + row_start[t], lig);
+    if (lig != 0) return;
+    a.table[q] = (KIND == UPD_SVREM) ? tau_of(Ns, f, b) : q_of(b, gr, p.beta, Ns);
+}
+
+// FP64 sums over t in increasing order
+template <int KIND>
+__device__ inline void anchor_sum_pixel(const double *__restrict__ sens, int Ns, int N, const SnapArgs &a, int n) {
+    double sum = 0.0;
+    for (int t = 0; t < Ns; ++t) sum = sum + (double)a.table[(int64_t)t * N + n];
+    if (KIND == UPD_SVREM) {
+        const double sa = sum / (double)Ns;
+        a.s_anc[n] = sa;
+        if (a.init_shat) a.s_hat[n] = sa;
+    } else if (KIND == UPD_SVRG) {
+        a.g_tilde[n] = (sum - sens[n]) / (double)Ns;
+    } else {
+        a.Q[n] = sum;
+    }
+}
+
+// frozen preconditioner entry i: d_t[n] = f0[n] / (A_t^T 1)[n] (per subset,
+// i = t*N + n) or d[n] = f0[n] / (A^T 1)[n]; 0 where the sensitivity is 0
+__device__ inline void precond_entry(const float *f0, const float *sens_t, const double *sens, int N,
+                                     int per_subset, int64_t i, float *d) {
+    if (per_subset) {
+        const int n = (int)(i % N);
+        const float st = sens_t[i];
+        d[i] = st > 0.0f ? (float)((double)f0[n] / (double)st) : 0.0f;
+    } else {
+        d[i] = sens[i] > 0.0 ? (float)((double)f0[i] / sens[i]) : 0.0f;
+    }
+}
+
+}  // namespace svr

@@ -23,13 +23,15 @@ k_forward(const int *__restrict__ row_ptr, const int *__restrict__ col, const WT
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int r = r0 + blockIdx.x * FWD_ROWS_PER_BLOCK + wv;
+    if (MODE == 1) {  // wave-uniform: the wave either has a row or not
+        if (r < r1) fwd_ratio_row(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane);
+        return;
+    }
     double acc = 0.0;
     if (r < r1) acc = row_dot(row_ptr, col, val, a.f, r, lane);
     acc = wave_sum(acc);
     if (MODE == 0) {
         if (lane == 0 && r < r1) a.out[row_sino[r]] = (float)acc;
-    } else if (MODE == 1) {
-        if (lane == 0 && r < r1) a.out[r] = em_ratio(a.g[r], acc + (double)a.w[r]);
     } else {
         __shared__ double part[FWD_ROWS_PER_BLOCK];
         if (lane == 0) {

@@ -21,19 +21,9 @@
 #include "common.h"
 #include "kernels.h"
 #include "penalty.h"
+#include "phases.h"
 
 namespace svr {
-
-__device__ inline float tau_of(int Ns, float f, double b) { return (float)(((double)Ns * (double)f) * b); }
-
-__device__ inline float q_of(double b, double gradR, double beta, int Ns) {
-    return (float)(b - (beta / (double)Ns) * gradR);
-}
-
-__device__ inline double precond_of(const UpdateArgs &u, int64_t q, int n, float f, float st) {
-    if (u.dpre) return (double)u.dpre[u.dpre_per_subset ? q : (int64_t)n];
-    return st > 0.0f ? (double)f / (double)st : 0.0;
-}
 
 template <int KIND, typename WT>
 __global__ void __launch_bounds__(BP_THREADS)
@@ -42,59 +32,7 @@ k_update(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *_
     const int gid = blockIdx.x * BP_THREADS + threadIdx.x;
     const int n = gid / BP_G, lig = gid % BP_G;
     if (n >= N) return;
-    const int64_t q = (int64_t)u.t * N + n;
-    const PenaltyArgs &p = u.pen;
-    // per-pixel operands first: they do not depend on the gather below, so
-    // their loads overlap with it
-    const float f = u.f[n];
-    constexpr bool EM = (KIND == UPD_SVREM || KIND == UPD_SEM);
-    const float st = (KIND != UPD_SVREM && KIND != UPD_SEM) ? sens_t[q] : 0.0f;
-    const double sh0 = EM ? u.s_hat[n] : 0.0;
-    const float tab = (KIND == UPD_SVREM || KIND == UPD_SVRG || KIND == UPD_SAGA) ? u.table[q] : 0.0f;
-    const double sanc = (KIND == UPD_SVREM) ? u.s_anc[n] : 0.0;
-    const double sn = (EM || KIND == UPD_SAGA) ? sens[n] : 0.0;
-    const double gt = (KIND == UPD_SVRG) ? u.g_tilde[n] : 0.0;
-    const double Qn = (KIND == UPD_SAGA) ? u.Q[n] : 0.0;
-    double D = 0.0, E = 0.0, gr = 0.0;
-    if (lig == 0 && p.beta > 0.0) {
-        if (EM) surrogate_at(u.f, n, p, D, E);
-        else if (KIND != UPD_OSEM) gr = penalty_grad_at(u.f, n, p);
-    }
-    const double b = bp_group(ptrT, rowT, valT, q, u.ratio, lig);
-    if (lig != 0) return;
-    float out;
-    if (KIND == UPD_OSEM) {
-        out = st > 0.0f ? (float)(((double)f * b) / (double)st) : 0.0f;
-    } else if (EM) {
-        const float tau = tau_of(u.Ns, f, b);
-        double sh;
-        if (KIND == UPD_SVREM)
-            sh = (1.0 - u.alpha) * sh0 + u.alpha * (((double)tau - (double)tab) + sanc);
-        else
-            sh = (1.0 - u.alpha) * sh0 + u.alpha * (double)tau;
-        u.s_hat[n] = sh;
-        const double bb = p.beta * D;
-        const double cc = (p.beta * (double)f * D + p.beta * E) - sn;
-        out = (float)mstep_root(sh, bb, cc, sn);
-    } else {
-        double dir, d;
-        if (KIND == UPD_SVRG) {
-            const float qn = q_of(b, gr, p.beta, u.Ns);
-            dir = ((double)qn - (double)tab) + gt;
-            d = precond_of(u, q, n, f, st);
-        } else if (KIND == UPD_SAGA) {
-            const float qn = q_of(b, gr, p.beta, u.Ns);
-            dir = ((double)qn - (double)tab) + (Qn - sn) / (double)u.Ns;
-            d = precond_of(u, q, n, f, st);
-            u.Q[n] = Qn + ((double)qn - (double)tab);
-            u.table[q] = qn;
-        } else {  // SGA / BSREM: iteration-dependent subset preconditioner
-            dir = (b - (double)st) - (p.beta / (double)u.Ns) * gr;
-            d = st > 0.0f ? (double)f / (double)st : 0.0;
-        }
-        out = (float)fmax(0.0, (double)f + (u.alpha * d) * dir);
-    }
-    u.f_out[n] = out;
+    update_pixel<KIND, WT>(ptrT, rowT, valT, sens_t, sens, N, u, n, lig);
 }
 
 template <int KIND>
@@ -142,33 +80,15 @@ k_anchor_table(const int *__restrict__ ptrT, const int *__restrict__ rowT, const
     const int64_t q = gid / BP_G;
     const int lig = (int)(gid % BP_G);
     if (q >= (int64_t)Ns * N) return;
-    const int t = (int)(q / N), n = (int)(q - (int64_t)t * N);
-    const float f = a.f[n];
-    const PenaltyArgs &p = a.pen;
-    double gr = 0.0;
-    if (KIND != UPD_SVREM && lig == 0 && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
-    const double b = bp_group(ptrT, rowT, valT, q, a.ratio_all + row_start[t], lig);
-    if (lig != 0) return;
-    a.table[q] = (KIND == UPD_SVREM) ? tau_of(Ns, f, b) : q_of(b, gr, p.beta, Ns);
+    anchor_entry<KIND, WT>(ptrT, rowT, valT, row_start, Ns, N, a, q, lig);
 }
 
-// sum kernel: FP64 sums over t in increasing order
 template <int KIND>
 __global__ void __launch_bounds__(256)
 k_anchor_sum(const double *__restrict__ sens, int Ns, int N, SnapArgs a) {
     const int n = blockIdx.x * 256 + threadIdx.x;
     if (n >= N) return;
-    double sum = 0.0;
-    for (int t = 0; t < Ns; ++t) sum = sum + (double)a.table[(int64_t)t * N + n];
-    if (KIND == UPD_SVREM) {
-        const double sa = sum / (double)Ns;
-        a.s_anc[n] = sa;
-        if (a.init_shat) a.s_hat[n] = sa;
-    } else if (KIND == UPD_SVRG) {
-        a.g_tilde[n] = (sum - sens[n]) / (double)Ns;
-    } else {
-        a.Q[n] = sum;
-    }
+    anchor_sum_pixel<KIND>(sens, Ns, N, a, n);
 }
 
 template <int KIND>
@@ -219,15 +139,8 @@ int launch_anchor_sum(const Matrix &A, int kind, const SnapArgs &a, hipStream_t 
 __global__ void k_precond(const float *f0, const float *sens_t, const double *sens, int Ns, int N,
                           int per_subset, float *d) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (per_subset) {
-        if (i >= (int64_t)Ns * N) return;
-        const int n = (int)(i % N);
-        const float st = sens_t[i];
-        d[i] = st > 0.0f ? (float)((double)f0[n] / (double)st) : 0.0f;
-    } else {
-        if (i >= N) return;
-        d[i] = sens[i] > 0.0 ? (float)((double)f0[i] / sens[i]) : 0.0f;
-    }
+    if (i >= (per_subset ? (int64_t)Ns * N : (int64_t)N)) return;
+    precond_entry(f0, sens_t, sens, N, per_subset, i, d);
 }
 
 int launch_precond(const Matrix &A, const float *f0, int per_subset, float *d, hipStream_t s) {

@@ -302,3 +302,29 @@ def test_empty_epoch_is_a_no_op(medium):
     R.svrem_epoch([])
     assert R.info().k == 0
     np.testing.assert_array_equal(R.image().cpu().numpy(), f0.astype(np.float32))
+
+
+@pytest.mark.parametrize("algo,precond", [("svrem", "subset_frozen"), ("svrg", "subset_frozen"),
+                                          ("svrg", "iterate"), ("saga", "full_frozen"), ("sga", "subset_frozen"),
+                                          ("bsrem", "subset_frozen"), ("sem", "subset_frozen"),
+                                          ("osem", "subset_frozen")])
+def test_persistent_and_per_phase_paths_agree_bitwise(medium, algo, precond):
+    """The persistent epoch kernel and the one-kernel-per-phase path run the
+    same device functions: images and full states must be bitwise equal,
+    including across epoch calls that straddle anchors (eta = 2, odd n)."""
+    P, Ao, A = medium
+    beta = _beta_for(P, Ao)
+    f0 = np.ones((1, P.geom.n_pixels))
+    Ns = P.n_subsets
+    orders = [datagen.make_order(Ns, n, seed=300 + i) for i, n in enumerate((Ns, 7, 2 * Ns + 3, 5))]
+    out = []
+    for flags in (0, binding.FLAG_PERSISTENT_EPOCH):
+        R = pkg.Recon(A, P.g, P.w, f0, pkg.params(algo, alpha=0.5, eta=2, beta=beta, precond=precond,
+                                                   flags=flags))
+        R.osem_epoch(list(range(Ns)))
+        for o in orders:
+            R.epoch(algo, o)
+        out.append((R.image().cpu().numpy(), R.get_state(), R.info().n_snapshots))
+    np.testing.assert_array_equal(out[0][0], out[1][0])
+    assert out[0][1] == out[1][1]
+    assert out[0][2] == out[1][2]
