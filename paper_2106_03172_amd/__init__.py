@@ -5,6 +5,6 @@ The compute path is the HIP library ``_lib/libsvr.so`` (C ABI in
 """
 
 from .binding import (  # noqa: F401
-    SvrError, SystemMatrix, Recon, params, geometry, lib, LIB_PATH, EXPORTED,
+    SvrError, SystemMatrix, Recon, Server, params, geometry, lib, LIB_PATH, EXPORTED, splitmix64_orders,
     SVR_W_F32, SVR_W_F16, SVR_W_BF16,
 )

@@ -351,3 +351,73 @@ class Recon:
             self.close()
         except Exception:
             pass
+
+
+class Server:
+    """Continuous-batching SVREM server (``svr_serve_*``)."""
+
+    def __init__(self, mem_budget_bytes: int, max_slots: int = 8, n_streams: int = 4):
+        cfg = svr_serve_config(int(mem_budget_bytes), int(max_slots), int(n_streams))
+        self.h = C.c_void_p()
+        _check(lib().svr_serve_create(C.byref(cfg), C.byref(self.h)))
+        self._keep = {}
+
+    def submit(self, geom, n_subsets: int, g, w, prm: svr_params, epochs: int, order_seed: int,
+               f0_value: float = 1.0, wtype: int = SVR_W_F32) -> int:
+        g = np.ascontiguousarray(g, dtype=np.float32).ravel()
+        w = np.ascontiguousarray(w, dtype=np.float32).ravel()
+        req = svr_serve_request(geometry(geom), int(n_subsets), int(wtype), prm, int(epochs),
+                                int(order_seed), g.ctypes.data_as(C.POINTER(C.c_float)),
+                                w.ctypes.data_as(C.POINTER(C.c_float)), float(f0_value))
+        t = C.c_uint64()
+        _check(lib().svr_serve_submit(self.h, C.byref(req), C.byref(t)))
+        self._keep[t.value] = geom.nx * geom.ny
+        return t.value
+
+    def step(self, max_ticks: int = 0):
+        _check(lib().svr_serve_step(self.h, int(max_ticks)))
+
+    def poll(self, ticket: int):
+        """None while pending, else a dict with the image and timings."""
+        n = self._keep.get(ticket, 1)  # unknown tickets are reported by the library
+        f = np.zeros(n, dtype=np.float32)
+        res = svr_serve_result(f.ctypes.data_as(C.POINTER(C.c_float)), 0.0, 0.0, 0.0, 0)
+        rc = lib().svr_serve_poll(self.h, C.c_uint64(ticket), C.byref(res))
+        if rc == SVR_PENDING:
+            return None
+        _check(rc)
+        self._keep.pop(ticket, None)
+        return dict(f=f, phi=res.phi, queue_ms=res.queue_ms, run_ms=res.run_ms, status=res.status)
+
+    def cancel(self, ticket: int):
+        _check(lib().svr_serve_cancel(self.h, C.c_uint64(ticket)))
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().svr_serve_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def splitmix64_orders(seed: int, n_subsets: int, epochs: int):
+    """The server's subset sequence: SplitMix64 (Steele, Lea and Flood, 2014)
+    from ``seed``, index = ((z >> 32) * Ns) >> 32, one epoch of Ns draws per tick."""
+    M64 = (1 << 64) - 1
+    s = int(seed) & M64
+    out = []
+    for _ in range(epochs):
+        o = []
+        for _ in range(n_subsets):
+            s = (s + 0x9E3779B97F4A7C15) & M64
+            z = s
+            z = ((z ^ (z >> 30)) * 0xBF58476D1CE4E5B9) & M64
+            z = ((z ^ (z >> 27)) * 0x94D049BB133111EB) & M64
+            z ^= z >> 31
+            o.append(((z >> 32) * n_subsets) >> 32)
+        out.append(np.array(o, dtype=np.int32))
+    return out

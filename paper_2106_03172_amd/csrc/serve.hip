@@ -48,7 +48,7 @@ struct Request {
     std::vector<float> g, w;
     State state = QUEUED;
     int status = SVR_OK;
-    int64_t est_bytes = 0, held_bytes = 0;
+    int64_t est_bytes = 0, est_matrix = 0, held_bytes = 0;
     svr_matrix *A = nullptr;
     svr_recon *R = nullptr;
     float *d_g = nullptr, *d_w = nullptr, *d_f0 = nullptr;
@@ -60,19 +60,24 @@ struct Request {
     clk::time_point t_submit, t_admit, t_done;
 };
 
-int64_t footprint_estimate(const svr_serve_request &r) {
+// Device bytes a request will hold: the matrix (both layouts) and the recon.
+// The matrix part is estimated from the geometry before the build: in parallel
+// beam each view crosses about (1 + |cos| + |sin|) * pixel/bin pieces per
+// pixel, 2.27 on average over angles; 2.6 leaves head room.
+struct Footprint {
+    int64_t matrix, rest;
+};
+Footprint footprint_estimate(const svr_serve_request &r) {
     const int64_t N = (int64_t)r.geom.nx * r.geom.ny;
     const int64_t M = (int64_t)r.geom.n_views * r.geom.n_bins;
     const int64_t Ns = r.n_subsets;
-    // parallel beam: each view crosses about (1 + |cos| + |sin|) * pixel/bin pieces
-    // per pixel (2.27 on average over angles); 2.6 leaves head room
     const double ratio = std::max(1.0, r.geom.pixel_mm / r.geom.bin_mm);
     const int64_t nnz = (int64_t)(2.6 * ratio * (double)r.geom.n_views * (double)N);
     const int wb = r.wtype == SVR_W_F32 ? 4 : 2;
-    int64_t mat = 2 * nnz * (4 + wb) + 4 * (2 * M + Ns * N) + 4 * Ns * N + 8 * N;
-    int64_t rec = 4 * (3 * M + 2 * N) + 8 * (2 * N) + 4 * Ns * N + 8 * (M / 4 + N / 256 + 8);
-    int64_t io = 4 * (2 * M + N);
-    return mat + rec + io;
+    Footprint fp;
+    fp.matrix = 2 * nnz * (4 + wb) + 4 * (2 * M + Ns * N) + 4 * Ns * N + 8 * N;
+    fp.rest = 4 * (3 * M + 2 * N) + 8 * (2 * N) + 4 * Ns * N + 8 * (M / 4 + N / 256 + 8) + 4 * (2 * M + N);
+    return fp;
 }
 
 }  // namespace
@@ -132,13 +137,10 @@ int admit(svr_server *S, Request *q, hipStream_t s) {
     for (int t = 0; t < r.n_subsets; ++t) cyc[t] = t;
     rc = svr_osem_epoch(q->R, cyc.data(), r.n_subsets, s);
     if (rc) return rc;
-    // replace the estimate by what the matrix actually holds
+    // replace the matrix estimate by what the matrix actually holds
     svr_matrix_info_t inf;
     svr_matrix_info(q->A, &inf, nullptr);
-    const int64_t actual = q->est_bytes - (int64_t)(2.6 * std::max(1.0, r.geom.pixel_mm / r.geom.bin_mm) *
-                                                    (double)r.geom.n_views * (double)N) *
-                                              2 * (4 + (r.wtype == SVR_W_F32 ? 4 : 2)) +
-                           inf.bytes;
+    const int64_t actual = q->est_bytes - q->est_matrix + inf.bytes;
     S->used_bytes += actual - q->held_bytes;
     q->held_bytes = actual;
     q->rng.s = r.order_seed;
@@ -216,7 +218,9 @@ int svr_serve_submit(svr_server *S, const svr_serve_request *r, uint64_t *ticket
     q->w.assign(r->w_host, r->w_host + M);
     q->req.g_host = nullptr;
     q->req.w_host = nullptr;
-    q->est_bytes = footprint_estimate(*r);
+    const Footprint fp = footprint_estimate(*r);
+    q->est_bytes = fp.matrix + fp.rest;
+    q->est_matrix = fp.matrix;
     if (q->est_bytes > S->cfg.mem_budget_bytes) {
         set_error("request needs about %lld bytes, more than the server budget %lld", (long long)q->est_bytes,
                   (long long)S->cfg.mem_budget_bytes);

@@ -1,0 +1,106 @@
+"""Continuous-batching server: results match the FP64 oracle run with the
+same subset sequence, each result is bitwise the same alone and in the mix,
+admission respects slots and the memory budget, cancellation works."""
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2106_03172_amd as pkg  # noqa: E402
+
+
+def rel(a, b):
+    return float(np.linalg.norm(np.ravel(a) - np.ravel(b)) / np.linalg.norm(np.ravel(b)))
+
+
+SPECS = [  # (nx, views, bins, subsets, counts, seed)
+    (48, 40, 67, 8, 5e4, 31),
+    (64, 60, 87, 6, 1e5, 32),
+    (32, 30, 45, 5, 3e4, 33),
+    (56, 50, 77, 10, 8e4, 34),
+]
+EPOCHS, ALPHA, BETA = 3, 0.7, 1e-3
+
+
+def _req(spec):
+    nx, V, B, Ns, counts, seed = spec
+    return datagen.make_problem(nx, nx, 2.0, V, B, 2.0, Ns, counts, seed=seed)
+
+
+def _serve(problems, max_slots=8, budget=1 << 31, seeds=None):
+    S = pkg.Server(budget, max_slots=max_slots, n_streams=3)
+    tickets = []
+    for i, P in enumerate(problems):
+        prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+        tickets.append(S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS,
+                                order_seed=(seeds[i] if seeds else 1000 + i)))
+    S.step(0)
+    res = [S.poll(t) for t in tickets]
+    S.close()
+    return res
+
+
+def test_server_matches_oracle_and_direct_recon():
+    P = _req(SPECS[1])
+    r = _serve([P], seeds=[77])[0]
+    assert r["status"] == 0
+    orders = pkg.splitmix64_orders(77, P.n_subsets, EPOCHS)
+    # direct recon through the C ABI with the same subset sequence: bitwise equal
+    A = pkg.SystemMatrix(P.geom, P.n_subsets)
+    R = pkg.Recon(A, P.g, P.w, np.ones((1, P.geom.n_pixels)), pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA))
+    R.osem_epoch(list(range(P.n_subsets)))
+    for o in orders:
+        R.svrem_epoch(o)
+    np.testing.assert_array_equal(r["f"], R.image().cpu().numpy()[0])
+    # FP64 oracle
+    Ao = oracle.system_matrix(P.geom)
+    m = oracle.Model(Ao, P.g, P.w, P.geom, P.n_subsets, beta=BETA)
+    f = oracle.osem_epoch(m, np.ones((1, P.geom.n_pixels)), range(P.n_subsets))
+    alg = oracle.SVREM(m, f, ALPHA, 1)
+    for o in orders:
+        alg.run(o)
+    assert rel(r["f"], alg.f) <= 1e-5
+    assert abs(r["phi"] - m.objective(r["f"][None, :].astype(np.float64))) <= 1e-6 * abs(r["phi"])
+
+
+def test_alone_equals_in_the_mix():
+    probs = [_req(s) for s in SPECS]
+    mixed = _serve(probs, max_slots=3, seeds=[11, 12, 13, 14])
+    for i, P in enumerate(probs):
+        alone = _serve([P], seeds=[11 + i])[0]
+        np.testing.assert_array_equal(alone["f"], mixed[i]["f"])
+        assert alone["phi"] == mixed[i]["phi"]
+
+
+def test_admission_by_slots_and_budget():
+    probs = [_req(s) for s in SPECS[:3]]
+    res = _serve(probs, max_slots=1)
+    assert all(r["status"] == 0 for r in res)
+    # one slot: each later request waited for the earlier ones
+    assert res[1]["queue_ms"] >= res[0]["run_ms"] * 0.5
+    assert res[2]["queue_ms"] >= res[1]["queue_ms"]
+    # a request that can never fit the budget is rejected at submit
+    S = pkg.Server(1 << 20, max_slots=2, n_streams=1)
+    with pytest.raises(pkg.SvrError):
+        S.submit(probs[0].geom, probs[0].n_subsets, probs[0].g, probs[0].w, pkg.params("svrem"), 2, 1)
+    S.close()
+
+
+def test_cancel_and_unknown_ticket():
+    probs = [_req(s) for s in SPECS[:2]]
+    S = pkg.Server(1 << 31, max_slots=1, n_streams=1)
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+    t0 = S.submit(probs[0].geom, probs[0].n_subsets, probs[0].g, probs[0].w, prm, EPOCHS, 1)
+    t1 = S.submit(probs[1].geom, probs[1].n_subsets, probs[1].g, probs[1].w, prm, EPOCHS, 2)
+    S.cancel(t1)
+    S.step(0)
+    assert S.poll(t0)["status"] == 0
+    assert S.poll(t1)["status"] == pkg.binding.SVR_ECANCELLED
+    with pytest.raises(pkg.SvrError):
+        S.poll(12345)
+    S.close()
