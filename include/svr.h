@@ -169,6 +169,9 @@ typedef struct {
 
 /* Creates a reconstruction of n_slices images that share A (the slices are
  * coupled only by the optional axial penalty).  g, w and f0 are copied.
+ * With n_slices > 1 the data are processed as one sparse-times-dense product
+ * per subset (slices as columns) and the recon runs OSEM and SVREM epochs
+ * (other algos are rejected with SVR_EINVAL).
  *   g_dev  : [S][M] counts (finite, >= 0);  w_dev: [S][M] background (finite, >= 0)
  *   f0_dev : [S][N] starting image (finite, > 0)
  * The matrix must outlive the recon.  Synchronises (validates the data). */

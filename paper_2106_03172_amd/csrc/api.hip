@@ -222,6 +222,61 @@ int run_epoch_persistent(Recon *R, int algo, int kind, const int32_t *order, int
     return SVR_OK;
 }
 
+// slice stacks: one sparse-times-dense product per phase (OSEM and SVREM)
+int run_epoch_slices(Recon *R, int algo, int kind, const int32_t *order, int32_t n, hipStream_t s) {
+    Matrix &A = *R->A;
+    const int S = R->S;
+    const int axial = (R->p.flags & SVR_FLAG_AXIAL_PENALTY) ? 1 : 0;
+    if (kind != UPD_OSEM && kind != UPD_SVREM) {
+        set_error("slice stacks (n_slices > 1) run OSEM and SVREM epochs");
+        return SVR_EINVAL;
+    }
+    int rc = SVR_OK;
+    for (int i = 0; i < n; ++i) {
+        const int t = order[i];
+        float *f = R->f[R->cur];
+        if (kind == UPD_SVREM && R->k % ((int64_t)R->p.eta * R->Ns) == 0) {
+            rc = prof_begin(R, 2, s);
+            if (!rc) rc = ms_forward(A, 0, A.M, 1, S, f, R->g, R->w, R->ratio, nullptr, nullptr, s, nullptr);
+            if (!rc) rc = prof_end(R, s);
+            if (!rc) rc = prof_begin(R, 3, s);
+            if (!rc) rc = ms_anchor_table(A, S, R->ratio, f, R->table, s);
+            if (!rc) rc = prof_end(R, s);
+            if (!rc) rc = prof_begin(R, 4, s);
+            if (!rc)
+                rc = ms_anchor_sum(A, S, R->table, R->s_anc, R->s_hat,
+                                   (R->k == 0) || (R->p.flags & SVR_FLAG_RESET_SHAT_AT_ANCHOR), s);
+            if (!rc) rc = prof_end(R, s);
+            if (rc) return rc;
+            R->n_snap++;
+        }
+        const int r0 = A.row_start[t], r1 = A.row_start[t + 1];
+        rc = prof_begin(R, 0, s);
+        if (!rc) rc = ms_forward(A, r0, r1, 1, S, f, R->g, R->w, R->ratio, nullptr, nullptr, s, nullptr);
+        if (!rc) rc = prof_end(R, s);
+        if (rc) return rc;
+        UpdateArgs u{};
+        u.t = t;
+        u.Ns = R->Ns;
+        u.ratio = R->ratio + (int64_t)r0 * S;
+        u.f = f;
+        u.f_out = R->f[1 - R->cur];
+        u.alpha = R->p.alpha;
+        u.s_hat = R->s_hat;
+        u.s_anc = R->s_anc;
+        u.table = R->table;
+        u.pen = pen_of(R);
+        if (kind == UPD_OSEM) u.pen.beta = 0.0;
+        rc = prof_begin(R, 1, s);
+        if (!rc) rc = ms_update(A, kind, S, axial, u, s);
+        if (!rc) rc = prof_end(R, s);
+        if (rc) return rc;
+        R->cur = 1 - R->cur;
+        if (algo != SVR_ALGO_OSEM) R->k++;
+    }
+    return SVR_OK;
+}
+
 // reports (once) a persistent kernel that left through its barrier time-out
 int check_status(Recon *R, hipStream_t s) {
     int st = 0;
@@ -249,6 +304,7 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
     // OSEM is the initialiser: it leaves k at 0, so the next variance-reduced
     // call starts with a fresh anchor (or table fill) and frozen preconditioner
     if (algo == SVR_ALGO_OSEM) R->k = 0;
+    if (R->S > 1) return run_epoch_slices(R, algo, kind, order, n, s);
     if (n > 0 && (R->p.flags & SVR_FLAG_PERSISTENT_EPOCH)) return run_epoch_persistent(R, algo, kind, order, n, s);
     for (int i = 0; i < n; ++i) {
         const int t = order[i];
@@ -484,7 +540,9 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     SVR_REQUIRE(out, "out is NULL");
     *out = nullptr;
     SVR_REQUIRE(A && g_dev && w_dev && f0_dev && p, "NULL argument");
-    SVR_REQUIRE(n_slices == 1, "this build reconstructs one slice per recon (n_slices = %d)", n_slices);
+    SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
+    SVR_REQUIRE(n_slices == 1 || p->algo == SVR_ALGO_SVREM || p->algo == SVR_ALGO_OSEM,
+                "slice stacks (n_slices > 1) run OSEM and SVREM");
     SVR_REQUIRE(kind_of_algo(p->algo) >= 0, "unknown algo %d", p->algo);
     SVR_REQUIRE(p->alpha > 0 && std::isfinite(p->alpha), "alpha must be finite and > 0");
     SVR_REQUIRE(p->beta >= 0 && std::isfinite(p->beta), "beta must be finite and >= 0");
@@ -507,23 +565,26 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     R->N = A->N;
     R->Ns = A->Ns;
     const int M = A->M, N = A->N, Ns = A->Ns;
-    const int64_t NT = (int64_t)Ns * N;
-    R->n_part = std::max((M + 3) / 4, (N + 255) / 256) + 1;
+    const int64_t S = n_slices;
+    const int64_t NT = (int64_t)Ns * N * S;
+    const int64_t MS_ = (int64_t)M * S, NS_ = (int64_t)N * S;
+    const int64_t nch = (S + 63) / 64;
+    R->n_part = (int)std::max<int64_t>(std::max<int64_t>((M * nch + 3) / 4, (NS_ + 255) / 256), (M + 3) / 4) + 1;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
-    chk(dalloc(&R->g, M));
-    chk(dalloc(&R->w, M));
-    chk(dalloc(&R->f[0], N));
-    chk(dalloc(&R->f[1], N));
-    chk(dalloc(&R->ratio, M));
+    chk(dalloc(&R->g, MS_));
+    chk(dalloc(&R->w, MS_));
+    chk(dalloc(&R->f[0], NS_));
+    chk(dalloc(&R->f[1], NS_));
+    chk(dalloc(&R->ratio, MS_));
     chk(dalloc(&R->part, R->n_part));
     chk(dalloc(&R->scal, 2));
     chk(dalloc(&R->bad, 1));
     chk(dalloc(&R->d_sync, persistent_sync_words()));
     chk(dalloc(&R->d_status, 1));
     const int algo = p->algo;
-    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SEM) chk(dalloc(&R->s_hat, N));
-    if (algo == SVR_ALGO_SVREM) chk(dalloc(&R->s_anc, N));
+    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SEM) chk(dalloc(&R->s_hat, NS_));
+    if (algo == SVR_ALGO_SVREM) chk(dalloc(&R->s_anc, NS_));
     if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) chk(dalloc(&R->table, NT));
     if (algo == SVR_ALGO_SVRG) chk(dalloc(&R->g_tilde, N));
     if (algo == SVR_ALGO_SAGA) chk(dalloc(&R->Q, N));
@@ -538,13 +599,13 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     }
     // validate the data on the device
     SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
-    int rc = launch_count_bad(g_dev, M, 0, R->bad, s);
-    if (!rc) rc = launch_count_bad(w_dev, M, 0, R->bad, s);
+    int rc = launch_count_bad(g_dev, MS_, 0, R->bad, s);
+    if (!rc) rc = launch_count_bad(w_dev, MS_, 0, R->bad, s);
     int nbad_gw = 0, nbad_f = 0;
     if (!rc) {
         SVR_HIP(hipMemcpyAsync(&nbad_gw, R->bad, sizeof(int), hipMemcpyDeviceToHost, s));
         SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
-        rc = launch_count_bad(f0_dev, N, 1, R->bad, s);
+        rc = launch_count_bad(f0_dev, NS_, 1, R->bad, s);
     }
     if (!rc) {
         SVR_HIP(hipMemcpyAsync(&nbad_f, R->bad, sizeof(int), hipMemcpyDeviceToHost, s));
@@ -559,13 +620,20 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
         }
         return rc;
     }
-    rc = launch_gather_rows(*A, g_dev, R->g, s);
-    if (!rc) rc = launch_gather_rows(*A, w_dev, R->w, s);
+    if (S == 1) {
+        rc = launch_gather_rows(*A, g_dev, R->g, s);
+        if (!rc) rc = launch_gather_rows(*A, w_dev, R->w, s);
+        if (!rc && hipMemcpyAsync(R->f[0], f0_dev, sizeof(float) * N, hipMemcpyDeviceToDevice, s) != hipSuccess)
+            rc = SVR_EDEVICE;
+    } else {
+        rc = ms_pack_sino(*A, (int)S, g_dev, R->g, s);
+        if (!rc) rc = ms_pack_sino(*A, (int)S, w_dev, R->w, s);
+        if (!rc) rc = ms_pack_img(N, (int)S, f0_dev, R->f[0], s);
+    }
     if (rc) { free_recon(R); return rc; }
-    SVR_HIP(hipMemcpyAsync(R->f[0], f0_dev, sizeof(float) * N, hipMemcpyDeviceToDevice, s));
-    SVR_HIP(hipMemsetAsync(R->ratio, 0, sizeof(float) * M, s));
+    SVR_HIP(hipMemsetAsync(R->ratio, 0, sizeof(float) * MS_, s));
     SVR_HIP(hipMemsetAsync(R->d_status, 0, sizeof(int), s));
-    if (R->s_hat) SVR_HIP(hipMemsetAsync(R->s_hat, 0, sizeof(double) * N, s));
+    if (R->s_hat) SVR_HIP(hipMemsetAsync(R->s_hat, 0, sizeof(double) * NS_, s));
     SVR_HIP(hipStreamSynchronize(s));
     *out = R;
     return SVR_OK;
@@ -586,12 +654,21 @@ int svr_objective(svr_recon *R, double *phi_host, void *stream) {
     hipStream_t s = (hipStream_t)stream;
     const Matrix &A = *R->A;
     SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
-    FwdArgs fa{R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad};
-    int nb = 0;
-    int rc = launch_forward(A, 0, A.M, 2, fa, s, &nb);
+    int nb = 0, nbp = 0, rc;
+    if (R->S == 1) {
+        FwdArgs fa{R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad};
+        rc = launch_forward(A, 0, A.M, 2, fa, s, &nb);
+    } else {
+        rc = ms_forward(A, 0, A.M, 2, R->S, R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad, s, &nb);
+    }
     if (!rc) rc = launch_reduce_sum(R->part, nb, R->scal, s);
-    int nbp = 0;
-    if (!rc) rc = launch_penalty_value(A, R->f[R->cur], R->p.penalty, R->p.delta, R->part, &nbp, s);
+    if (!rc) {
+        if (R->S == 1)
+            rc = launch_penalty_value(A, R->f[R->cur], R->p.penalty, R->p.delta, R->part, &nbp, s);
+        else
+            rc = ms_penalty_value(A, R->S, R->f[R->cur], R->p.penalty, R->p.delta,
+                                  (R->p.flags & SVR_FLAG_AXIAL_PENALTY) ? 1 : 0, R->part, &nbp, s);
+    }
     if (!rc) rc = launch_reduce_sum(R->part, nbp, R->scal + 1, s);
     if (rc) return rc;
     double h[2];
@@ -615,9 +692,12 @@ int svr_get_image(const svr_recon *R, float *f_dev, void *stream) {
     clear_error();
     SVR_REQUIRE(R && f_dev, "NULL argument");
     SVR_HIP(hipSetDevice(R->device));
-    SVR_HIP(hipMemcpyAsync(f_dev, R->f[R->cur], sizeof(float) * R->N, hipMemcpyDeviceToDevice,
-                           (hipStream_t)stream));
-    return SVR_OK;
+    if (R->S == 1) {
+        SVR_HIP(hipMemcpyAsync(f_dev, R->f[R->cur], sizeof(float) * R->N, hipMemcpyDeviceToDevice,
+                               (hipStream_t)stream));
+        return SVR_OK;
+    }
+    return ms_unpack_img(R->N, R->S, R->f[R->cur], f_dev, (hipStream_t)stream);
 }
 
 }  // extern "C"
@@ -629,7 +709,7 @@ struct Field {
     size_t bytes;
 };
 std::vector<Field> state_fields(const Recon *R) {
-    const size_t N = R->N, NT = (size_t)R->Ns * R->N;
+    const size_t N = (size_t)R->N * R->S, NT = (size_t)R->Ns * R->N * R->S;
     std::vector<Field> v;
     v.push_back({R->f[R->cur], 4 * N});
     if (R->s_hat) v.push_back({R->s_hat, 8 * N});
@@ -637,7 +717,7 @@ std::vector<Field> state_fields(const Recon *R) {
     if (R->Q) v.push_back({R->Q, 8 * N});
     if (R->g_tilde) v.push_back({R->g_tilde, 8 * N});
     if (R->table) v.push_back({R->table, 4 * NT});
-    if (R->dpre) v.push_back({R->dpre, 4 * (R->dpre_per_subset ? NT : N)});
+    if (R->dpre) v.push_back({R->dpre, 4 * (R->dpre_per_subset ? (size_t)R->Ns * R->N : (size_t)R->N)});
     return v;
 }
 struct StateHeader {

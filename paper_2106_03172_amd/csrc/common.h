@@ -205,6 +205,19 @@ struct EpochArgs {
 int launch_epoch(const Matrix &A, int kind, const EpochArgs &e, hipStream_t s, int *grid_cache);
 int persistent_sync_words();
 
+// slice stacks (slices.hip): images [N][S], data and ratios [row][S]
+int ms_forward(const Matrix &A, int r0, int r1, int mode, int S, const float *X, const float *g, const float *w,
+               float *ratio, double *part, int *bad, hipStream_t s, int *nb_out);
+int ms_update(const Matrix &A, int kind, int S, int axial, const UpdateArgs &u, hipStream_t s);
+int ms_anchor_table(const Matrix &A, int S, const float *ratio_all, const float *X, float *table, hipStream_t s);
+int ms_anchor_sum(const Matrix &A, int S, const float *table, double *s_anc, double *s_hat, int init_shat,
+                  hipStream_t s);
+int ms_penalty_value(const Matrix &A, int S, const float *X, int potential, double delta, int axial, double *part,
+                     int *nb_out, hipStream_t s);
+int ms_pack_sino(const Matrix &A, int S, const float *src, float *dst, hipStream_t s);
+int ms_pack_img(int N, int S, const float *src, float *dst, hipStream_t s);
+int ms_unpack_img(int N, int S, const float *src, float *dst, hipStream_t s);
+
 // frozen preconditioner d = f0 / sens_t (per subset) or f0 / sens
 int launch_precond(const Matrix &A, const float *f0, int per_subset, float *d, hipStream_t s);
 

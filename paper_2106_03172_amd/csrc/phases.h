@@ -15,6 +15,23 @@ __device__ inline float q_of(double b, double gradR, double beta, int Ns) {
     return (float)(b - (beta / (double)Ns) * gradR);
 }
 
+// OSEM update of one pixel (Sec. 2.2, eq. Mstep)
+__device__ inline float osem_math(float f, double b, float st) {
+    return st > 0.0f ? (float)(((double)f * b) / (double)st) : 0.0f;
+}
+
+// SVREM statistic recursion (Sec. 2.3, eq. tempsvrem) and penalised M-step
+// (Sec. 3): returns f+ and the new running statistic in *sh_out
+__device__ inline float svrem_math(int Ns, double alpha, double beta, float f, double b, double sh0, float tab,
+                                   double sanc, double sn, double D, double E, double *sh_out) {
+    const float tau = tau_of(Ns, f, b);
+    const double sh = (1.0 - alpha) * sh0 + alpha * (((double)tau - (double)tab) + sanc);
+    *sh_out = sh;
+    const double bb = beta * D;
+    const double cc = (beta * (double)f * D + beta * E) - sn;
+    return (float)mstep_root(sh, bb, cc, sn);
+}
+
 __device__ inline double precond_of(const UpdateArgs &u, int64_t q, int n, float f, float st) {
     if (u.dpre) return (double)u.dpre[u.dpre_per_subset ? q : (int64_t)n];
     return st > 0.0f ? (double)f / (double)st : 0.0;
@@ -48,14 +65,14 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const int *__r
     if (lig != 0) return;
     float out;
     if (KIND == UPD_OSEM) {
-        out = st > 0.0f ? (float)(((double)f * b) / (double)st) : 0.0f;
-    } else if (EM) {
-        const float tau = tau_of(u.Ns, f, b);
+        out = osem_math(f, b, st);
+    } else if (KIND == UPD_SVREM) {
         double sh;
-        if (KIND == UPD_SVREM)
-            sh = (1.0 - u.alpha) * sh0 + u.alpha * (((double)tau - (double)tab) + sanc);
-        else
-            sh = (1.0 - u.alpha) * sh0 + u.alpha * (double)tau;
+        out = svrem_math(u.Ns, u.alpha, p.beta, f, b, sh0, tab, sanc, sn, D, E, &sh);
+        u.s_hat[n] = sh;
+    } else if (EM) {  // SEM
+        const float tau = tau_of(u.Ns, f, b);
+        const double sh = (1.0 - u.alpha) * sh0 + u.alpha * (double)tau;
         u.s_hat[n] = sh;
         const double bb = p.beta * D;
         const double cc = (p.beta * (double)f * D + p.beta * E) - sn;
