@@ -123,6 +123,9 @@ def main():
     ap.add_argument("--eta", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--workload", choices=("headline", "multislice", "serve"), default="headline",
+                    help="headline: the JSON line below; multislice / serve: supplementary measurements")
+    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--persistent", action="store_true",
                     help="one persistent cooperative kernel per epoch call instead of one kernel per phase")
     args = ap.parse_args()
@@ -141,6 +144,10 @@ def main():
     import paper_2106_03172_amd as pkg
 
     torch.cuda.set_device(0)
+    if args.workload == "multislice":
+        return bench_multislice(args)
+    if args.workload == "serve":
+        return bench_serve(args)
     wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
     wb = 4 if args.wtype == "f32" else 2
     cfg = dict(datagen.CONFIG_HEADLINE)
@@ -261,6 +268,133 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_multislice(args):
+    """SVREM on a stack of 127 slices of 285 x 285 (2.5 mm) sharing one 2D matrix
+    (344 views x 435 bins, 21 subsets), in-plane 8-neighbour + 2 axial quadratic
+    penalty, one sparse-times-dense product per subset and phase."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2106_03172_amd as pkg
+    cfg = datagen.CONFIG_MULTISLICE
+    wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
+    wb = 4 if args.wtype == "f32" else 2
+    log("generating the 127-slice stack")
+    P = datagen.make_multislice_problem(cfg["nx"], cfg["ny"], cfg["pixel_mm"], cfg["n_views"], cfg["n_bins"],
+                                        cfg["bin_mm"], cfg["n_subsets"], cfg["counts"], n_slices=cfg["n_slices"],
+                                        seed=cfg["seed"])
+    Ns, S, N, M = cfg["n_subsets"], cfg["n_slices"], P.geom.n_pixels, P.geom.n_rays
+    A = pkg.SystemMatrix(P.geom, Ns, wt)
+    inf, per_subset = A.info()
+    prm = pkg.params("svrem", alpha=args.alpha, eta=args.eta, beta=args.beta,
+                     flags=pkg.binding.FLAG_AXIAL_PENALTY)
+    R = pkg.Recon(A, P.g, P.w, np.ones((S, N), dtype=np.float32), prm)
+    R.osem_epoch(list(range(Ns)))
+    per = args.eta * Ns
+    steps = max(1, args.steps)
+    orders = [datagen.make_order(Ns, per, seed=700 + i) for i in range(args.warmup + 2 * steps)]
+    for i in range(args.warmup):
+        R.svrem_epoch(orders[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(steps):
+        R.svrem_epoch(orders[args.warmup + i])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    R.set_profiling(True)
+    used = []
+    for i in range(steps):
+        o = orders[args.warmup + steps + i]
+        used.extend(int(t) for t in o)
+        R.svrem_epoch(o)
+    kt = R.kernel_times()
+    R.set_profiling(False)
+    nnz_t = float(np.mean([per_subset[t] for t in used]))
+    Mt = float(np.mean([len(range(t, P.geom.n_views, Ns)) * P.geom.n_bins for t in used]))
+    # algorithmic bytes: the matrix rows once, the image or ratio block once, data, state
+    byts = {"forward": nnz_t * (4 + wb) + 4 * (Mt + 1) + 4 * N * S + 12 * Mt * S,
+            "update": nnz_t * (4 + wb) + 4 * (N + 1) + 4 * Mt * S + 8 * N + 36 * N * S,
+            "anchor_forward": inf.nnz * (4 + wb) + 4 * (M + 1) + 4 * N * S + 12 * M * S,
+            "anchor_table": inf.nnz * (4 + wb) + 4 * (Ns * N + 1) + 4 * M * S + 4 * N * S + 4 * Ns * N * S,
+            "anchor_sum": 4 * Ns * N * S + 8 * N * S}
+    kernels = {}
+    tot = sum(v[1] for v in kt.values())
+    for name, (n, ms) in kt.items():
+        if n:
+            avg = ms / n / 1e3
+            kernels[name] = {"launches": n, "avg_us": round(avg * 1e6, 2), "share": round(ms / tot, 3),
+                             "gbs": round(byts[name] / avg / 1e9, 1)}
+    value = steps * (args.eta + 1) / el
+    print(json.dumps({"workload": "multislice", "metric": "SVREM stack epochs/s (127 x 285^2, 344x435, 21 subsets)",
+                      "value": round(value, 3), "slice_epochs_per_s": round(value * S, 1), "unit": "epochs/s",
+                      "ms_per_step": round(1e3 * el / steps, 3), "steps": steps, "wtype": args.wtype,
+                      "nnz": int(inf.nnz), "kernels": kernels, "objective_after": R.objective()}), flush=True)
+
+
+def bench_serve(args):
+    """Continuous batching of independent SVREM requests with Poisson arrivals
+    (sizes from {128, 192, 256, 384}^2, views in [120, 400], bins 1.35 N,
+    subsets in {8, 14, 21}, counts log-uniform in [1e5, 1e7], 30 epochs).
+    First all requests arrive at once to measure capacity; then they arrive
+    as a Poisson stream at 0.8 of that capacity; p50/p99 latency is taken
+    from arrival to completion."""
+    import numpy as np
+
+    import datagen
+    import paper_2106_03172_amd as pkg
+    n = args.requests
+    specs = datagen.serving_requests(n, 1.0, seed=0)
+    log(f"generating {n} requests")
+    data = []
+    for r in specs:
+        P = datagen.make_problem(r["nx"], r["ny"], r["pixel_mm"], r["n_views"], r["n_bins"], r["bin_mm"],
+                                 r["n_subsets"], r["counts"], seed=r["seed"])
+        data.append(P)
+    prm = pkg.params("svrem", alpha=args.alpha, eta=1, beta=1e-3)
+
+    def run(arrivals):
+        S = pkg.Server(64 << 30, max_slots=16, n_streams=8)
+        order = np.argsort(arrivals)
+        done, tickets = {}, {}
+        nxt = 0
+        t0 = time.perf_counter()
+        while len(done) < n:
+            now = time.perf_counter() - t0
+            while nxt < n and arrivals[order[nxt]] <= now:
+                i = int(order[nxt])
+                P = data[i]
+                tickets[i] = S.submit(P.geom, P.n_subsets, P.g, P.w, prm, specs[i]["epochs"], 1000 + i)
+                nxt += 1
+            if tickets:
+                S.step(1)
+            elif nxt < n:
+                time.sleep(max(0.0, arrivals[order[nxt]] - (time.perf_counter() - t0)))
+            for i in list(tickets):
+                res = S.poll(tickets[i])
+                if res is not None:
+                    done[i] = (time.perf_counter() - t0 - arrivals[i], res)
+                    del tickets[i]
+        total = time.perf_counter() - t0
+        S.close()
+        return done, total
+
+    done, total = run(np.zeros(n))
+    capacity = n / total
+    log(f"capacity {capacity:.2f} requests/s (all {n} at t=0, {total:.2f} s)")
+    rate = 0.8 * capacity
+    gaps = np.random.Generator(np.random.PCG64(4001)).exponential(1.0 / rate, n)
+    arrivals = np.cumsum(gaps)
+    done, total = run(arrivals)
+    lat = np.array([done[i][0] for i in range(n)]) * 1e3
+    ok = all(done[i][1]["status"] == 0 for i in range(n))
+    print(json.dumps({"workload": "serve", "metric": "p50/p99 recon latency and requests/s (Poisson arrivals)",
+                      "requests": n, "capacity_rps": round(capacity, 3), "offered_rps": round(rate, 3),
+                      "achieved_rps": round(n / total, 3), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+                      "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2),
+                      "all_ok": ok, "epochs_per_request": specs[0]["epochs"]}), flush=True)
 
 
 if __name__ == "__main__":

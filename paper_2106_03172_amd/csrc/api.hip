@@ -17,6 +17,7 @@ struct svr_recon {
     svr_params p{};
     int S = 1;
     int device = 0;
+    hipStream_t owner = nullptr;        // stream its memory was allocated on (freed there)
     int M = 0, N = 0, Ns = 0;
     float *g = nullptr, *w = nullptr;   // subset-ordered data
     float *f[2] = {nullptr, nullptr};   // ping-pong iterate
@@ -62,11 +63,11 @@ int kind_of_algo(int algo) {
 
 void free_recon(Recon *R) {
     if (!R) return;
+    AllocStream as(R->owner);
     for (hipEvent_t e : R->ev) (void)hipEventDestroy(e);
     void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ratio, R->s_hat, R->s_anc, R->Q, R->g_tilde,
                     R->table, R->dpre, R->part, R->scal, R->bad, R->d_order, R->d_sync, R->d_status};
-    for (void *q : ptrs)
-        if (q) (void)hipFree(q);
+    for (void *q : ptrs) dfree(q);
     delete R;
 }
 
@@ -164,7 +165,8 @@ int64_t anchors_in(const Recon *R, int algo, int64_t k0, int n) {
 int run_epoch_persistent(Recon *R, int algo, int kind, const int32_t *order, int32_t n, hipStream_t s) {
     Matrix &A = *R->A;
     if (n > R->order_cap) {
-        if (R->d_order) SVR_HIP(hipFree(R->d_order));
+        AllocStream as(s);
+        dfree(R->d_order);  // stream-ordered after any earlier epoch reading it
         R->d_order = nullptr;
         R->order_cap = 0;
         SVR_HIP(dalloc(&R->d_order, n));
@@ -383,6 +385,7 @@ int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t
     (void)hipGetDevice(&A->device);
     hipStream_t s = (hipStream_t)stream;
     if (mu_dev) {
+        AllocStream as(s);
         int *cnt = nullptr;
         hipError_t e = dalloc(&cnt, 1);
         if (e != hipSuccess) { delete A; set_error("allocation failed"); return SVR_ENOMEM; }
@@ -391,7 +394,7 @@ int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t
         int h = 0;
         (void)hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, s);
         (void)hipStreamSynchronize(s);
-        (void)hipFree(cnt);
+        dfree(cnt);
         if (h) { delete A; set_error("mu has %d negative or non-finite entries", h); return SVR_EINVAL; }
     }
     rc = build_matrix(*A, mu_dev, s);
@@ -490,10 +493,10 @@ int svr_sensitivity(const svr_matrix *A, int32_t subset, double *out_dev, void *
 void svr_matrix_destroy(svr_matrix *A) {
     if (!A) return;
     (void)hipSetDevice(A->device);
+    AllocStream as(A->owner);
     void *ptrs[] = {A->d_row_start, A->d_row_sino, A->d_row_ptr, A->d_col, A->d_val, A->d_ptrT,
                     A->d_rowT, A->d_valT, A->d_sens_t, A->d_sens};
-    for (void *q : ptrs)
-        if (q) (void)hipFree(q);
+    for (void *q : ptrs) dfree(q);
     delete A;
 }
 
@@ -557,6 +560,8 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     hipStream_t s = (hipStream_t)stream;
     svr_recon *R = new (std::nothrow) svr_recon();
     SVR_REQUIRE(R, "host allocation failed");
+    AllocStream as(s);
+    R->owner = s;
     R->A = A;
     R->p = *p;
     R->S = n_slices;

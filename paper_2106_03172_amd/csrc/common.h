@@ -35,9 +35,18 @@ void clear_error();
         }                                                                         \
     } while (0)
 
-// Device allocation helper that honours an optional fault-injection budget
-// (environment SVR_FAULT_ALLOC_AFTER=n makes the (n+1)-th allocation fail).
+// Device allocations are stream-ordered (hipMallocAsync / hipFreeAsync) on the
+// stream set by the innermost AllocStream of the calling thread, so creating
+// or destroying an object never waits for work on other streams.  dmalloc
+// honours an optional fault-injection budget (environment
+// SVR_FAULT_ALLOC_AFTER=n makes the (n+1)-th allocation fail).
+struct AllocStream {
+    hipStream_t prev;
+    explicit AllocStream(hipStream_t s);
+    ~AllocStream();
+};
 hipError_t dmalloc(void **p, size_t bytes);
+void dfree(void *p);
 template <typename T>
 inline hipError_t dalloc(T **p, size_t count) {
     return dmalloc(reinterpret_cast<void **>(p), count * sizeof(T));
@@ -65,6 +74,7 @@ struct Matrix {
     int64_t nnz = 0;
     int max_row_nnz = 0, max_col_nnz = 0;
     int device = 0;
+    hipStream_t owner = nullptr;    // stream its memory was allocated on (freed there)
     std::vector<int> row_start;     // host, Ns+1: first subset-ordered row of each subset
     std::vector<int64_t> nnz_sub;   // host, Ns
     int *d_row_start = nullptr;     // device copy of row_start

@@ -201,75 +201,88 @@ __global__ void k_sens(int Ns, int N, const int *ptrT, const WT *valT, float *se
     sens[n] = tot;
 }
 
+// stats[0] = longest row, stats[1] = longest transposed row, stats[2 + t] =
+// row_ptr at the first row of subset t (t = 0..Ns)
+__global__ void k_row_stats(int M, const int *row_ptr, int *stats) {
+    const int r = blockIdx.x * blockDim.x + threadIdx.x;
+    if (r < M) atomicMax(&stats[0], row_ptr[r + 1] - row_ptr[r]);
+}
+__global__ void k_max_count(int64_t n, const int *cnt, int *stats) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) atomicMax(&stats[1], cnt[i]);
+}
+__global__ void k_subset_offsets(int Ns, const int *row_start, const int *row_ptr, int *stats) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t <= Ns) stats[2 + t] = row_ptr[row_start[t]];
+}
+
 template <typename WT>
 static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     const int M = A.M, N = A.N, Ns = A.Ns, B = A.geom.n_bins;
     const int T = 256;
     const int gM = (M + T - 1) / T;
-    int *counts = nullptr;
+    const int64_t NT = (int64_t)Ns * N;
+    int *counts = nullptr, *cnt = nullptr, *stats = nullptr;
+    auto cleanup = [&]() {
+        dfree(counts);
+        dfree(cnt);
+        dfree(stats);
+    };
     SVR_HIP(dalloc(&counts, M));
+    SVR_HIP(dalloc(&stats, Ns + 3));
+    SVR_HIP(hipMemsetAsync(stats, 0, sizeof(int) * (Ns + 3), s));
     k_siddon_count<<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, counts);
     SVR_HIP(hipGetLastError());
     SVR_HIP(dalloc(&A.d_row_ptr, M + 1));
     int64_t nnz = 0;
-    int rc = exclusive_scan(counts, M, A.d_row_ptr, &nnz, s);
-    if (rc) { (void)hipFree(counts); return rc; }
+    int rc = exclusive_scan(counts, M, A.d_row_ptr, &nnz, s);  // synchronises: nnz sizes the arrays
+    if (rc) { cleanup(); return rc; }
     A.nnz = nnz;
-    SVR_HIP(dalloc(&A.d_col, nnz));
     WT *val = nullptr, *valT = nullptr;
+    SVR_HIP(dalloc(&A.d_col, nnz));
     SVR_HIP(dalloc(&val, nnz));
-    A.d_val = val;
-    k_siddon_fill<WT><<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, A.d_row_ptr, mu, A.d_col, val);
-    SVR_HIP(hipGetLastError());
-
-    // host copies of the row counts: per-subset nnz and the longest row
-    std::vector<int> hptr(M + 1);
-    SVR_HIP(hipMemcpyAsync(hptr.data(), A.d_row_ptr, sizeof(int) * (M + 1), hipMemcpyDeviceToHost, s));
-    SVR_HIP(hipStreamSynchronize(s));
-    A.nnz_sub.assign(Ns, 0);
-    A.max_row_nnz = 0;
-    for (int t = 0; t < Ns; ++t)
-        A.nnz_sub[t] = (int64_t)hptr[A.row_start[t + 1]] - hptr[A.row_start[t]];
-    for (int r = 0; r < M; ++r) A.max_row_nnz = std::max(A.max_row_nnz, hptr[r + 1] - hptr[r]);
-
-    // transposed rows per subset
-    const int64_t NT = (int64_t)Ns * N;
-    int *cnt = nullptr;
-    SVR_HIP(dalloc(&cnt, NT));
-    SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
-    k_col_count<<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, A.d_col, cnt);
-    SVR_HIP(hipGetLastError());
-    SVR_HIP(dalloc(&A.d_ptrT, NT + 1));
-    int64_t nnzT = 0;
-    rc = exclusive_scan(cnt, NT, A.d_ptrT, &nnzT, s);
-    if (rc) { (void)hipFree(counts); (void)hipFree(cnt); return rc; }
-    if (nnzT != nnz) { set_error("transpose count mismatch"); return SVR_EDEVICE; }
-    std::vector<int> hcnt(NT);
-    SVR_HIP(hipMemcpyAsync(hcnt.data(), cnt, sizeof(int) * NT, hipMemcpyDeviceToHost, s));
-    SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
     SVR_HIP(dalloc(&A.d_rowT, nnz));
     SVR_HIP(dalloc(&valT, nnz));
-    A.d_valT = valT;
-    k_fill_T<WT><<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, A.d_col,
-                                  val, A.d_ptrT, cnt, A.d_rowT, valT);
-    SVR_HIP(hipGetLastError());
-    k_sort_T<WT><<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, A.d_rowT, valT);
-    SVR_HIP(hipGetLastError());
+    SVR_HIP(dalloc(&cnt, NT));
+    SVR_HIP(dalloc(&A.d_ptrT, NT + 1));
     SVR_HIP(dalloc(&A.d_sens_t, NT));
     SVR_HIP(dalloc(&A.d_sens, N));
+    A.d_val = val;
+    A.d_valT = valT;
+    k_siddon_fill<WT><<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, A.d_row_ptr, mu, A.d_col, val);
+    k_row_stats<<<gM, T, 0, s>>>(M, A.d_row_ptr, stats);
+    k_subset_offsets<<<(Ns + 1 + T - 1) / T, T, 0, s>>>(Ns, A.d_row_start, A.d_row_ptr, stats);
+    // transposed rows per subset
+    SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
+    k_col_count<<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, A.d_col, cnt);
+    k_max_count<<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, cnt, stats);
+    SVR_HIP(hipGetLastError());
+    int64_t nnzT = 0;
+    rc = exclusive_scan(cnt, NT, A.d_ptrT, &nnzT, s);
+    if (rc) { cleanup(); return rc; }
+    if (nnzT != nnz) { cleanup(); set_error("transpose count mismatch"); return SVR_EDEVICE; }
+    SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
+    k_fill_T<WT><<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, A.d_col,
+                                  val, A.d_ptrT, cnt, A.d_rowT, valT);
+    k_sort_T<WT><<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, A.d_rowT, valT);
     k_sens<WT><<<(N + T - 1) / T, T, 0, s>>>(Ns, N, A.d_ptrT, valT, A.d_sens_t, A.d_sens);
     SVR_HIP(hipGetLastError());
+    std::vector<int> h(Ns + 3);
+    SVR_HIP(hipMemcpyAsync(h.data(), stats, sizeof(int) * (Ns + 3), hipMemcpyDeviceToHost, s));
     SVR_HIP(hipStreamSynchronize(s));
-    A.max_col_nnz = 0;
-    for (int64_t q = 0; q < NT; ++q) A.max_col_nnz = std::max(A.max_col_nnz, hcnt[q]);
-    SVR_HIP(hipFree(counts));
-    SVR_HIP(hipFree(cnt));
+    A.max_row_nnz = h[0];
+    A.max_col_nnz = h[1];
+    A.nnz_sub.assign(Ns, 0);
+    for (int t = 0; t < Ns; ++t) A.nnz_sub[t] = (int64_t)h[2 + t + 1] - h[2 + t];
+    cleanup();
     A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + 2 * nnz + NT + 1 + (Ns + 1)) +
               (int64_t)A.wbytes() * 2 * nnz + (int64_t)sizeof(float) * NT + (int64_t)sizeof(double) * N;
     return SVR_OK;
 }
 
 int build_matrix(Matrix &A, const float *mu_dev, hipStream_t s) {
+    AllocStream as(s);
+    A.owner = s;
     const svr_geometry &g = A.geom;
     const int Ns = A.Ns, B = g.n_bins;
     A.M = g.n_views * B;

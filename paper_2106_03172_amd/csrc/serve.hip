@@ -100,9 +100,10 @@ namespace {
 void release(svr_server *S, Request *q) {
     if (q->R) svr_recon_destroy(q->R);
     if (q->A) svr_matrix_destroy(q->A);
-    if (q->d_g) (void)hipFree(q->d_g);
-    if (q->d_w) (void)hipFree(q->d_w);
-    if (q->d_f0) (void)hipFree(q->d_f0);
+    AllocStream as(S->streams[q->stream]);
+    dfree(q->d_g);
+    dfree(q->d_w);
+    dfree(q->d_f0);
     q->R = nullptr;
     q->A = nullptr;
     q->d_g = q->d_w = q->d_f0 = nullptr;
@@ -117,6 +118,7 @@ __global__ void k_fill(float *x, int64_t n, float v) {
 
 // builds the request's matrix and recon and runs the OSEM initialisation epoch
 int admit(svr_server *S, Request *q, hipStream_t s) {
+    AllocStream as(s);
     const svr_serve_request &r = q->req;
     const int64_t M = (int64_t)r.geom.n_views * r.geom.n_bins;
     const int64_t N = (int64_t)r.geom.nx * r.geom.ny;
@@ -157,11 +159,12 @@ int finish(svr_server *S, Request *q, hipStream_t s) {
     q->status = rc;
     q->f.resize(N);
     float *tmp = nullptr;
+    AllocStream as(s);
     if (dalloc(&tmp, N) == hipSuccess) {
         svr_get_image(q->R, tmp, s);
         (void)hipMemcpyAsync(q->f.data(), tmp, sizeof(float) * N, hipMemcpyDeviceToHost, s);
         (void)hipStreamSynchronize(s);
-        (void)hipFree(tmp);
+        dfree(tmp);
     } else {
         q->status = SVR_ENOMEM;
     }

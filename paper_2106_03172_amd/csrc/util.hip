@@ -33,6 +33,24 @@ LaunchEvents &pending_timing() {
 }
 
 static long g_alloc_budget = -2;  // -2: not read yet, -1: unlimited
+static thread_local hipStream_t g_alloc_stream = nullptr;
+
+AllocStream::AllocStream(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
+AllocStream::~AllocStream() { g_alloc_stream = prev; }
+
+// keep freed blocks in the device's default pool instead of returning them
+// to the driver at every synchronisation
+static void keep_pool_memory() {
+    static thread_local int done_dev = -1;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || dev == done_dev) return;
+    hipMemPool_t pool;
+    if (hipDeviceGetDefaultMemPool(&pool, dev) == hipSuccess) {
+        uint64_t big = UINT64_MAX;
+        (void)hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &big);
+    }
+    done_dev = dev;
+}
 
 hipError_t dmalloc(void **p, size_t bytes) {
     if (g_alloc_budget == -2) {
@@ -45,7 +63,12 @@ hipError_t dmalloc(void **p, size_t bytes) {
     }
     if (g_alloc_budget > 0) --g_alloc_budget;
     if (bytes == 0) bytes = 16;
-    return hipMalloc(p, bytes);
+    keep_pool_memory();
+    return hipMallocAsync(p, bytes, g_alloc_stream);
+}
+
+void dfree(void *p) {
+    if (p) (void)hipFreeAsync(p, g_alloc_stream);
 }
 
 // ---------------------------------------------------------------------------
@@ -124,6 +147,7 @@ __global__ void __launch_bounds__(SCAN_T) k_scan_apply(const int *in, int64_t n,
 }
 
 int exclusive_scan(const int *in, int64_t n, int *out, int64_t *total, hipStream_t s) {
+    AllocStream as(s);
     int nb = (int)((n + SCAN_CHUNK - 1) / SCAN_CHUNK);
     if (nb < 1) nb = 1;
     int64_t *bsum = nullptr;
@@ -133,14 +157,14 @@ int exclusive_scan(const int *in, int64_t n, int *out, int64_t *total, hipStream
     SVR_HIP(hipMemcpyAsync(total, bsum + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SVR_HIP(hipStreamSynchronize(s));
     if (*total < 0 || *total > INT32_MAX) {
-        (void)hipFree(bsum);
+        dfree(bsum);
         set_error("scan total %lld exceeds int32", (long long)*total);
         return SVR_EINVAL;
     }
     k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, bsum, out);
     SVR_HIP(hipGetLastError());
     SVR_HIP(hipStreamSynchronize(s));
-    SVR_HIP(hipFree(bsum));
+    dfree(bsum);
     return SVR_OK;
 }
 
