@@ -60,15 +60,17 @@ def traffic_from_profile(kernel_kind, wtype):
 
 
 def algorithmic_bytes(kind, A_info, nnz_t_mean, M, Mt_mean, N, Ns, wb):
-    """Bytes each launch of a kernel must move at minimum."""
+    """Bytes each launch of a kernel must move at minimum (see DESIGN.md);
+    ``ib`` index bytes (2 or 4) and ``wb`` weight bytes per non-zero."""
+    ib = A_info.index_bytes
     if kind == "forward":  # index + weight stream, row pointers, image, g, w, ratio
-        return nnz_t_mean * (4 + wb) + 4 * (Mt_mean + 1) + 4 * N + 12 * Mt_mean
+        return nnz_t_mean * (ib + wb) + 4 * (Mt_mean + 1) + 4 * N + 12 * Mt_mean
     if kind == "update":   # transposed stream, pointers, ratio, per-pixel SVREM state
-        return nnz_t_mean * (4 + wb) + 4 * (N + 1) + 4 * Mt_mean + 44 * N
+        return nnz_t_mean * (ib + wb) + 4 * (N + 1) + 4 * Mt_mean + 44 * N
     if kind == "anchor_forward":
-        return A_info.nnz * (4 + wb) + 4 * (M + 1) + 4 * N + 12 * M
+        return A_info.nnz * (ib + wb) + 4 * (M + 1) + 4 * N + 12 * M
     if kind == "anchor_table":  # all transposed rows, their pointers, ratio, f, table write
-        return A_info.nnz * (4 + wb) + 4 * (Ns * N + 1) + 4 * M + 4 * N + 4 * Ns * N
+        return A_info.nnz * (ib + wb) + 4 * (Ns * N + 1) + 4 * M + 4 * N + 4 * Ns * N
     if kind == "anchor_sum":    # table read, A^T 1 (SVRG) or s_hat/s_anc writes
         return 4 * Ns * N + 8 * N
     raise ValueError(kind)
@@ -123,7 +125,7 @@ def main():
     ap.add_argument("--eta", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("headline", "multislice", "serve"), default="headline",
+    ap.add_argument("--workload", choices=("headline", "multislice", "serve", "copy"), default="headline",
                     help="headline: the JSON line below; multislice / serve: supplementary measurements")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--persistent", action="store_true",
@@ -148,6 +150,8 @@ def main():
         return bench_multislice(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "copy":
+        return bench_copy(args)
     wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
     wb = 4 if args.wtype == "f32" else 2
     cfg = dict(datagen.CONFIG_HEADLINE)
@@ -240,11 +244,12 @@ def main():
     torch.cuda.synchronize()
     fwd_s = ev[0].elapsed_time(ev[1]) / reps / 1e3
     bwd_s = ev[1].elapsed_time(ev[2]) / reps / 1e3
-    fwd_b = inf.nnz * (4 + wb) + 4 * (M + 1) + 4 * N + 4 * M
-    bwd_b = inf.nnz * (4 + wb) + 4 * (Ns * N + 1) + 4 * N + 12 * M
+    ib = inf.index_bytes
+    fwd_b = inf.nnz * (ib + wb) + 4 * (M + 1) + 4 * N + 4 * M
+    bwd_b = inf.nnz * (ib + wb) + 4 * (Ns * N + 1) + 4 * N + 12 * M
     projector = {"forward_gbs": round(fwd_b / fwd_s / 1e9, 1), "back_gbs": round(bwd_b / bwd_s / 1e9, 1),
                  "forward_us": round(fwd_s * 1e6, 2), "back_us": round(bwd_s * 1e6, 2),
-                 "matrix_mb": round(inf.nnz * (4 + wb) / 1e6, 1)}
+                 "matrix_mb": round(inf.nnz * (ib + wb) / 1e6, 1), "index_bytes": ib}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -268,6 +273,20 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_copy(args):
+    """A plain device copy of a known size (256 MiB read + 256 MiB written per
+    launch): the calibration run for the HBM byte counters of rocprofv3."""
+    import torch
+    n = 64 << 20  # floats
+    x = torch.rand(n, device="cuda")
+    y = torch.empty_like(x)
+    for _ in range(max(1, args.steps)):
+        y.copy_(x)
+    torch.cuda.synchronize()
+    print(json.dumps({"workload": "copy", "bytes_read_per_launch": 4 * n, "bytes_written_per_launch": 4 * n,
+                      "launches": max(1, args.steps)}), flush=True)
 
 
 def bench_multislice(args):
@@ -315,10 +334,11 @@ def bench_multislice(args):
     nnz_t = float(np.mean([per_subset[t] for t in used]))
     Mt = float(np.mean([len(range(t, P.geom.n_views, Ns)) * P.geom.n_bins for t in used]))
     # algorithmic bytes: the matrix rows once, the image or ratio block once, data, state
-    byts = {"forward": nnz_t * (4 + wb) + 4 * (Mt + 1) + 4 * N * S + 12 * Mt * S,
-            "update": nnz_t * (4 + wb) + 4 * (N + 1) + 4 * Mt * S + 8 * N + 36 * N * S,
-            "anchor_forward": inf.nnz * (4 + wb) + 4 * (M + 1) + 4 * N * S + 12 * M * S,
-            "anchor_table": inf.nnz * (4 + wb) + 4 * (Ns * N + 1) + 4 * M * S + 4 * N * S + 4 * Ns * N * S,
+    ib = inf.index_bytes
+    byts = {"forward": nnz_t * (ib + wb) + 4 * (Mt + 1) + 4 * N * S + 12 * Mt * S,
+            "update": nnz_t * (ib + wb) + 4 * (N + 1) + 4 * Mt * S + 8 * N + 36 * N * S,
+            "anchor_forward": inf.nnz * (ib + wb) + 4 * (M + 1) + 4 * N * S + 12 * M * S,
+            "anchor_table": inf.nnz * (ib + wb) + 4 * (Ns * N + 1) + 4 * M * S + 4 * N * S + 4 * Ns * N * S,
             "anchor_sum": 4 * Ns * N * S + 8 * N * S}
     kernels = {}
     tot = sum(v[1] for v in kt.values())

@@ -71,9 +71,12 @@ typedef struct {
     double  arc_rad;     /* angular range, normally pi */
 } svr_geometry;
 
-/* Storage type of the matrix weights (index arrays are int32).  Products
- * are accumulated in FP64 whatever the storage type. */
+/* Storage type of the matrix weights.  Products are accumulated in FP64
+ * whatever the storage type.  Index arrays are uint16 when every pixel index
+ * and every subset-local row index fits (N <= 65536 and at most 65536 rows per
+ * subset), else int32; OR-ing SVR_W_INDEX32 into wtype forces int32. */
 enum { SVR_W_F32 = 0, SVR_W_F16 = 1, SVR_W_BF16 = 2 };
+#define SVR_W_INDEX32 0x100
 
 typedef struct svr_matrix svr_matrix;
 typedef struct svr_recon  svr_recon;
@@ -104,7 +107,8 @@ typedef struct {
     int32_t n_pixels;      /* N = nx * ny */
     int32_t max_row_nnz;   /* longest row of A */
     int32_t max_col_nnz;   /* longest transposed row of any subset */
-    int32_t wtype;
+    int32_t wtype;         /* SVR_W_F32 / F16 / BF16 */
+    int32_t index_bytes;   /* 2 (uint16) or 4 (int32) */
 } svr_matrix_info_t;
 
 /* Sizes of a built matrix; nnz_per_subset (nullable) receives n_subsets

@@ -23,6 +23,7 @@ LIB_PATH = os.environ.get("SVR_LIBRARY", os.path.join(_HERE, "_lib", "libsvr.so"
 SVR_OK, SVR_PENDING, SVR_EINVAL, SVR_ENOMEM, SVR_EDEVICE = 0, 1, -1, -2, -3
 SVR_ENOTFOUND, SVR_ENUMERIC, SVR_ECANCELLED = -4, -5, -6
 SVR_W_F32, SVR_W_F16, SVR_W_BF16 = 0, 1, 2
+SVR_W_INDEX32 = 0x100
 ALGO = dict(osem=0, svrem=1, svrg=2, saga=3, sga=4, bsrem=5, sem=6)
 PEN = dict(quadratic=0, huber=1, logcosh=2, hyperbola=3)
 PRECOND = dict(subset_frozen=0, full_frozen=1, iterate=2)
@@ -44,7 +45,7 @@ class svr_geometry(C.Structure):
 class svr_matrix_info_t(C.Structure):
     _fields_ = [("nnz", C.c_int64), ("bytes", C.c_int64), ("n_subsets", C.c_int32),
                 ("n_rows", C.c_int32), ("n_pixels", C.c_int32), ("max_row_nnz", C.c_int32),
-                ("max_col_nnz", C.c_int32), ("wtype", C.c_int32)]
+                ("max_col_nnz", C.c_int32), ("wtype", C.c_int32), ("index_bytes", C.c_int32)]
 
 
 class svr_params(C.Structure):

@@ -123,8 +123,10 @@ int check_order(const Recon *R, const int32_t *order, int32_t n) {
     return SVR_OK;
 }
 
-// ratio of all rows at the current image, then the algorithm's snapshot
-int snapshot(Recon *R, int kind, hipStream_t s) {
+// Anchor pass at the current image (ratio of all rows, then the table) fused
+// with the update of the iteration that takes it (subset t): see
+// anchor_sum_update_pixel.
+int anchor_iteration(Recon *R, int kind, UpdateArgs &u, hipStream_t s) {
     Matrix &A = *R->A;
     FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
     int rc = prof_begin(R, 2, s);
@@ -144,8 +146,13 @@ int snapshot(Recon *R, int kind, hipStream_t s) {
     rc = prof_begin(R, 3, s);
     if (!rc) rc = launch_anchor_table(A, kind, sa, s);
     if (!rc) rc = prof_end(R, s);
-    if (!rc) rc = prof_begin(R, 4, s);
-    if (!rc) rc = launch_anchor_sum(A, kind, sa, s);
+    if (rc) return rc;
+    if ((kind == UPD_SVRG || kind == UPD_SAGA) && R->k == 0 && R->p.precond != SVR_PRECOND_ITERATE) {
+        rc = launch_precond(A, R->f[R->cur], R->dpre_per_subset, R->dpre, s);
+        if (rc) return rc;
+    }
+    rc = prof_begin(R, 4, s);
+    if (!rc) rc = launch_anchor_sum_update(A, kind, sa, u, s);
     if (!rc) rc = prof_end(R, s);
     if (rc) return rc;
     R->n_snap++;
@@ -310,25 +317,6 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
     if (n > 0 && (R->p.flags & SVR_FLAG_PERSISTENT_EPOCH)) return run_epoch_persistent(R, algo, kind, order, n, s);
     for (int i = 0; i < n; ++i) {
         const int t = order[i];
-        if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG) {
-            if (R->k % ((int64_t)R->p.eta * R->Ns) == 0) {
-                rc = snapshot(R, kind, s);
-                if (rc) return rc;
-            }
-        } else if (algo == SVR_ALGO_SAGA && R->k == 0) {
-            rc = snapshot(R, kind, s);
-            if (rc) return rc;
-        }
-        if ((algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) && R->k == 0 &&
-            R->p.precond != SVR_PRECOND_ITERATE) {
-            rc = launch_precond(A, R->f[R->cur], R->dpre_per_subset, R->dpre, s);
-            if (rc) return rc;
-        }
-        FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
-        rc = prof_begin(R, 0, s);
-        if (!rc) rc = launch_forward(A, A.row_start[t], A.row_start[t + 1], 1, fa, s);
-        if (!rc) rc = prof_end(R, s);
-        if (rc) return rc;
         UpdateArgs u{};
         u.t = t;
         u.Ns = R->Ns;
@@ -348,10 +336,22 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
         u.shat_zero = (algo == SVR_ALGO_SEM && R->k == 0);
         u.pen = pen_of(R);
         if (algo == SVR_ALGO_OSEM) u.pen.beta = 0.0;
-        rc = prof_begin(R, 1, s);
-        if (!rc) rc = launch_update(A, kind, u, s);
-        if (!rc) rc = prof_end(R, s);
-        if (rc) return rc;
+        const bool anchor = ((algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG) &&
+                             R->k % ((int64_t)R->p.eta * R->Ns) == 0) ||
+                            (algo == SVR_ALGO_SAGA && R->k == 0);
+        if (anchor) {
+            rc = anchor_iteration(R, kind, u, s);
+            if (rc) return rc;
+        } else {
+            FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
+            rc = prof_begin(R, 0, s);
+            if (!rc) rc = launch_forward(A, A.row_start[t], A.row_start[t + 1], 1, fa, s);
+            if (!rc) rc = prof_end(R, s);
+            if (!rc) rc = prof_begin(R, 1, s);
+            if (!rc) rc = launch_update(A, kind, u, s);
+            if (!rc) rc = prof_end(R, s);
+            if (rc) return rc;
+        }
         R->cur = 1 - R->cur;
         if (algo != SVR_ALGO_OSEM) R->k++;
     }
@@ -376,12 +376,16 @@ int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t
     int rc = check_geom(geom);
     if (rc) return rc;
     SVR_REQUIRE(n_subsets >= 1 && n_subsets <= geom->n_views, "n_subsets must be in [1, n_views]");
-    SVR_REQUIRE(wtype == SVR_W_F32 || wtype == SVR_W_F16 || wtype == SVR_W_BF16, "unknown wtype %d", wtype);
+    const int wbase = wtype & 0xff;
+    SVR_REQUIRE((wtype & ~(0xff | SVR_W_INDEX32)) == 0 &&
+                    (wbase == SVR_W_F32 || wbase == SVR_W_F16 || wbase == SVR_W_BF16),
+                "unknown wtype %d", wtype);
     svr_matrix *A = new (std::nothrow) svr_matrix();
     SVR_REQUIRE(A, "host allocation failed");
     A->geom = *geom;
     A->Ns = n_subsets;
-    A->wtype = wtype;
+    A->wtype = wbase;
+    A->idx16 = (wtype & SVR_W_INDEX32) ? 0 : 1;
     (void)hipGetDevice(&A->device);
     hipStream_t s = (hipStream_t)stream;
     if (mu_dev) {
@@ -417,6 +421,7 @@ int svr_matrix_info(const svr_matrix *A, svr_matrix_info_t *info, int64_t *nnz_p
     info->max_row_nnz = A->max_row_nnz;
     info->max_col_nnz = A->max_col_nnz;
     info->wtype = A->wtype;
+    info->index_bytes = A->ibytes();
     if (nnz_per_subset)
         for (int t = 0; t < A->Ns; ++t) nnz_per_subset[t] = A->nnz_sub[t];
     return SVR_OK;
@@ -438,12 +443,25 @@ int svr_matrix_export(const svr_matrix *A, int32_t which, int32_t *ptr, int32_t 
     SVR_HIP(hipSetDevice(A->device));
     const int64_t nnz = A->nnz;
     const int wb = A->wbytes();
+    const int ib = A->ibytes();
+    auto idx_host = [&](const void *dev, std::vector<int> &out) -> int {
+        out.resize(nnz);
+        if (ib == 4) {
+            SVR_HIP(hipMemcpy(out.data(), dev, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+        } else {
+            std::vector<uint16_t> t(nnz);
+            SVR_HIP(hipMemcpy(t.data(), dev, sizeof(uint16_t) * nnz, hipMemcpyDeviceToHost));
+            for (int64_t i = 0; i < nnz; ++i) out[i] = t[i];
+        }
+        return SVR_OK;
+    };
     if (which == 0) {
-        std::vector<int> rp(A->M + 1), rs(A->M), col(nnz);
+        std::vector<int> rp(A->M + 1), rs(A->M), col;
         std::vector<char> v(nnz * wb);
         SVR_HIP(hipMemcpy(rp.data(), A->d_row_ptr, sizeof(int) * (A->M + 1), hipMemcpyDeviceToHost));
         SVR_HIP(hipMemcpy(rs.data(), A->d_row_sino, sizeof(int) * A->M, hipMemcpyDeviceToHost));
-        SVR_HIP(hipMemcpy(col.data(), A->d_col, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+        int rc = idx_host(A->d_col, col);
+        if (rc) return rc;
         SVR_HIP(hipMemcpy(v.data(), A->d_val, (size_t)wb * nnz, hipMemcpyDeviceToHost));
         std::vector<int> inv(A->M);
         for (int r = 0; r < A->M; ++r) inv[rs[r]] = r;
@@ -460,7 +478,12 @@ int svr_matrix_export(const svr_matrix *A, int32_t which, int32_t *ptr, int32_t 
     } else {
         const int64_t NT = (int64_t)A->Ns * A->N;
         if (ptr) SVR_HIP(hipMemcpy(ptr, A->d_ptrT, sizeof(int) * (NT + 1), hipMemcpyDeviceToHost));
-        if (idx) SVR_HIP(hipMemcpy(idx, A->d_rowT, sizeof(int) * nnz, hipMemcpyDeviceToHost));
+        if (idx) {
+            std::vector<int> r;
+            int rc = idx_host(A->d_rowT, r);
+            if (rc) return rc;
+            memcpy(idx, r.data(), sizeof(int) * nnz);
+        }
         if (val) {
             std::vector<char> v(nnz * wb);
             SVR_HIP(hipMemcpy(v.data(), A->d_valT, (size_t)wb * nnz, hipMemcpyDeviceToHost));

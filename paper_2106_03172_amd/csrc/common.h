@@ -80,17 +80,32 @@ struct Matrix {
     int *d_row_start = nullptr;     // device copy of row_start
     int *d_row_sino = nullptr;      // M: natural sinogram index of each subset-ordered row
     int *d_row_ptr = nullptr;       // M+1
-    int *d_col = nullptr;           // nnz
+    void *d_col = nullptr;          // nnz pixel indices (int32, or uint16 when idx16)
     void *d_val = nullptr;          // nnz (float / _Float16 / bf16_t)
     int *d_ptrT = nullptr;          // Ns*N+1
-    int *d_rowT = nullptr;          // nnz (subset-local row)
+    void *d_rowT = nullptr;         // nnz subset-local rows (int32, or uint16 when idx16)
     void *d_valT = nullptr;         // nnz
+    int idx16 = 0;                  // indices stored as uint16 (N and every subset's rows <= 65536)
     float *d_sens_t = nullptr;      // Ns*N
     double *d_sens = nullptr;       // N
     int64_t bytes = 0;
     int wbytes() const { return wtype == SVR_W_F32 ? 4 : 2; }
+    int ibytes() const { return idx16 ? 2 : 4; }
     int rows_of(int t) const { return row_start[t + 1] - row_start[t]; }
 };
+
+// Calls f(WT{}, IT{}) with the matrix's weight and index storage types.
+template <class F>
+inline int with_types(const Matrix &A, F &&f) {
+    if (A.idx16) {
+        if (A.wtype == SVR_W_F32) return f(float{}, uint16_t{});
+        if (A.wtype == SVR_W_F16) return f(_Float16{}, uint16_t{});
+        return f(bf16_t{}, uint16_t{});
+    }
+    if (A.wtype == SVR_W_F32) return f(float{}, int{});
+    if (A.wtype == SVR_W_F16) return f(_Float16{}, int{});
+    return f(bf16_t{}, int{});
+}
 
 // ---------------------------------------------------------------------------
 // kernel launchers (defined next to their kernels)
@@ -183,13 +198,17 @@ struct SnapArgs {
 };
 int launch_anchor_table(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
 int launch_anchor_sum(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
+// anchor sums fused with the update of the iteration that takes the anchor
+int launch_anchor_sum_update(const Matrix &A, int kind, const SnapArgs &a, const UpdateArgs &u, hipStream_t s);
 
 // persistent epoch kernel (persist.hip): a whole epoch call in one
 // cooperative launch
 struct EpochArgs {
-    const int *row_ptr, *col;
+    const int *row_ptr;
+    const void *col;
     const void *val;
-    const int *ptrT, *rowT;
+    const int *ptrT;
+    const void *rowT;
     const void *valT;
     const int *row_start;
     const float *sens_t;

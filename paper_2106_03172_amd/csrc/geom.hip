@@ -201,6 +201,11 @@ __global__ void k_sens(int Ns, int N, const int *ptrT, const WT *valT, float *se
     sens[n] = tot;
 }
 
+__global__ void k_narrow(const int *src, int64_t n, uint16_t *dst) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) dst[i] = (uint16_t)src[i];
+}
+
 // stats[0] = longest row, stats[1] = longest transposed row, stats[2 + t] =
 // row_ptr at the first row of subset t (t = 0..Ns)
 __global__ void k_row_stats(int M, const int *row_ptr, int *stats) {
@@ -239,22 +244,25 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     if (rc) { cleanup(); return rc; }
     A.nnz = nnz;
     WT *val = nullptr, *valT = nullptr;
-    SVR_HIP(dalloc(&A.d_col, nnz));
+    int *col = nullptr, *rowT = nullptr;
+    SVR_HIP(dalloc(&col, nnz));
     SVR_HIP(dalloc(&val, nnz));
-    SVR_HIP(dalloc(&A.d_rowT, nnz));
+    SVR_HIP(dalloc(&rowT, nnz));
     SVR_HIP(dalloc(&valT, nnz));
+    A.d_col = col;
+    A.d_rowT = rowT;
     SVR_HIP(dalloc(&cnt, NT));
     SVR_HIP(dalloc(&A.d_ptrT, NT + 1));
     SVR_HIP(dalloc(&A.d_sens_t, NT));
     SVR_HIP(dalloc(&A.d_sens, N));
     A.d_val = val;
     A.d_valT = valT;
-    k_siddon_fill<WT><<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, A.d_row_ptr, mu, A.d_col, val);
+    k_siddon_fill<WT><<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, A.d_row_ptr, mu, col, val);
     k_row_stats<<<gM, T, 0, s>>>(M, A.d_row_ptr, stats);
     k_subset_offsets<<<(Ns + 1 + T - 1) / T, T, 0, s>>>(Ns, A.d_row_start, A.d_row_ptr, stats);
     // transposed rows per subset
     SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
-    k_col_count<<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, A.d_col, cnt);
+    k_col_count<<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt);
     k_max_count<<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, cnt, stats);
     SVR_HIP(hipGetLastError());
     int64_t nnzT = 0;
@@ -262,9 +270,9 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     if (rc) { cleanup(); return rc; }
     if (nnzT != nnz) { cleanup(); set_error("transpose count mismatch"); return SVR_EDEVICE; }
     SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
-    k_fill_T<WT><<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, A.d_col,
-                                  val, A.d_ptrT, cnt, A.d_rowT, valT);
-    k_sort_T<WT><<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, A.d_rowT, valT);
+    k_fill_T<WT><<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
+                                  val, A.d_ptrT, cnt, rowT, valT);
+    k_sort_T<WT><<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, rowT, valT);
     k_sens<WT><<<(N + T - 1) / T, T, 0, s>>>(Ns, N, A.d_ptrT, valT, A.d_sens_t, A.d_sens);
     SVR_HIP(hipGetLastError());
     std::vector<int> h(Ns + 3);
@@ -275,7 +283,26 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     A.nnz_sub.assign(Ns, 0);
     for (int t = 0; t < Ns; ++t) A.nnz_sub[t] = (int64_t)h[2 + t + 1] - h[2 + t];
     cleanup();
-    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + 2 * nnz + NT + 1 + (Ns + 1)) +
+    // 16-bit indices when every pixel index and every subset-local row fits
+    int max_rows = 0;
+    for (int t = 0; t < Ns; ++t) max_rows = std::max(max_rows, A.rows_of(t));
+    if (A.idx16 && N <= 65536 && max_rows <= 65536 && nnz > 0) {
+        uint16_t *c16 = nullptr, *r16 = nullptr;
+        SVR_HIP(dalloc(&c16, nnz));
+        SVR_HIP(dalloc(&r16, nnz));
+        const unsigned gn = (unsigned)((nnz + T - 1) / T);
+        k_narrow<<<gn, T, 0, s>>>(col, nnz, c16);
+        k_narrow<<<gn, T, 0, s>>>(rowT, nnz, r16);
+        SVR_HIP(hipGetLastError());
+        dfree(col);
+        dfree(rowT);
+        A.d_col = c16;
+        A.d_rowT = r16;
+        SVR_HIP(hipStreamSynchronize(s));
+    } else {
+        A.idx16 = 0;
+    }
+    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + NT + 1 + (Ns + 1)) + (int64_t)A.ibytes() * 2 * nnz +
               (int64_t)A.wbytes() * 2 * nnz + (int64_t)sizeof(float) * NT + (int64_t)sizeof(double) * N;
     return SVR_OK;
 }

@@ -58,8 +58,8 @@ __device__ inline double wave_sum(double v) {
 }
 
 // (A f)_r: the lanes of a wavefront stride over row r's non-zeros, FP64 products
-template <typename WT>
-__device__ inline double row_dot(const int *__restrict__ row_ptr, const int *__restrict__ col,
+template <typename WT, typename IT>
+__device__ inline double row_dot(const int *__restrict__ row_ptr, const IT *__restrict__ col,
                                  const WT *__restrict__ val, const float *__restrict__ f, int r, int lane) {
     const int beg = row_ptr[r], end = row_ptr[r + 1];
     double acc = 0.0;
@@ -69,7 +69,7 @@ __device__ inline double row_dot(const int *__restrict__ row_ptr, const int *__r
 #pragma unroll
         for (int u = 0; u < FWD_U; ++u) {
             const int i = base + 64 * u;
-            c[u] = i < end ? col[i] : -1;
+            c[u] = i < end ? (int)col[i] : -1;
             v[u] = i < end ? load_w(val[i]) : 0.0f;
         }
 #pragma unroll
@@ -88,8 +88,8 @@ __device__ inline float em_ratio(float g, double yb) {
 
 // Forward row r with the EM ratio written to ratio[r]; every lane of the
 // wavefront calls it with the same r.
-template <typename WT>
-__device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const int *__restrict__ col,
+template <typename WT, typename IT>
+__device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const IT *__restrict__ col,
                                      const WT *__restrict__ val, const float *__restrict__ f,
                                      const float *__restrict__ g, const float *__restrict__ w,
                                      float *__restrict__ ratio, int r, int lane) {
@@ -101,8 +101,8 @@ __device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const int 
 
 // sum over transposed row q of val * y[row], BP_G lanes per row; every lane
 // of the group returns the same value
-template <typename WT>
-__device__ inline double bp_group(const int *__restrict__ ptrT, const int *__restrict__ rowT,
+template <typename WT, typename IT>
+__device__ inline double bp_group(const int *__restrict__ ptrT, const IT *__restrict__ rowT,
                                   const WT *__restrict__ valT, int64_t q, const float *__restrict__ y,
                                   int lig) {
     const int beg = ptrT[q], end = ptrT[q + 1];
@@ -113,7 +113,7 @@ __device__ inline double bp_group(const int *__restrict__ ptrT, const int *__res
 #pragma unroll
         for (int u = 0; u < BP_U; ++u) {
             const int i = base + BP_G * u;
-            rr[u] = i < end ? rowT[i] : -1;
+            rr[u] = i < end ? (int)rowT[i] : -1;
             v[u] = i < end ? load_w(valT[i]) : 0.0f;
         }
 #pragma unroll

@@ -74,11 +74,13 @@ __device__ inline bool grid_barrier(unsigned *gs, unsigned &gen_local, int *abor
     return *abort_lds == 0;
 }
 
-template <int KIND, typename WT>
+template <int KIND, typename WT, typename IT>
 __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
     __shared__ int abort_lds;
     const WT *val = (const WT *)e.val;
     const WT *valT = (const WT *)e.valT;
+    const IT *col = (const IT *)e.col;
+    const IT *rowT = (const IT *)e.rowT;
     const int nthreads = gridDim.x * blockDim.x;
     const int gtid = blockIdx.x * blockDim.x + threadIdx.x;
     const int lane = threadIdx.x & 63;
@@ -96,7 +98,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
         const bool anchor = vr_anchor ? (k % ((long long)e.eta * Ns) == 0) : (KIND == UPD_SAGA && k == 0);
         if (anchor) {
             for (int r = gwave; r < e.M; r += nwaves)
-                fwd_ratio_row(e.row_ptr, e.col, val, f, e.g, e.w, e.ratio, r, lane);
+                fwd_ratio_row(e.row_ptr, col, val, f, e.g, e.w, e.ratio, r, lane);
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
             SnapArgs sa{};
             sa.ratio_all = e.ratio;
@@ -109,7 +111,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
             sa.Q = e.Q;
             sa.pen = e.pen;
             for (long long q = ggroup; q < (long long)Ns * N; q += ngroups)
-                anchor_entry<KIND, WT>(e.ptrT, e.rowT, valT, e.row_start, Ns, N, sa, q, lig);
+                anchor_entry<KIND, WT, IT>(e.ptrT, rowT, valT, e.row_start, Ns, N, sa, q, lig);
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
             for (int n = gtid; n < N; n += nthreads) anchor_sum_pixel<KIND>(e.sens, Ns, N, sa, n);
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
@@ -123,7 +125,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
         {
             const int r0 = e.row_start[t], r1 = e.row_start[t + 1];
             for (int r = r0 + gwave; r < r1; r += nwaves)
-                fwd_ratio_row(e.row_ptr, e.col, val, f, e.g, e.w, e.ratio, r, lane);
+                fwd_ratio_row(e.row_ptr, col, val, f, e.g, e.w, e.ratio, r, lane);
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
             UpdateArgs u{};
             u.t = t;
@@ -142,7 +144,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
             u.shat_zero = (KIND == UPD_SEM && k == 0);
             u.pen = e.pen;
             for (int n = ggroup; n < N; n += ngroups)
-                update_pixel<KIND, WT>(e.ptrT, e.rowT, valT, e.sens_t, e.sens, N, u, n, lig);
+                update_pixel<KIND, WT, IT>(e.ptrT, rowT, valT, e.sens_t, e.sens, N, u, n, lig);
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
         }
         cur ^= 1;
@@ -152,9 +154,9 @@ aborted:
     if (gtid == 0) e.status[0] = 1;
 }
 
-template <int KIND, typename WT>
+template <int KIND, typename WT, typename IT>
 static int launch_epoch_t(const EpochArgs &e, hipStream_t s, int *grid_cache) {
-    auto kern = k_epoch<KIND, WT>;
+    auto kern = k_epoch<KIND, WT, IT>;
     if (*grid_cache <= 0) {
         int dev = 0, cus = 0, per_cu = 0;
         SVR_HIP(hipGetDevice(&dev));
@@ -180,11 +182,9 @@ static int launch_epoch_t(const EpochArgs &e, hipStream_t s, int *grid_cache) {
 
 template <int KIND>
 static int launch_epoch_k(const Matrix &A, const EpochArgs &e, hipStream_t s, int *grid_cache) {
-    switch (A.wtype) {
-        case SVR_W_F32: return launch_epoch_t<KIND, float>(e, s, grid_cache);
-        case SVR_W_F16: return launch_epoch_t<KIND, _Float16>(e, s, grid_cache);
-        default: return launch_epoch_t<KIND, bf16_t>(e, s, grid_cache);
-    }
+    return with_types(A, [&](auto w, auto i) {
+        return launch_epoch_t<KIND, decltype(w), decltype(i)>(e, s, grid_cache);
+    });
 }
 
 int launch_epoch(const Matrix &A, int kind, const EpochArgs &e, hipStream_t s, int *grid_cache) {

@@ -22,14 +22,18 @@ __device__ inline float osem_math(float f, double b, float st) {
 
 // SVREM statistic recursion (Sec. 2.3, eq. tempsvrem) and penalised M-step
 // (Sec. 3): returns f+ and the new running statistic in *sh_out
-__device__ inline float svrem_math(int Ns, double alpha, double beta, float f, double b, double sh0, float tab,
-                                   double sanc, double sn, double D, double E, double *sh_out) {
-    const float tau = tau_of(Ns, f, b);
+__device__ inline float svrem_math_tau(double alpha, double beta, float f, float tau, double sh0, float tab,
+                                       double sanc, double sn, double D, double E, double *sh_out) {
     const double sh = (1.0 - alpha) * sh0 + alpha * (((double)tau - (double)tab) + sanc);
     *sh_out = sh;
     const double bb = beta * D;
     const double cc = (beta * (double)f * D + beta * E) - sn;
     return (float)mstep_root(sh, bb, cc, sn);
+}
+
+__device__ inline float svrem_math(int Ns, double alpha, double beta, float f, double b, double sh0, float tab,
+                                   double sanc, double sn, double D, double E, double *sh_out) {
+    return svrem_math_tau(alpha, beta, f, tau_of(Ns, f, b), sh0, tab, sanc, sn, D, E, sh_out);
 }
 
 __device__ inline double precond_of(const UpdateArgs &u, int64_t q, int n, float f, float st) {
@@ -39,8 +43,8 @@ __device__ inline double precond_of(const UpdateArgs &u, int64_t q, int n, float
 
 // One pixel's fused back-projection and update; the BP_G lanes of the
 // pixel's group call it together.
-template <int KIND, typename WT>
-__device__ inline void update_pixel(const int *__restrict__ ptrT, const int *__restrict__ rowT,
+template <int KIND, typename WT, typename IT>
+__device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__restrict__ rowT,
                                     const WT *__restrict__ valT, const float *__restrict__ sens_t,
                                     const double *__restrict__ sens, int N, const UpdateArgs &u, int n, int lig) {
     const int64_t q = (int64_t)u.t * N + n;
@@ -98,8 +102,8 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const int *__r
     u.f_out[n] = out;
 }
 
-template <int KIND, typename WT>
-__device__ inline void anchor_entry(const int *__restrict__ ptrT, const int *__restrict__ rowT,
+template <int KIND, typename WT, typename IT>
+__device__ inline void anchor_entry(const int *__restrict__ ptrT, const IT *__restrict__ rowT,
                                     const WT *__restrict__ valT, const int *__restrict__ row_start, int Ns, int N,
                                     const SnapArgs &a, int64_t q, int lig) {
     const int t = (int)(q / N), n = (int)(q - (int64_t)t * N);
@@ -126,6 +130,43 @@ __device__ inline void anchor_sum_pixel(const double *__restrict__ sens, int Ns,
     } else {
         a.Q[n] = sum;
     }
+}
+
+// The anchor sums of pixel n followed by the update of the iteration that
+// takes the anchor.  There f = f_anc, so the subset term of subset u.t is the
+// table entry itself (the same gather and the same expression computed it),
+// and the update needs no forward projection or gather of its own:
+//   SVREM: tau_t(f) - tau_anc_t = 0;  SVRG: q_t(f) - q_anc_t = 0;
+//   SAGA (table fill at k = 0): q_t(f) - q_t = 0 and Q is unchanged.
+template <int KIND>
+__device__ inline void anchor_sum_update_pixel(const float *__restrict__ sens_t, const double *__restrict__ sens,
+                                               int Ns, int N, const SnapArgs &a, const UpdateArgs &u, int n) {
+    anchor_sum_pixel<KIND>(sens, Ns, N, a, n);
+    const int64_t q = (int64_t)u.t * N + n;
+    const PenaltyArgs &p = u.pen;
+    const float f = u.f[n];
+    const float tab = u.table[q];
+    float out;
+    if (KIND == UPD_SVREM) {
+        double D = 0.0, E = 0.0;
+        if (p.beta > 0.0) surrogate_at(u.f, n, p, D, E);
+        double sh;
+        out = svrem_math_tau(u.alpha, p.beta, f, tab, u.s_hat[n], tab, u.s_anc[n], sens[n], D, E, &sh);
+        u.s_hat[n] = sh;
+    } else {
+        const float st = sens_t[q];
+        double dir;
+        if (KIND == UPD_SVRG) {
+            dir = ((double)tab - (double)tab) + u.g_tilde[n];
+        } else {
+            const double Qn = u.Q[n];
+            dir = ((double)tab - (double)tab) + (Qn - sens[n]) / (double)u.Ns;
+            u.Q[n] = Qn + ((double)tab - (double)tab);
+        }
+        const double d = precond_of(u, q, n, f, st);
+        out = (float)fmax(0.0, (double)f + (u.alpha * d) * dir);
+    }
+    u.f_out[n] = out;
 }
 
 // frozen preconditioner entry i: d_t[n] = f0[n] / (A_t^T 1)[n] (per subset,

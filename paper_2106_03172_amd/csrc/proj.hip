@@ -16,9 +16,9 @@
 
 namespace svr {
 
-template <int MODE, typename WT>
+template <int MODE, typename WT, typename IT>
 __global__ void __launch_bounds__(FWD_THREADS)
-k_forward(const int *__restrict__ row_ptr, const int *__restrict__ col, const WT *__restrict__ val,
+k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
           const int *__restrict__ row_sino, int r0, int r1, FwdArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
@@ -59,22 +59,13 @@ k_forward(const int *__restrict__ row_ptr, const int *__restrict__ col, const WT
 
 template <int MODE>
 static int launch_forward_t(const Matrix &A, int r0, int r1, const FwdArgs &a, hipStream_t s, int nb) {
-    hipError_t e;
-    switch (A.wtype) {
-        case SVR_W_F32:
-            e = launch_k(k_forward<MODE, float>, nb, FWD_THREADS, s, A.d_row_ptr, A.d_col,
-                         (const float *)A.d_val, A.d_row_sino, r0, r1, a);
-            break;
-        case SVR_W_F16:
-            e = launch_k(k_forward<MODE, _Float16>, nb, FWD_THREADS, s, A.d_row_ptr, A.d_col,
-                         (const _Float16 *)A.d_val, A.d_row_sino, r0, r1, a);
-            break;
-        default:
-            e = launch_k(k_forward<MODE, bf16_t>, nb, FWD_THREADS, s, A.d_row_ptr, A.d_col,
-                         (const bf16_t *)A.d_val, A.d_row_sino, r0, r1, a);
-    }
-    SVR_HIP(e);
-    return SVR_OK;
+    return with_types(A, [&](auto w, auto i) {
+        using WT = decltype(w);
+        using IT = decltype(i);
+        SVR_HIP(launch_k(k_forward<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_col,
+                         (const WT *)A.d_val, A.d_row_sino, r0, r1, a));
+        return SVR_OK;
+    });
 }
 
 int launch_forward(const Matrix &A, int r0, int r1, int mode, const FwdArgs &a, hipStream_t s, int *nbo) {
@@ -88,9 +79,9 @@ int launch_forward(const Matrix &A, int r0, int r1, int mode, const FwdArgs &a, 
 }
 
 // x[n] = sum over subset t's transposed row (t = -1: all subsets, in t order)
-template <typename WT>
+template <typename WT, typename IT>
 __global__ void __launch_bounds__(BP_THREADS)
-k_backproject(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *__restrict__ valT,
+k_backproject(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
               const int *__restrict__ row_start, int Ns, int N, int t, const float *__restrict__ y_sub,
               float *__restrict__ x) {
     const int gid = blockIdx.x * BP_THREADS + threadIdx.x;
@@ -109,21 +100,13 @@ k_backproject(const int *__restrict__ ptrT, const int *__restrict__ rowT, const 
 int launch_backproject(const Matrix &A, int t, const float *y_sub, float *x, hipStream_t s) {
     const int nb = (int)(((int64_t)A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
     const float *ysub = (t >= 0) ? y_sub + A.row_start[t] : y_sub;
-    switch (A.wtype) {
-        case SVR_W_F32:
-            k_backproject<float><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const float *)A.d_valT,
-                                                          A.d_row_start, A.Ns, A.N, t, ysub, x);
-            break;
-        case SVR_W_F16:
-            k_backproject<_Float16><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const _Float16 *)A.d_valT,
-                                                             A.d_row_start, A.Ns, A.N, t, ysub, x);
-            break;
-        default:
-            k_backproject<bf16_t><<<nb, BP_THREADS, 0, s>>>(A.d_ptrT, A.d_rowT, (const bf16_t *)A.d_valT,
-                                                           A.d_row_start, A.Ns, A.N, t, ysub, x);
-    }
-    SVR_HIP(hipGetLastError());
-    return SVR_OK;
+    return with_types(A, [&](auto w, auto i) {
+        using WT = decltype(w);
+        using IT = decltype(i);
+        SVR_HIP(launch_k(k_backproject<WT, IT>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+                         (const WT *)A.d_valT, A.d_row_start, A.Ns, A.N, t, ysub, x));
+        return SVR_OK;
+    });
 }
 
 // penalty value partials: one FP64 partial per block of 256 pixels

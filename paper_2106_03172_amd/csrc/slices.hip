@@ -29,13 +29,13 @@ __device__ inline float rl_f(float v, int j) { return __int_as_float(__builtin_a
 
 // sum over the entries [beg, end) of idx/val of val * y[idx*S + s]; wave-uniform
 // beg/end; lanes with act = false load nothing and return 0
-template <typename WT>
-__device__ inline double ms_dot(const int *__restrict__ idx, const WT *__restrict__ val, int beg, int end,
+template <typename WT, typename IT>
+__device__ inline double ms_dot(const IT *__restrict__ idx, const WT *__restrict__ val, int beg, int end,
                                 const float *__restrict__ y, int S, int s, bool act, int lane) {
     double acc = 0.0;
     for (int base = beg; base < end; base += 64) {
         const int i = base + lane;
-        const int cv = i < end ? idx[i] : 0;
+        const int cv = i < end ? (int)idx[i] : 0;
         const float av = i < end ? load_w(val[i]) : 0.0f;
         const int cnt = min(64, end - base);
         for (int j = 0; j < cnt; j += MS_U) {
@@ -90,9 +90,9 @@ __device__ inline double penalty_share_at_ms(const float *X, int n, int s, int S
 }
 
 // ---- forward: MODE 1 ratio, MODE 2 log-likelihood partials -------------------
-template <int MODE, typename WT>
+template <int MODE, typename WT, typename IT>
 __global__ void __launch_bounds__(MS_THREADS)
-k_ms_forward(const int *__restrict__ row_ptr, const int *__restrict__ col, const WT *__restrict__ val, int r0,
+k_ms_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val, int r0,
              int r1, int S, int nch, const float *__restrict__ X, const float *__restrict__ g,
              const float *__restrict__ w, float *__restrict__ ratio, double *__restrict__ part, int *bad) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -131,9 +131,9 @@ k_ms_forward(const int *__restrict__ row_ptr, const int *__restrict__ col, const
 }
 
 // ---- fused back-projection + OSEM / SVREM update -----------------------------
-template <int KIND, typename WT>
+template <int KIND, typename WT, typename IT>
 __global__ void __launch_bounds__(MS_THREADS)
-k_ms_update(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *__restrict__ valT,
+k_ms_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
             const float *__restrict__ sens_t, const double *__restrict__ sens, int N, int S, int nch, int axial,
             UpdateArgs u) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -172,9 +172,9 @@ k_ms_update(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT
 }
 
 // ---- SVREM anchor: tau table and FP64 sums -----------------------------------
-template <typename WT>
+template <typename WT, typename IT>
 __global__ void __launch_bounds__(MS_THREADS)
-k_ms_anchor_table(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *__restrict__ valT,
+k_ms_anchor_table(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
                   const int *__restrict__ row_start, int Ns, int N, int S, int nch, const float *__restrict__ ratio,
                   const float *__restrict__ X, float *__restrict__ table) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -248,63 +248,49 @@ int ms_forward(const Matrix &A, int r0, int r1, int mode, int S, const float *X,
     const unsigned nb = blocks_for((int64_t)(r1 - r0) * nch);
     if (nb_out) *nb_out = (int)nb;
     if (nb == 0) return SVR_OK;
-    hipError_t e;
-#define SVR_MS_FWD(M_, T_)                                                                                     \
-    e = launch_k(k_ms_forward<M_, T_>, nb, MS_THREADS, s, A.d_row_ptr, A.d_col, (const T_ *)A.d_val, r0, r1, S, \
-                 nch, X, g, w, ratio, part, bad)
-    if (mode == 1) {
-        if (A.wtype == SVR_W_F32) SVR_MS_FWD(1, float);
-        else if (A.wtype == SVR_W_F16) SVR_MS_FWD(1, _Float16);
-        else SVR_MS_FWD(1, bf16_t);
-    } else {
-        if (A.wtype == SVR_W_F32) SVR_MS_FWD(2, float);
-        else if (A.wtype == SVR_W_F16) SVR_MS_FWD(2, _Float16);
-        else SVR_MS_FWD(2, bf16_t);
-    }
-#undef SVR_MS_FWD
-    SVR_HIP(e);
-    return SVR_OK;
+    return with_types(A, [&](auto wv, auto iv) {
+        using WT = decltype(wv);
+        using IT = decltype(iv);
+        if (mode == 1)
+            SVR_HIP(launch_k(k_ms_forward<1, WT, IT>, nb, MS_THREADS, s, A.d_row_ptr, (const IT *)A.d_col,
+                             (const WT *)A.d_val, r0, r1, S, nch, X, g, w, ratio, part, bad));
+        else
+            SVR_HIP(launch_k(k_ms_forward<2, WT, IT>, nb, MS_THREADS, s, A.d_row_ptr, (const IT *)A.d_col,
+                             (const WT *)A.d_val, r0, r1, S, nch, X, g, w, ratio, part, bad));
+        return SVR_OK;
+    });
 }
 
 int ms_update(const Matrix &A, int kind, int S, int axial, const UpdateArgs &u, hipStream_t s) {
     const int nch = nchunks(S);
     const unsigned nb = blocks_for((int64_t)A.N * nch);
-    hipError_t e;
-#define SVR_MS_UPD(K_, T_)                                                                                     \
-    e = launch_k(k_ms_update<K_, T_>, nb, MS_THREADS, s, A.d_ptrT, A.d_rowT, (const T_ *)A.d_valT, A.d_sens_t, \
-                 A.d_sens, A.N, S, nch, axial, u)
-    if (kind == UPD_OSEM) {
-        if (A.wtype == SVR_W_F32) SVR_MS_UPD(UPD_OSEM, float);
-        else if (A.wtype == SVR_W_F16) SVR_MS_UPD(UPD_OSEM, _Float16);
-        else SVR_MS_UPD(UPD_OSEM, bf16_t);
-    } else if (kind == UPD_SVREM) {
-        if (A.wtype == SVR_W_F32) SVR_MS_UPD(UPD_SVREM, float);
-        else if (A.wtype == SVR_W_F16) SVR_MS_UPD(UPD_SVREM, _Float16);
-        else SVR_MS_UPD(UPD_SVREM, bf16_t);
-    } else {
+    if (kind != UPD_OSEM && kind != UPD_SVREM) {
         set_error("slice stacks support OSEM and SVREM updates");
         return SVR_EINVAL;
     }
-#undef SVR_MS_UPD
-    SVR_HIP(e);
-    return SVR_OK;
+    return with_types(A, [&](auto wv, auto iv) {
+        using WT = decltype(wv);
+        using IT = decltype(iv);
+        if (kind == UPD_OSEM)
+            SVR_HIP(launch_k(k_ms_update<UPD_OSEM, WT, IT>, nb, MS_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+                             (const WT *)A.d_valT, A.d_sens_t, A.d_sens, A.N, S, nch, axial, u));
+        else
+            SVR_HIP(launch_k(k_ms_update<UPD_SVREM, WT, IT>, nb, MS_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+                             (const WT *)A.d_valT, A.d_sens_t, A.d_sens, A.N, S, nch, axial, u));
+        return SVR_OK;
+    });
 }
 
 int ms_anchor_table(const Matrix &A, int S, const float *ratio_all, const float *X, float *table, hipStream_t s) {
     const int nch = nchunks(S);
     const unsigned nb = blocks_for((int64_t)A.Ns * A.N * nch);
-    hipError_t e;
-    if (A.wtype == SVR_W_F32)
-        e = launch_k(k_ms_anchor_table<float>, nb, MS_THREADS, s, A.d_ptrT, A.d_rowT, (const float *)A.d_valT,
-                     A.d_row_start, A.Ns, A.N, S, nch, ratio_all, X, table);
-    else if (A.wtype == SVR_W_F16)
-        e = launch_k(k_ms_anchor_table<_Float16>, nb, MS_THREADS, s, A.d_ptrT, A.d_rowT,
-                     (const _Float16 *)A.d_valT, A.d_row_start, A.Ns, A.N, S, nch, ratio_all, X, table);
-    else
-        e = launch_k(k_ms_anchor_table<bf16_t>, nb, MS_THREADS, s, A.d_ptrT, A.d_rowT, (const bf16_t *)A.d_valT,
-                     A.d_row_start, A.Ns, A.N, S, nch, ratio_all, X, table);
-    SVR_HIP(e);
-    return SVR_OK;
+    return with_types(A, [&](auto wv, auto iv) {
+        using WT = decltype(wv);
+        using IT = decltype(iv);
+        SVR_HIP(launch_k(k_ms_anchor_table<WT, IT>, nb, MS_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+                         (const WT *)A.d_valT, A.d_row_start, A.Ns, A.N, S, nch, ratio_all, X, table));
+        return SVR_OK;
+    });
 }
 
 int ms_anchor_sum(const Matrix &A, int S, const float *table, double *s_anc, double *s_hat, int init_shat,

@@ -25,35 +25,26 @@
 
 namespace svr {
 
-template <int KIND, typename WT>
+template <int KIND, typename WT, typename IT>
 __global__ void __launch_bounds__(BP_THREADS)
-k_update(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *__restrict__ valT,
+k_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
          const float *__restrict__ sens_t, const double *__restrict__ sens, int N, UpdateArgs u) {
     const int gid = blockIdx.x * BP_THREADS + threadIdx.x;
     const int n = gid / BP_G, lig = gid % BP_G;
     if (n >= N) return;
-    update_pixel<KIND, WT>(ptrT, rowT, valT, sens_t, sens, N, u, n, lig);
+    update_pixel<KIND, WT, IT>(ptrT, rowT, valT, sens_t, sens, N, u, n, lig);
 }
 
 template <int KIND>
 static int launch_update_k(const Matrix &A, const UpdateArgs &u, hipStream_t s) {
     const int nb = (int)(((int64_t)A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
-    hipError_t e;
-    switch (A.wtype) {
-        case SVR_W_F32:
-            e = launch_k(k_update<KIND, float>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT, (const float *)A.d_valT,
-                         A.d_sens_t, A.d_sens, A.N, u);
-            break;
-        case SVR_W_F16:
-            e = launch_k(k_update<KIND, _Float16>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT,
-                         (const _Float16 *)A.d_valT, A.d_sens_t, A.d_sens, A.N, u);
-            break;
-        default:
-            e = launch_k(k_update<KIND, bf16_t>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT, (const bf16_t *)A.d_valT,
-                         A.d_sens_t, A.d_sens, A.N, u);
-    }
-    SVR_HIP(e);
-    return SVR_OK;
+    return with_types(A, [&](auto w, auto i) {
+        using WT = decltype(w);
+        using IT = decltype(i);
+        SVR_HIP(launch_k(k_update<KIND, WT, IT>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+                         (const WT *)A.d_valT, A.d_sens_t, A.d_sens, A.N, u));
+        return SVR_OK;
+    });
 }
 
 int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s) {
@@ -72,15 +63,15 @@ int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s)
 // ---- anchor pass ---------------------------------------------------------------
 // table kernel: one BP_G-lane group per (subset, pixel), the same gather and
 // the same tau / q expressions as the iteration kernel
-template <int KIND, typename WT>
+template <int KIND, typename WT, typename IT>
 __global__ void __launch_bounds__(BP_THREADS)
-k_anchor_table(const int *__restrict__ ptrT, const int *__restrict__ rowT, const WT *__restrict__ valT,
+k_anchor_table(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
                const int *__restrict__ row_start, int Ns, int N, SnapArgs a) {
     const int64_t gid = (int64_t)blockIdx.x * BP_THREADS + threadIdx.x;
     const int64_t q = gid / BP_G;
     const int lig = (int)(gid % BP_G);
     if (q >= (int64_t)Ns * N) return;
-    anchor_entry<KIND, WT>(ptrT, rowT, valT, row_start, Ns, N, a, q, lig);
+    anchor_entry<KIND, WT, IT>(ptrT, rowT, valT, row_start, Ns, N, a, q, lig);
 }
 
 template <int KIND>
@@ -92,24 +83,43 @@ k_anchor_sum(const double *__restrict__ sens, int Ns, int N, SnapArgs a) {
 }
 
 template <int KIND>
-static int launch_anchor_table_k(const Matrix &A, const SnapArgs &a, hipStream_t s) {
-    const int nb = (int)(((int64_t)A.Ns * A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
+__global__ void __launch_bounds__(256)
+k_anchor_sum_update(const float *__restrict__ sens_t, const double *__restrict__ sens, int Ns, int N, SnapArgs a,
+                    UpdateArgs u) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    anchor_sum_update_pixel<KIND>(sens_t, sens, Ns, N, a, u, n);
+}
+
+int launch_anchor_sum_update(const Matrix &A, int kind, const SnapArgs &a, const UpdateArgs &u, hipStream_t s) {
+    const int nb = (A.N + 255) / 256;
     hipError_t e;
-    switch (A.wtype) {
-        case SVR_W_F32:
-            e = launch_k(k_anchor_table<KIND, float>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT,
-                         (const float *)A.d_valT, A.d_row_start, A.Ns, A.N, a);
+    switch (kind) {
+        case UPD_SVREM:
+            e = launch_k(k_anchor_sum_update<UPD_SVREM>, nb, 256, s, A.d_sens_t, A.d_sens, A.Ns, A.N, a, u);
             break;
-        case SVR_W_F16:
-            e = launch_k(k_anchor_table<KIND, _Float16>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT,
-                         (const _Float16 *)A.d_valT, A.d_row_start, A.Ns, A.N, a);
+        case UPD_SVRG:
+            e = launch_k(k_anchor_sum_update<UPD_SVRG>, nb, 256, s, A.d_sens_t, A.d_sens, A.Ns, A.N, a, u);
             break;
-        default:
-            e = launch_k(k_anchor_table<KIND, bf16_t>, nb, BP_THREADS, s, A.d_ptrT, A.d_rowT,
-                         (const bf16_t *)A.d_valT, A.d_row_start, A.Ns, A.N, a);
+        case UPD_SAGA:
+            e = launch_k(k_anchor_sum_update<UPD_SAGA>, nb, 256, s, A.d_sens_t, A.d_sens, A.Ns, A.N, a, u);
+            break;
+        default: set_error("no anchor pass for kind %d", kind); return SVR_EINVAL;
     }
     SVR_HIP(e);
     return SVR_OK;
+}
+
+template <int KIND>
+static int launch_anchor_table_k(const Matrix &A, const SnapArgs &a, hipStream_t s) {
+    const int nb = (int)(((int64_t)A.Ns * A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
+    return with_types(A, [&](auto w, auto i) {
+        using WT = decltype(w);
+        using IT = decltype(i);
+        SVR_HIP(launch_k(k_anchor_table<KIND, WT, IT>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+                         (const WT *)A.d_valT, A.d_row_start, A.Ns, A.N, a));
+        return SVR_OK;
+    });
 }
 
 int launch_anchor_table(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s) {
