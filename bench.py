@@ -166,6 +166,9 @@ def main():
     build_s = time.perf_counter() - tb
     inf, per_subset = A.info()
     log(f"nnz = {inf.nnz}, build {build_s:.3f} s")
+    tuning = A.tune()
+    log(f"autotuned run lengths: forward {tuning[0]} rows/wavefront ({tuning[2]:.1f} us), "
+        f"anchor table {tuning[1]} rows/group ({tuning[3]:.1f} us)")
 
     f0 = np.ones((1, N), dtype=np.float32)
     flags = pkg.binding.FLAG_PERSISTENT_EPOCH if args.persistent else 0
@@ -265,6 +268,7 @@ def main():
                                f"alpha={args.alpha}, eta={args.eta}; {args.wtype} weights and FP32 iterate, "
                                f"FP64 products, sums and statistics",
                    "epochs_per_step": epochs_per_step, "nnz": int(inf.nnz), "build_s": round(build_s, 4),
+                   "tuning": {"fwd_rows_per_wave": tuning[0], "bp_rows_per_group": tuning[1]},
                    "objective_after": phi, "parallelism": "single GPU",
                    "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                                for k, v in kernels.items()},

@@ -89,7 +89,7 @@ typedef struct svr_server svr_server;
  * (one per pixel, entries by ascending view and bin) for a gather-only
  * back-projection.  Also computes the sensitivities A_t^T 1 and A^T 1.
  *   geom        : scanner; nx, ny, n_views, n_bins >= 1, sizes > 0
- *   n_subsets   : 1 <= n_subsets <= n_views
+ *   n_subsets   : 1 <= n_subsets <= n_views, n_subsets * nx * ny < 2^31
  *   wtype       : SVR_W_F32 / SVR_W_F16 / SVR_W_BF16 (round to nearest even)
  *   mu_dev      : optional attenuation map (nx*ny floats, 1/mm, >= 0) or NULL;
  *                 every weight of ray m is multiplied by exp(-sum_n a_mn mu_n)
@@ -128,6 +128,37 @@ int svr_matrix_export(const svr_matrix *A, int32_t which, int32_t *ptr, int32_t 
 int svr_sensitivity(const svr_matrix *A, int32_t subset, double *out_dev, void *stream);
 
 void svr_matrix_destroy(svr_matrix *A);
+
+/* Run lengths of the passes over the whole matrix (the anchor pass of
+ * eq. tempsvrem / eq. svrg_update / eq. saga_update, the objective, and the
+ * projectors over all subsets).  A wavefront that owns a run of rows keeps the
+ * next row's loads in flight while it sums the current one; the run length
+ * never changes a row's arithmetic, so every result is bitwise the same under
+ * any tuning.  0 means "chosen from the sizes and the device's compute units".
+ * A forward pass over no more rows than the device holds wavefronts at once
+ * (the per-subset passes at the usual sizes) always runs one row per
+ * wavefront. */
+typedef struct {
+    int32_t fwd_rows_per_wave;   /* rows of A per wavefront, 0..63 */
+    int32_t bp_rows_per_group;   /* (subset, pixel) transposed rows per lane group, 0..1024 */
+    double  fwd_us, bp_us;       /* svr_matrix_tune: measured duration of the chosen runs */
+} svr_tuning_t;
+
+/* Run lengths in use for the whole-matrix passes (0 resolved to the
+ * size-based choice); fwd_us and bp_us are 0.  Host-only. */
+int svr_matrix_get_tuning(const svr_matrix *A, svr_tuning_t *t);
+
+/* Sets the run lengths (0 = size-based).  Errors: SVR_EINVAL out of range.
+ * Not to be called while work that uses A is being enqueued from another
+ * thread. */
+int svr_matrix_set_tuning(svr_matrix *A, const svr_tuning_t *t);
+
+/* Autotuner: times the candidate run lengths of the whole-matrix forward
+ * pass and of the anchor table on A itself, the two kernels alternating as in
+ * an anchor pass (HIP events on `stream`, median of 9 pairs, synthetic
+ * operands), keeps the fastest in A and reports it in out (nullable).  Allocates about 4(2M + N + Ns*N) bytes for the duration of
+ * the call and synchronises.  Errors: SVR_ENOMEM, SVR_EDEVICE (A unchanged). */
+int svr_matrix_tune(svr_matrix *A, void *stream, svr_tuning_t *out);
 
 /* ---- projectors ---------------------------------------------------------- */
 

@@ -64,6 +64,11 @@ class svr_kernel_times_t(C.Structure):
     _fields_ = [("launches", C.c_int64 * 6), ("total_ms", C.c_double * 6)]
 
 
+class svr_tuning_t(C.Structure):
+    _fields_ = [("fwd_rows_per_wave", C.c_int32), ("bp_rows_per_group", C.c_int32),
+                ("fwd_us", C.c_double), ("bp_us", C.c_double)]
+
+
 class svr_serve_config(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("n_streams", C.c_int32)]
 
@@ -90,6 +95,9 @@ _SIGS = {
     "svr_matrix_export": ([_VP, _I32, _VP, _VP, _VP], C.c_int),
     "svr_sensitivity": ([_VP, _I32, _VP, _VP], C.c_int),
     "svr_matrix_destroy": ([_VP], None),
+    "svr_matrix_get_tuning": ([_VP, C.POINTER(svr_tuning_t)], C.c_int),
+    "svr_matrix_set_tuning": ([_VP, C.POINTER(svr_tuning_t)], C.c_int),
+    "svr_matrix_tune": ([_VP, _VP, C.POINTER(svr_tuning_t)], C.c_int),
     "svr_project": ([_VP, _I32, _VP, _I32, _VP, _VP], C.c_int),
     "svr_backproject": ([_VP, _I32, _VP, _I32, _VP, _VP], C.c_int),
     "svr_recon_create": ([_VP, _VP, _VP, _VP, _I32, C.POINTER(svr_params), _VP, C.POINTER(_VP)], C.c_int),
@@ -251,6 +259,22 @@ class SystemMatrix:
         out = torch.empty(self.N, dtype=torch.float64, device="cuda")
         _check(lib().svr_sensitivity(self.h, int(subset), _dev(out, "float64"), _stream(stream)))
         return out
+
+    def tuning(self):
+        """Effective run lengths of the whole-matrix passes: (rows per wavefront, rows per lane group)."""
+        t = svr_tuning_t()
+        _check(lib().svr_matrix_get_tuning(self.h, C.byref(t)))
+        return int(t.fwd_rows_per_wave), int(t.bp_rows_per_group)
+
+    def set_tuning(self, fwd_rows_per_wave: int = 0, bp_rows_per_group: int = 0):
+        t = svr_tuning_t(int(fwd_rows_per_wave), int(bp_rows_per_group), 0.0, 0.0)
+        _check(lib().svr_matrix_set_tuning(self.h, C.byref(t)))
+
+    def tune(self, stream=None):
+        """Autotunes the run lengths on the device; returns (fwd, bp, fwd_us, bp_us)."""
+        t = svr_tuning_t()
+        _check(lib().svr_matrix_tune(self.h, _stream(stream), C.byref(t)))
+        return int(t.fwd_rows_per_wave), int(t.bp_rows_per_group), float(t.fwd_us), float(t.bp_us)
 
     def project(self, x, subset: int = -1, y=None, stream=None):
         import torch

@@ -376,6 +376,7 @@ int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t
     int rc = check_geom(geom);
     if (rc) return rc;
     SVR_REQUIRE(n_subsets >= 1 && n_subsets <= geom->n_views, "n_subsets must be in [1, n_views]");
+    SVR_REQUIRE((int64_t)n_subsets * geom->nx * geom->ny < (1ll << 31), "n_subsets * nx * ny must be below 2^31");
     const int wbase = wtype & 0xff;
     SVR_REQUIRE((wtype & ~(0xff | SVR_W_INDEX32)) == 0 &&
                     (wbase == SVR_W_F32 || wbase == SVR_W_F16 || wbase == SVR_W_BF16),
@@ -387,6 +388,8 @@ int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t
     A->wtype = wbase;
     A->idx16 = (wtype & SVR_W_INDEX32) ? 0 : 1;
     (void)hipGetDevice(&A->device);
+    if (hipDeviceGetAttribute(&A->cus, hipDeviceAttributeMultiprocessorCount, A->device) != hipSuccess || A->cus < 1)
+        A->cus = 1;
     hipStream_t s = (hipStream_t)stream;
     if (mu_dev) {
         AllocStream as(s);
@@ -597,7 +600,7 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     const int64_t NT = (int64_t)Ns * N * S;
     const int64_t MS_ = (int64_t)M * S, NS_ = (int64_t)N * S;
     const int64_t nch = (S + 63) / 64;
-    R->n_part = (int)std::max<int64_t>(std::max<int64_t>((M * nch + 3) / 4, (NS_ + 255) / 256), (M + 3) / 4) + 1;
+    R->n_part = (int)std::max<int64_t>(std::max<int64_t>((M * nch + 3) / 4, (NS_ + 255) / 256), M) + 1;
     hipError_t e = hipSuccess;
     auto chk = [&](hipError_t x) { if (x != hipSuccess && e == hipSuccess) e = x; };
     chk(dalloc(&R->g, MS_));

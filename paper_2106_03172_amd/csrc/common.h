@@ -89,6 +89,9 @@ struct Matrix {
     float *d_sens_t = nullptr;      // Ns*N
     double *d_sens = nullptr;       // N
     int64_t bytes = 0;
+    int cus = 0;                    // compute units of the device (sizes the whole-matrix runs)
+    int run_fwd = 0;                // rows per wavefront in whole-matrix forward passes (0: by size)
+    int run_bp = 0;                 // transposed rows per lane group in whole-matrix back-projections (0: by size)
     int wbytes() const { return wtype == SVR_W_F32 ? 4 : 2; }
     int ibytes() const { return idx16 ? 2 : 4; }
     int rows_of(int t) const { return row_start[t + 1] - row_start[t]; }
@@ -117,12 +120,13 @@ int build_matrix(Matrix &A, const float *mu_dev, hipStream_t s);
 // forward projection of rows [r0, r1) of the subset-ordered matrix.
 //  mode 0: y[row_sino[r]] = (A f)_r                           (plain projection)
 //  mode 1: ratio[r] = g[r] / ((A f)_r + w[r])   (0 if g == 0 or ybar <= 0)
-//  mode 2: partial log-likelihood sums into part[blockIdx], ratio not written
+//  mode 2: log-likelihood term of row r into part[r - r0], ratio not written
+//          (*n_blocks_out receives the number of terms, r1 - r0)
 struct FwdArgs {
     const float *f;       // image, N floats
     const float *g, *w;   // subset-ordered data (modes 1, 2)
     float *out;           // mode 0: natural-order sinogram; mode 1: ratio (subset order)
-    double *part;         // mode 2: one partial per block
+    double *part;         // mode 2: one term per row
     int *bad;             // mode 2: set when g > 0 and ybar <= 0
 };
 int launch_forward(const Matrix &A, int r0, int r1, int mode, const FwdArgs &a, hipStream_t s,

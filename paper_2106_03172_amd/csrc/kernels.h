@@ -57,26 +57,79 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
-// (A f)_r: the lanes of a wavefront stride over row r's non-zeros, FP64 products
+// One batch of a sparse row held in registers: lane j of an L-lane team
+// holds entries base + j + L*u (u < U) of the row ending at `end`, index -1
+// past the end.  Every sparse sum in the library walks its rows batch by
+// batch through this struct, so a row's products are always added in the
+// same order, whichever kernel (and whichever pipelining) computes it.
+template <int L, int U, typename WT, typename IT>
+struct RowBatch {
+    int c[U];
+    float v[U];
+    __device__ inline void load(const IT *__restrict__ idx, const WT *__restrict__ val, int base, int end) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = base + L * u;
+            c[u] = i < end ? (int)idx[i] : -1;
+            v[u] = i < end ? load_w(val[i]) : 0.0f;
+        }
+    }
+    __device__ inline void gather(const float *__restrict__ x, float (&xv)[U]) const {
+#pragma unroll
+        for (int u = 0; u < U; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : 0.0f;
+    }
+    // acc + v*x with one FP64 fused multiply-add: the product of two FP32
+    // values is exact in FP64, so this rounds exactly like a multiply
+    // followed by an add
+    __device__ inline double fma(const float (&xv)[U], double acc) const {
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+            if (c[u] >= 0) acc = __builtin_fma((double)v[u], (double)xv[u], acc);
+        return acc;
+    }
+};
+
+// the batches of a row after its first, starting at lane offset `first`
+template <int L, int U, typename WT, typename IT>
+__device__ inline double row_rest(const IT *__restrict__ idx, const WT *__restrict__ val, const float *__restrict__ x,
+                                  int first, int end, double acc) {
+    for (int base = first + L * U; base < end; base += L * U) {
+        RowBatch<L, U, WT, IT> b;
+        float xv[U];
+        b.load(idx, val, base, end);
+        b.gather(x, xv);
+        acc = b.fma(xv, acc);
+    }
+    return acc;
+}
+
+// sum over entries [beg, end) of val * x[idx], lanes of an L-lane team
+// striding the row; per-lane partial (reduce across the team afterwards)
+template <int L, int U, typename WT, typename IT>
+__device__ inline double row_partial(const IT *__restrict__ idx, const WT *__restrict__ val,
+                                     const float *__restrict__ x, int beg, int end, int lane) {
+    RowBatch<L, U, WT, IT> b;
+    float xv[U];
+    b.load(idx, val, beg + lane, end);
+    b.gather(x, xv);
+    return row_rest<L, U, WT, IT>(idx, val, x, beg + lane, end, b.fma(xv, 0.0));
+}
+
+// (A f)_r: the lanes of a wavefront stride over row r's non-zeros, FP64
+// products.  Written as one loop (not through RowBatch) because this is the
+// per-iteration path, where the peeled first batch of row_partial costs a few
+// percent; the entries, their order and the operations are row_partial's.
 template <typename WT, typename IT>
 __device__ inline double row_dot(const int *__restrict__ row_ptr, const IT *__restrict__ col,
                                  const WT *__restrict__ val, const float *__restrict__ f, int r, int lane) {
     const int beg = row_ptr[r], end = row_ptr[r + 1];
     double acc = 0.0;
     for (int base = beg + lane; base < end; base += 64 * FWD_U) {
-        int c[FWD_U];
-        float v[FWD_U], x[FWD_U];
-#pragma unroll
-        for (int u = 0; u < FWD_U; ++u) {
-            const int i = base + 64 * u;
-            c[u] = i < end ? (int)col[i] : -1;
-            v[u] = i < end ? load_w(val[i]) : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < FWD_U; ++u) x[u] = c[u] >= 0 ? f[c[u]] : 0.0f;
-#pragma unroll
-        for (int u = 0; u < FWD_U; ++u)
-            if (c[u] >= 0) acc = acc + (double)v[u] * (double)x[u];
+        RowBatch<64, FWD_U, WT, IT> b;
+        float xv[FWD_U];
+        b.load(col, val, base, end);
+        b.gather(f, xv);
+        acc = b.fma(xv, acc);
     }
     return acc;
 }
@@ -99,6 +152,11 @@ __device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const IT *
     if (lane == 0) ratio[r] = em_ratio(gv, acc + (double)wv);
 }
 
+__device__ inline double group_sum(double acc) {
+    for (int o = BP_G / 2; o > 0; o >>= 1) acc = acc + __shfl_xor(acc, o, 64);
+    return acc;
+}
+
 // sum over transposed row q of val * y[row], BP_G lanes per row; every lane
 // of the group returns the same value
 template <typename WT, typename IT>
@@ -107,23 +165,82 @@ __device__ inline double bp_group(const int *__restrict__ ptrT, const IT *__rest
                                   int lig) {
     const int beg = ptrT[q], end = ptrT[q + 1];
     double acc = 0.0;
-    for (int base = beg + lig; base < end; base += BP_G * BP_U) {
-        int rr[BP_U];
-        float v[BP_U], x[BP_U];
-#pragma unroll
-        for (int u = 0; u < BP_U; ++u) {
-            const int i = base + BP_G * u;
-            rr[u] = i < end ? (int)rowT[i] : -1;
-            v[u] = i < end ? load_w(valT[i]) : 0.0f;
-        }
-#pragma unroll
-        for (int u = 0; u < BP_U; ++u) x[u] = rr[u] >= 0 ? y[rr[u]] : 0.0f;
-#pragma unroll
-        for (int u = 0; u < BP_U; ++u)
-            if (rr[u] >= 0) acc = acc + (double)v[u] * (double)x[u];
+    for (int base = beg + lig; base < end; base += BP_G * BP_U) {  // as row_dot
+        RowBatch<BP_G, BP_U, WT, IT> b;
+        float xv[BP_U];
+        b.load(rowT, valT, base, end);
+        b.gather(y, xv);
+        acc = b.fma(xv, acc);
     }
-    for (int o = BP_G / 2; o > 0; o >>= 1) acc = acc + __shfl_xor(acc, o, 64);
-    return acc;
+    return group_sum(acc);
+}
+
+// ---- pipelined row runs -------------------------------------------------------
+// A wavefront that owns a run of rows [ra, ra + nr) of A walks them with the
+// first index/weight batch of row i+1 in flight while it gathers and sums
+// row i (the run's row pointers are loaded up front, one per lane), so each
+// row costs about one memory latency instead of three.  `fin(i, acc)` gets
+// the wavefront-reduced sum of row ra + i; nr <= 63.
+template <typename WT, typename IT, class Fin>
+__device__ inline void fwd_run(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
+                               const float *__restrict__ f, int ra, int nr, int lane, Fin fin) {
+    const int rp = lane <= nr ? row_ptr[ra + lane] : 0;
+    int beg = __builtin_amdgcn_readlane(rp, 0), end = __builtin_amdgcn_readlane(rp, 1);
+    RowBatch<64, FWD_U, WT, IT> cur;
+    cur.load(col, val, beg + lane, end);
+    for (int i = 0; i < nr; ++i) {
+        float xv[FWD_U];
+        cur.gather(f, xv);
+        int nbeg = 0, nend = 0;
+        RowBatch<64, FWD_U, WT, IT> nxt;
+        if (i + 1 < nr) {
+            nbeg = __builtin_amdgcn_readlane(rp, i + 1);
+            nend = __builtin_amdgcn_readlane(rp, i + 2);
+            nxt.load(col, val, nbeg + lane, nend);
+        }
+        double acc = cur.fma(xv, 0.0);
+        acc = row_rest<64, FWD_U, WT, IT>(col, val, f, beg + lane, end, acc);
+        fin(i, wave_sum(acc));
+        beg = nbeg;
+        end = nend;
+        cur = nxt;
+    }
+}
+
+// A BP_G-lane group that owns the transposed rows q(0), q(1), ..., q(n-1)
+// walks them three deep: row pointers (and one per-row operand) of step
+// i+2, the index/weight batch of step i+1 and the gathers of step i are in
+// flight together.  `seq(i, q, y, aux)` names step i's row, the vector it
+// gathers from and loads the per-row operand `aux` (false: no row, the sum
+// is 0); `fin(i, b, aux)` gets the group-reduced sum.  Every lane of the
+// group takes the same steps.
+template <typename WT, typename IT, class Seq, class Fin>
+__device__ inline void bp_run(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
+                              int n, int lig, Seq seq, Fin fin) {
+    int64_t q;
+    const float *y0 = nullptr, *y1 = nullptr;
+    int b0 = 0, e0 = 0, b1 = 0, e1 = 0;
+    float a0 = 0.0f, a1 = 0.0f;
+    if (n > 0 && seq(0, q, y0, a0)) { b0 = ptrT[q]; e0 = ptrT[q + 1]; }
+    if (n > 1 && seq(1, q, y1, a1)) { b1 = ptrT[q]; e1 = ptrT[q + 1]; }
+    RowBatch<BP_G, BP_U, WT, IT> cur;
+    cur.load(rowT, valT, b0 + lig, e0);
+    for (int i = 0; i < n; ++i) {
+        float xv[BP_U];
+        cur.gather(y0, xv);
+        RowBatch<BP_G, BP_U, WT, IT> nxt;
+        nxt.load(rowT, valT, b1 + lig, e1);
+        const float *y2 = nullptr;
+        int b2 = 0, e2 = 0;
+        float a2 = 0.0f;
+        if (i + 2 < n && seq(i + 2, q, y2, a2)) { b2 = ptrT[q]; e2 = ptrT[q + 1]; }
+        double acc = cur.fma(xv, 0.0);
+        acc = row_rest<BP_G, BP_U, WT, IT>(rowT, valT, y0, b0 + lig, e0, acc);
+        fin(i, group_sum(acc), a0);
+        b0 = b1; e0 = e1; y0 = y1; a0 = a1;
+        b1 = b2; e1 = e2; y1 = y2; a1 = a2;
+        cur = nxt;
+    }
 }
 
 }  // namespace svr

@@ -102,18 +102,25 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
     u.f_out[n] = out;
 }
 
+// table entry (subset t, pixel n) from its back-projected sum b and f = f_n;
+// the group's first lane writes it
+template <int KIND>
+__device__ inline void anchor_finish(const SnapArgs &a, int Ns, int64_t q, int n, float f, double b) {
+    const PenaltyArgs &p = a.pen;
+    double gr = 0.0;
+    if (KIND != UPD_SVREM && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
+    a.table[q] = (KIND == UPD_SVREM) ? tau_of(Ns, f, b) : q_of(b, gr, p.beta, Ns);
+}
+
 template <int KIND, typename WT, typename IT>
 __device__ inline void anchor_entry(const int *__restrict__ ptrT, const IT *__restrict__ rowT,
                                     const WT *__restrict__ valT, const int *__restrict__ row_start, int Ns, int N,
                                     const SnapArgs &a, int64_t q, int lig) {
     const int t = (int)(q / N), n = (int)(q - (int64_t)t * N);
     const float f = a.f[n];
-    const PenaltyArgs &p = a.pen;
-    double gr = 0.0;
-    if (KIND != UPD_SVREM && lig == 0 && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
     const double b = bp_group(ptrT, rowT, valT, q, a.ratio_all + row_start[t], lig);
     if (lig != 0) return;
-    a.table[q] = (KIND == UPD_SVREM) ? tau_of(Ns, f, b) : q_of(b, gr, p.beta, Ns);
+    anchor_finish<KIND>(a, Ns, q, n, f, b);
 }
 
 // FP64 sums over t in increasing order

@@ -8,6 +8,11 @@
 //
 // Back-projection: BP_G lanes per pixel over that pixel's transposed row of
 // subset t, FP64 products, fixed butterfly reduction.
+//
+// Passes over many more rows than the device holds wavefronts (the whole
+// matrix) give each wavefront a run of consecutive rows and pipeline them
+// (fwd_run, bp_run): per row the arithmetic is the one-row code's, so the
+// results do not depend on the run length.
 #include <cmath>
 
 #include "common.h"
@@ -16,6 +21,18 @@
 
 namespace svr {
 
+// g log ybar - ybar of one row (0 log 0 = 0); flags g > 0 with ybar <= 0
+__device__ inline double loglik_term(float g, double yb, int *bad) {
+    if (g > 0.0f) {
+        if (yb > 0.0) return (double)g * log(yb) - yb;
+        atomicOr(bad, 1);
+        return 0.0;
+    }
+    return -yb;
+}
+
+// one wavefront per row; mode 2 writes the row's log-likelihood term to
+// part[r - r0] (summed afterwards in a fixed order)
 template <int MODE, typename WT, typename IT>
 __global__ void __launch_bounds__(FWD_THREADS)
 k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
@@ -27,58 +44,85 @@ k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT 
         if (r < r1) fwd_ratio_row(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane);
         return;
     }
-    double acc = 0.0;
-    if (r < r1) acc = row_dot(row_ptr, col, val, a.f, r, lane);
-    acc = wave_sum(acc);
-    if (MODE == 0) {
-        if (lane == 0 && r < r1) a.out[row_sino[r]] = (float)acc;
-    } else {
-        __shared__ double part[FWD_ROWS_PER_BLOCK];
-        if (lane == 0) {
-            double term = 0.0;
-            if (r < r1) {
-                const double yb = acc + (double)a.w[r];
-                const float gv = a.g[r];
-                if (gv > 0.0f) {
-                    if (yb > 0.0) term = (double)gv * log(yb) - yb;
-                    else { atomicOr(a.bad, 1); term = 0.0; }
-                } else {
-                    term = -yb;
-                }
-            }
-            part[wv] = term;
-        }
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            double s = 0.0;
-            for (int i = 0; i < FWD_ROWS_PER_BLOCK; ++i) s = s + part[i];
-            a.part[blockIdx.x] = s;
-        }
+    if (r >= r1) return;  // wave-uniform
+    const double acc = wave_sum(row_dot(row_ptr, col, val, a.f, r, lane));
+    if (lane != 0) return;
+    if (MODE == 0) a.out[row_sino[r]] = (float)acc;
+    else a.part[r - r0] = loglik_term(a.g[r], acc + (double)a.w[r], a.bad);
+}
+
+// rows [ra, ra + R) per wavefront, pipelined; the run's per-row operands and
+// results are held one per lane, so they are read and written coalesced
+template <int MODE, typename WT, typename IT>
+__global__ void __launch_bounds__(FWD_THREADS)
+k_forward_run(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
+              const int *__restrict__ row_sino, int r0, int r1, int R, FwdArgs a) {
+    const int lane = threadIdx.x & 63;
+    const int wv = threadIdx.x >> 6;
+    const int64_t ra64 = (int64_t)r0 + ((int64_t)blockIdx.x * FWD_ROWS_PER_BLOCK + wv) * R;
+    const int nr = ra64 < r1 ? (int)min((int64_t)R, (int64_t)r1 - ra64) : 0;
+    const int ra = nr > 0 ? (int)ra64 : r0;
+    float gl = 0.0f, wl = 0.0f;
+    int sl = 0;
+    if (lane < nr) {
+        if (MODE == 0) sl = row_sino[ra + lane];
+        else { gl = a.g[ra + lane]; wl = a.w[ra + lane]; }
     }
+    if (nr == 0) return;  // wave-uniform
+    float outv = 0.0f;
+    double term = 0.0;
+    fwd_run<WT, IT>(row_ptr, col, val, a.f, ra, nr, lane, [&](int i, double acc) {
+        if (lane != i) return;
+        if (MODE == 0) outv = (float)acc;
+        else if (MODE == 1) outv = em_ratio(gl, acc + (double)wl);
+        else term = loglik_term(gl, acc + (double)wl, a.bad);
+    });
+    if (lane >= nr) return;
+    if (MODE == 0) a.out[sl] = outv;
+    else if (MODE == 1) a.out[ra + lane] = outv;
+    else a.part[ra - r0 + lane] = term;
+}
+
+// Rows per wavefront for a pass over `rows` rows: 1 while the rows fit in the
+// wavefronts the device holds at once (8 per SIMD; the per-subset passes),
+// else the tuned run length, by default 2 (the run kernel holds two rows'
+// operands in registers, which costs occupancy; longer runs lose more than
+// the overlap gains at the sizes measured).
+int forward_run_length(const Matrix &A, int rows) {
+    const int64_t slots = (int64_t)std::max(A.cus, 1) * 32;
+    if (rows <= slots) return 1;
+    return A.run_fwd > 0 ? std::min(A.run_fwd, 63) : 2;
 }
 
 template <int MODE>
-static int launch_forward_t(const Matrix &A, int r0, int r1, const FwdArgs &a, hipStream_t s, int nb) {
+static int launch_forward_t(const Matrix &A, int r0, int r1, int R, const FwdArgs &a, hipStream_t s, int nb) {
     return with_types(A, [&](auto w, auto i) {
         using WT = decltype(w);
         using IT = decltype(i);
-        SVR_HIP(launch_k(k_forward<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_col,
-                         (const WT *)A.d_val, A.d_row_sino, r0, r1, a));
+        if (R == 1)
+            SVR_HIP(launch_k(k_forward<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_col,
+                             (const WT *)A.d_val, A.d_row_sino, r0, r1, a));
+        else
+            SVR_HIP(launch_k(k_forward_run<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_col,
+                             (const WT *)A.d_val, A.d_row_sino, r0, r1, R, a));
         return SVR_OK;
     });
 }
 
 int launch_forward(const Matrix &A, int r0, int r1, int mode, const FwdArgs &a, hipStream_t s, int *nbo) {
     const int rows = r1 - r0;
-    const int nb = rows > 0 ? (rows + FWD_ROWS_PER_BLOCK - 1) / FWD_ROWS_PER_BLOCK : 0;
-    if (nbo) *nbo = nb;
+    const int R = rows > 0 ? forward_run_length(A, rows) : 1;
+    const int64_t waves = rows > 0 ? ((int64_t)rows + R - 1) / R : 0;
+    const int nb = (int)((waves + FWD_ROWS_PER_BLOCK - 1) / FWD_ROWS_PER_BLOCK);
+    if (nbo) *nbo = mode == 2 ? rows : nb;
     if (nb == 0) return SVR_OK;
-    if (mode == 0) return launch_forward_t<0>(A, r0, r1, a, s, nb);
-    if (mode == 1) return launch_forward_t<1>(A, r0, r1, a, s, nb);
-    return launch_forward_t<2>(A, r0, r1, a, s, nb);
+    if (mode == 0) return launch_forward_t<0>(A, r0, r1, R, a, s, nb);
+    if (mode == 1) return launch_forward_t<1>(A, r0, r1, R, a, s, nb);
+    return launch_forward_t<2>(A, r0, r1, R, a, s, nb);
 }
 
-// x[n] = sum over subset t's transposed row (t = -1: all subsets, in t order)
+// x[n] = sum over subset t's transposed row (t = -1: all subsets, in t order,
+// pipelined over t)
 template <typename WT, typename IT>
 __global__ void __launch_bounds__(BP_THREADS)
 k_backproject(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
@@ -86,14 +130,16 @@ k_backproject(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const W
               float *__restrict__ x) {
     const int gid = blockIdx.x * BP_THREADS + threadIdx.x;
     const int n = gid / BP_G, lig = gid % BP_G;
-    if (n >= N) return;
+    if (n >= N) return;  // whole groups leave together
     double acc = 0.0;
-    if (t >= 0) {
-        acc = bp_group(ptrT, rowT, valT, (int64_t)t * N + n, y_sub, lig);
-    } else {
-        for (int tt = 0; tt < Ns; ++tt)
-            acc = acc + bp_group(ptrT, rowT, valT, (int64_t)tt * N + n, y_sub + row_start[tt], lig);
-    }
+    bp_run<WT, IT>(ptrT, rowT, valT, t >= 0 ? 1 : Ns, lig,
+                   [&](int i, int64_t &q, const float *&y, float &) {
+                       const int tt = t >= 0 ? t : i;
+                       q = (int64_t)tt * N + n;
+                       y = t >= 0 ? y_sub : y_sub + row_start[tt];
+                       return true;
+                   },
+                   [&](int, double b, float) { acc = t >= 0 ? b : acc + b; });
     if (lig == 0) x[n] = (float)acc;
 }
 

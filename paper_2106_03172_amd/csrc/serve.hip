@@ -76,7 +76,7 @@ Footprint footprint_estimate(const svr_serve_request &r) {
     const int wb = r.wtype == SVR_W_F32 ? 4 : 2;
     Footprint fp;
     fp.matrix = 2 * nnz * (4 + wb) + 4 * (2 * M + Ns * N) + 4 * Ns * N + 8 * N;
-    fp.rest = 4 * (3 * M + 2 * N) + 8 * (2 * N) + 4 * Ns * N + 8 * (M / 4 + N / 256 + 8) + 4 * (2 * M + N);
+    fp.rest = 4 * (3 * M + 2 * N) + 8 * (2 * N) + 4 * Ns * N + 8 * (M + N / 256 + 8) + 4 * (2 * M + N);
     return fp;
 }
 

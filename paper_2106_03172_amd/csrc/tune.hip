@@ -1,0 +1,163 @@
+// Autotuner for the run lengths of the whole-matrix passes: rows of A per
+// wavefront in the forward projection over every row (the anchor pass, the
+// objective, svr_project over all subsets) and (subset, pixel) rows per lane
+// group in the anchor table.  Each candidate is timed with HIP events on the
+// matrix itself, on synthetic operands (image 1, data 1, background 0.1); the
+// fastest is kept in the matrix.  The run length changes only which
+// wavefront computes a row, never the row's arithmetic, so every result is
+// bitwise the same under any tuning.
+#include <algorithm>
+#include <vector>
+
+#include "common.h"
+#include "kernels.h"
+
+namespace svr {
+int forward_run_length(const Matrix &A, int rows);
+int table_run_length(const Matrix &A);
+
+namespace {
+
+__global__ void k_fill(float *x, int64_t n, float v) {
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n) x[i] = v;
+}
+
+int fill(float *x, int64_t n, float v, hipStream_t s) {
+    k_fill<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(x, n, v);
+    SVR_HIP(hipGetLastError());
+    return SVR_OK;
+}
+
+int tune(Matrix &A, hipStream_t s, svr_tuning_t *out) {
+    AllocStream as(s);
+    float *f = nullptr, *g = nullptr, *w = nullptr, *ratio = nullptr, *table = nullptr;
+    hipEvent_t e0 = nullptr, e1 = nullptr, e2 = nullptr, e3 = nullptr;
+    auto cleanup = [&]() {
+        dfree(f); dfree(g); dfree(w); dfree(ratio); dfree(table);
+        for (hipEvent_t e : {e0, e1, e2, e3})
+            if (e) (void)hipEventDestroy(e);
+    };
+    const int64_t NT = (int64_t)A.Ns * A.N;
+    if (dalloc(&f, A.N) != hipSuccess || dalloc(&g, A.M) != hipSuccess || dalloc(&w, A.M) != hipSuccess ||
+        dalloc(&ratio, A.M) != hipSuccess || dalloc(&table, NT) != hipSuccess) {
+        cleanup();
+        set_error("tuning buffers: allocation failed");
+        return SVR_ENOMEM;
+    }
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess || hipEventCreate(&e2) != hipSuccess ||
+        hipEventCreate(&e3) != hipSuccess) {
+        cleanup();
+        set_error("tuning: event creation failed");
+        return SVR_EDEVICE;
+    }
+    int rc = fill(f, A.N, 1.0f, s);
+    if (!rc) rc = fill(g, A.M, 1.0f, s);
+    if (!rc) rc = fill(w, A.M, 0.1f, s);
+    const int keep_f = A.run_fwd, keep_b = A.run_bp;
+    FwdArgs fa{f, g, w, ratio, nullptr, nullptr};
+    SnapArgs sa{};
+    sa.ratio_all = ratio;
+    sa.f = f;
+    sa.table = table;
+    // The two kernels are timed as the anchor pass runs them, alternately
+    // (each streams its own layout of A, so each starts with the cache state
+    // the other leaves behind): first the forward candidates with the table at
+    // one row per group, then the table candidates after the chosen forward.
+    auto pair_time = [&](double *us_fwd, double *us_tab) -> int {
+        std::vector<float> tf, tt;
+        for (int r = 0; r < 10; ++r) {
+            SVR_HIP(hipEventRecord(e0, s));
+            int q = launch_forward(A, 0, A.M, 1, fa, s);
+            if (q) return q;
+            SVR_HIP(hipEventRecord(e1, s));
+            SVR_HIP(hipEventRecord(e2, s));
+            q = launch_anchor_table(A, UPD_SVREM, sa, s);
+            if (q) return q;
+            SVR_HIP(hipEventRecord(e3, s));
+            SVR_HIP(hipEventSynchronize(e3));
+            float a = 0.0f, b = 0.0f;
+            SVR_HIP(hipEventElapsedTime(&a, e0, e1));
+            SVR_HIP(hipEventElapsedTime(&b, e2, e3));
+            if (r > 0) {  // the first pair warms up
+                tf.push_back(a);
+                tt.push_back(b);
+            }
+        }
+        std::sort(tf.begin(), tf.end());
+        std::sort(tt.begin(), tt.end());
+        *us_fwd = 1e3 * (double)tf[tf.size() / 2];
+        *us_tab = 1e3 * (double)tt[tt.size() / 2];
+        return SVR_OK;
+    };
+    int best_f = 1, best_b = 1;
+    double us_f = 1e30, us_b = 1e30;
+    A.run_bp = 1;
+    for (int R : {1, 2, 3, 4, 6, 8, 12, 16}) {
+        if (rc) break;
+        if (R > 1 && (int64_t)A.M < (int64_t)R * std::max(A.cus, 1) * 4) break;  // fewer waves than SIMDs
+        A.run_fwd = R;
+        double uf = 0.0, ut = 0.0;
+        rc = pair_time(&uf, &ut);
+        if (!rc && uf < us_f) { us_f = uf; best_f = R; }
+    }
+    A.run_fwd = best_f;
+    for (int T : {1, 2, 3, 4, 6, 8, 12, 16}) {
+        if (rc) break;
+        if (T > 1 && NT < (int64_t)T * std::max(A.cus, 1) * 4 * (64 / BP_G)) break;
+        A.run_bp = T;
+        double uf = 0.0, ut = 0.0;
+        rc = pair_time(&uf, &ut);
+        if (!rc && ut < us_b) { us_b = ut; best_b = T; }
+    }
+    if (rc) {
+        A.run_fwd = keep_f;
+        A.run_bp = keep_b;
+    } else {
+        A.run_fwd = best_f;
+        A.run_bp = best_b;
+        if (out) {
+            out->fwd_rows_per_wave = best_f;
+            out->bp_rows_per_group = best_b;
+            out->fwd_us = us_f;
+            out->bp_us = us_b;
+        }
+    }
+    SVR_HIP(hipStreamSynchronize(s));
+    cleanup();
+    return rc;
+}
+
+}  // namespace
+}  // namespace svr
+
+extern "C" {
+
+int svr_matrix_get_tuning(const svr_matrix *A, svr_tuning_t *t) {
+    svr::clear_error();
+    SVR_REQUIRE(A && t, "NULL argument");
+    t->fwd_rows_per_wave = A->run_fwd > 0 ? A->run_fwd : svr::forward_run_length(*A, A->M);
+    t->bp_rows_per_group = svr::table_run_length(*A);
+    t->fwd_us = 0.0;
+    t->bp_us = 0.0;
+    return SVR_OK;
+}
+
+int svr_matrix_set_tuning(svr_matrix *A, const svr_tuning_t *t) {
+    svr::clear_error();
+    SVR_REQUIRE(A && t, "NULL argument");
+    SVR_REQUIRE(t->fwd_rows_per_wave >= 0 && t->fwd_rows_per_wave <= 63, "fwd_rows_per_wave must be in [0, 63]");
+    SVR_REQUIRE(t->bp_rows_per_group >= 0 && t->bp_rows_per_group <= 1024, "bp_rows_per_group must be in [0, 1024]");
+    A->run_fwd = t->fwd_rows_per_wave;
+    A->run_bp = t->bp_rows_per_group;
+    return SVR_OK;
+}
+
+int svr_matrix_tune(svr_matrix *A, void *stream, svr_tuning_t *out) {
+    svr::clear_error();
+    SVR_REQUIRE(A, "NULL argument");
+    SVR_HIP(hipSetDevice(A->device));
+    return svr::tune(*A, (hipStream_t)stream, out);
+}
+
+}  // extern "C"

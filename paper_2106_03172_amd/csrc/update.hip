@@ -74,6 +74,42 @@ k_anchor_table(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const 
     anchor_entry<KIND, WT, IT>(ptrT, rowT, valT, row_start, Ns, N, a, q, lig);
 }
 
+// The same table with runs: each wavefront owns `steps` x (64 / BP_G)
+// consecutive (subset, pixel) rows; at step i its groups take the next
+// 64 / BP_G rows, pipelined by bp_run.
+template <int KIND, typename WT, typename IT>
+__global__ void __launch_bounds__(BP_THREADS)
+k_anchor_table_run(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
+               const int *__restrict__ row_start, int Ns, int N, int steps, SnapArgs a) {
+    constexpr int GPW = 64 / BP_G;  // groups per wavefront
+    const int lane = threadIdx.x & 63, gi = lane / BP_G, lig = lane % BP_G;
+    const int64_t wave = ((int64_t)blockIdx.x * BP_THREADS + threadIdx.x) >> 6;
+    const int64_t total = (int64_t)Ns * N;  // < 2^31
+    const int64_t q0 = wave * GPW * steps + gi;
+    bp_run<WT, IT>(ptrT, rowT, valT, steps, lig,
+                   [&](int i, int64_t &q, const float *&y, float &f) {
+                       q = q0 + (int64_t)GPW * i;
+                       if (q >= total) return false;
+                       const int t = (int)q / N;
+                       y = a.ratio_all + row_start[t];
+                       f = a.f[(int)q - t * N];
+                       return true;
+                   },
+                   [&](int i, double b, float f) {
+                       const int64_t q = q0 + (int64_t)GPW * i;
+                       if (lig != 0 || q >= total) return;
+                       anchor_finish<KIND>(a, Ns, q, (int)q % N, f, b);
+                   });
+}
+
+// (subset, pixel) rows per lane group of a whole-table pass.  Without a
+// tuned value: 1 (the run kernel holds two rows' operands in registers,
+// which costs occupancy; svr_matrix_tune measures whether runs pay off)
+int table_run_length(const Matrix &A) {
+    if (A.run_bp > 0) return std::min(A.run_bp, 1024);
+    return 1;
+}
+
 template <int KIND>
 __global__ void __launch_bounds__(256)
 k_anchor_sum(const double *__restrict__ sens, int Ns, int N, SnapArgs a) {
@@ -112,12 +148,19 @@ int launch_anchor_sum_update(const Matrix &A, int kind, const SnapArgs &a, const
 
 template <int KIND>
 static int launch_anchor_table_k(const Matrix &A, const SnapArgs &a, hipStream_t s) {
-    const int nb = (int)(((int64_t)A.Ns * A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
+    constexpr int GPW = 64 / BP_G;
+    const int steps = table_run_length(A);
+    const int64_t waves = ((int64_t)A.Ns * A.N + (int64_t)GPW * steps - 1) / ((int64_t)GPW * steps);
+    const int nb = (int)((waves * 64 + BP_THREADS - 1) / BP_THREADS);
     return with_types(A, [&](auto w, auto i) {
         using WT = decltype(w);
         using IT = decltype(i);
-        SVR_HIP(launch_k(k_anchor_table<KIND, WT, IT>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
-                         (const WT *)A.d_valT, A.d_row_start, A.Ns, A.N, a));
+        if (steps == 1)
+            SVR_HIP(launch_k(k_anchor_table<KIND, WT, IT>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+                             (const WT *)A.d_valT, A.d_row_start, A.Ns, A.N, a));
+        else
+            SVR_HIP(launch_k(k_anchor_table_run<KIND, WT, IT>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+                             (const WT *)A.d_valT, A.d_row_start, A.Ns, A.N, steps, a));
         return SVR_OK;
     });
 }

@@ -1,0 +1,101 @@
+"""GPU: the run lengths of the whole-matrix passes (svr_matrix_set_tuning /
+svr_matrix_tune) never change a result.
+
+A run length only decides which wavefront (or lane group) sums a row; the
+row's own arithmetic is the same code at every setting, so projections over
+all subsets, back-projections, the objective and whole epochs of the
+variance-reduced methods must be bitwise identical under every tuning,
+including ragged last runs (rows not a multiple of the run length) and runs
+longer than the pass.  The results are also checked once against the FP64
+oracle, so a tuning that is consistently wrong would fail too.
+"""
+
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+import paper_2106_03172_amd as pkg  # noqa: E402
+
+TUNINGS = [(1, 1), (2, 3), (7, 5), (13, 16), (63, 1024), (0, 0)]
+
+
+def rel(a, b):
+    a, b = np.asarray(a, np.float64).ravel(), np.asarray(b, np.float64).ravel()
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def dev(x):
+    return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
+
+
+def run_all(P, A, x, y, f0, order):
+    """Every whole-matrix result of A at its current tuning, on the host."""
+    out = {"fwd": A.project(x).cpu().numpy(), "bp": A.backproject(y).cpu().numpy()}
+    for algo, kw in (("svrem", dict(alpha=0.7, eta=1, beta=1e-2)),
+                     ("svrg", dict(alpha=0.5, eta=1, beta=1e-2)),
+                     ("saga", dict(alpha=0.5, beta=1e-2))):
+        R = pkg.Recon(A, P.g, P.w, f0, pkg.params(algo, **kw))
+        R.osem_epoch(list(range(P.n_subsets)))
+        R.epoch(algo, order)
+        out[algo] = R.image().cpu().numpy()
+        out[algo + "_phi"] = R.objective()
+        R.close()
+    return out
+
+
+@pytest.mark.parametrize("shape", ["medium", "headline"])
+def test_results_are_bitwise_independent_of_tuning(shape):
+    if shape == "medium":
+        P = datagen.make_problem(96, 96, 2.0, 70, 131, 2.0, 7, 3e5, attenuation=False, seed=21)
+    else:
+        P = datagen.make_problem(**datagen.CONFIG_HEADLINE)
+    A = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32)
+    rng = np.random.default_rng(5)
+    x = dev(rng.uniform(0.0, 2.0, A.N))
+    y = dev(rng.uniform(0.0, 2.0, A.M))
+    f0 = np.ones(A.N, np.float32)
+    order = datagen.make_order(P.n_subsets, 2 * P.n_subsets, seed=9)
+    ref = None
+    for fw, bp in TUNINGS:
+        A.set_tuning(fw, bp)
+        eff = A.tuning()
+        assert eff[0] == (fw or eff[0]) and eff[1] == (bp or eff[1])
+        print("tuning", (fw, bp), "effective", eff, flush=True)
+        got = run_all(P, A, x, y, f0, order)
+        if ref is None:
+            ref = got
+            continue
+        for k in ref:
+            assert np.array_equal(np.asarray(got[k]), np.asarray(ref[k])), (k, fw, bp)
+    tuned = A.tune()
+    print("tuned", tuned, flush=True)
+    assert 1 <= tuned[0] <= 63 and 1 <= tuned[1] <= 1024 and tuned[2] > 0 and tuned[3] > 0
+    assert A.tuning() == tuned[:2]
+    got = run_all(P, A, x, y, f0, order)
+    for k in ref:
+        assert np.array_equal(np.asarray(got[k]), np.asarray(ref[k])), (k, "tuned")
+
+    if shape == "medium":  # the shared results against the oracle
+        Ao = oracle.system_matrix(P.geom)
+        xf = x.cpu().numpy().astype(np.float64)
+        yf = y.cpu().numpy().astype(np.float64)
+        assert rel(ref["fwd"].ravel(), Ao @ xf) < 1e-6
+        assert rel(ref["bp"].ravel(), Ao.T @ yf) < 1e-6
+
+
+def test_tuning_rejects_out_of_range():
+    P = datagen.make_problem(**datagen.CONFIG_SMALL)
+    A = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32, mu=P.mu)
+    for bad in ((-1, 0), (64, 0), (0, -1), (0, 1025)):
+        with pytest.raises(pkg.SvrError):
+            A.set_tuning(*bad)
+    A.set_tuning(63, 1024)
+    assert A.tuning() == (63, 1024)
+    A.set_tuning(0, 0)
+    fw, bp = A.tuning()
+    assert fw >= 1 and bp >= 1
