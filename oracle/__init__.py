@@ -25,6 +25,6 @@ from .penalty import (  # noqa: F401
     POT_QUADRATIC, POT_HUBER, POT_LOGCOSH, POT_HYPERBOLA,
 )
 from .em import (  # noqa: F401
-    Model, mstep_root, osem_epoch, mlem, SVREM, SEM,
+    Model, mstep_root, osem_epoch, mlem, SVREM, SEM, SAGAEM, loglik_rows, lik_ratio,
 )
 from .gradient import SVRG, SAGA, SGA, BSREM, PRECOND_SUBSET_FROZEN, PRECOND_FULL_FROZEN, PRECOND_ITERATE  # noqa: F401

@@ -28,6 +28,17 @@ Readings of passages the paper leaves open or prints garbled:
   ``a < 0`` (possible when ``alpha > 1``): the surrogate is unbounded as
   ``f -> 0``, so ``f = 0``;
   pixels never seen (``sum_m a_mn = 0``) are 0.
+* modified likelihood (Sec. 2.3, eq. modified_LL), optional (``ll_eps > 0``):
+  rows with ``w_m = 0`` and ``ybar_m <= eps`` use the second-order expansion
+  of ``phi_m(l) = g_m log l - l`` about ``eps``.  It is the theoretical remedy
+  for the gradient methods (Theorem 1); the EM statistics ``tau_t`` keep the
+  practical zero-denominator rule;
+* SAGA-type online EM (Sec. 2.3, the remark after eq. tempsvrem, which the
+  paper does not examine): the table ``S_t`` starts from one full pass at
+  ``f^(0)`` and ``s_hat^0 = s(f^(0))``; the refreshed index ``t~_k`` is an
+  explicit input (by default ``t~_k = t_k``); the refresh uses ``f^(k)``, the
+  image before the update, and happens after ``s_hat`` has used the old
+  entry.
 """
 
 from __future__ import annotations
@@ -46,6 +57,40 @@ def _safe_div(x, d):
     return out
 
 
+def loglik_rows(g, yb, w, eps: float = 0.0):
+    """Per-row ``phi_m(ybar_m) = g_m log ybar_m - ybar_m`` (``0 log 0 = 0``;
+    ``-inf`` where ``g_m > 0`` and ``ybar_m <= 0``).  With ``eps > 0``, rows with
+    ``w_m = 0`` and ``ybar_m <= eps`` take the modified value of eq. modified_LL:
+    ``phi(eps) + phi'(eps) (ybar - eps) + phi''(eps)/2 (ybar - eps)^2`` with
+    ``phi'(l) = g/l - 1`` and ``phi''(l) = -g/l^2``."""
+    g, yb, w = np.broadcast_arrays(np.asarray(g, float), np.asarray(yb, float), np.asarray(w, float))
+    out = -yb.copy()
+    pos = g > 0
+    ok = pos & (yb > 0)
+    out[ok] = g[ok] * np.log(yb[ok]) - yb[ok]
+    out[pos & (yb <= 0)] = -np.inf
+    if eps > 0:
+        mod = pos & (w == 0) & (yb <= eps)
+        gm, d = g[mod], yb[mod] - eps
+        out[mod] = (gm * np.log(eps) - eps) + (gm / eps - 1.0) * d - 0.5 * (gm / eps ** 2) * d * d
+    return out
+
+
+def lik_ratio(g, yb, w, eps: float = 0.0):
+    """``phi_m'(ybar_m) + 1``, the ratio whose back-projection minus ``A^T 1`` is
+    the likelihood gradient: ``g/ybar`` (0 where ``g = 0`` or ``ybar <= 0``);
+    with ``eps > 0``, rows with ``w = 0`` and ``ybar <= eps`` take the
+    modified derivative ``phi''(eps) (ybar - eps) + phi'(eps) + 1
+    = g (2 eps - ybar) / eps^2`` (eq. modified_LL)."""
+    g, yb, w = np.broadcast_arrays(np.asarray(g, float), np.asarray(yb, float), np.asarray(w, float))
+    out = np.zeros(yb.shape)
+    np.divide(g, yb, out=out, where=(yb > 0) & (g != 0))
+    if eps > 0:
+        mod = (g > 0) & (w == 0) & (yb <= eps)
+        out[mod] = g[mod] * (2.0 * eps - yb[mod]) / eps ** 2
+    return out
+
+
 class Model:
     """The penalised Poisson problem of Sec. 2.1 and Sec. 3 with its partition.
 
@@ -55,7 +100,8 @@ class Model:
     """
 
     def __init__(self, A: sp.csr_matrix, g, w, geom, n_subsets: int, beta: float = 0.0,
-                 potential: int = POT_QUADRATIC, delta: float = 1.0, axial: bool = False):
+                 potential: int = POT_QUADRATIC, delta: float = 1.0, axial: bool = False,
+                 ll_eps: float = 0.0):
         self.A = A.tocsr()
         self.geom = geom
         self.ny, self.nx = geom.ny, geom.nx
@@ -66,6 +112,7 @@ class Model:
         self.potential = potential
         self.delta = float(delta)
         self.axial = axial
+        self.ll_eps = float(ll_eps)  # > 0: modified likelihood (eq. modified_LL) in L and grad L
         self.rows = subset_rows(geom, n_subsets)
         self.A_t = [self.A[r] for r in self.rows]
         self.AT_t = [a.T.tocsr() for a in self.A_t]
@@ -114,9 +161,12 @@ class Model:
 
     # -- objective and gradients ------------------------------------------
     def loglik(self, f) -> float:
-        """``L(f) = sum_m g_m log ybar_m - ybar_m`` (eq. log_likelihood, up to a constant)."""
+        """``L(f) = sum_m g_m log ybar_m - ybar_m`` (eq. log_likelihood, up to a constant);
+        with ``ll_eps > 0`` the modified likelihood of eq. modified_LL."""
         f = np.atleast_2d(f)
         yb = (self.A @ f.T).T + self.w
+        if self.ll_eps > 0:
+            return float(np.sum(loglik_rows(self.g, yb, self.w, self.ll_eps)))
         if np.any((yb <= 0) & (self.g > 0)):
             return -np.inf
         lg = np.zeros_like(yb)
@@ -134,7 +184,11 @@ class Model:
         return self.loglik(f) - self.beta * self.penalty(f)
 
     def grad_L_t(self, f, t):
-        """``grad L_t(f) = A_t^T (g_t / ybar_t - 1)`` (Sec. 4, eq. osem_additive)."""
+        """``grad L_t(f) = A_t^T (g_t / ybar_t - 1)`` (Sec. 4, eq. osem_additive), or
+        ``A_t^T phi_hat'(ybar_t)`` with the modified likelihood."""
+        if self.ll_eps > 0:
+            r = lik_ratio(self.g_t[t], self.fwd_t(f, t), self.w_t[t], self.ll_eps)
+            return (self.AT_t[t] @ r.T).T - self.sens_t[t]
         return self.back_t(f, t) - self.sens_t[t]
 
     def grad_Phi_t(self, f, t):
@@ -142,6 +196,10 @@ class Model:
         return self.grad_L_t(f, t) - (self.beta / self.Ns) * self.grad_R(f)
 
     def grad_Phi(self, f):
+        if self.ll_eps > 0:
+            f = np.atleast_2d(f)
+            r = lik_ratio(self.g, (self.A @ f.T).T + self.w, self.w, self.ll_eps)
+            return (self.AT @ r.T).T - self.sens - self.beta * self.grad_R(f)
         return self.back_full(f) - self.sens - self.beta * self.grad_R(f)
 
     # -- M-step ------------------------------------------------------------
@@ -279,4 +337,47 @@ class SEM:
     def run(self, order):
         for t in order:
             self.step(int(t))
+        return self.f
+
+
+class SAGAEM:
+    """SAGA-type online EM (Sec. 2.3, the remark after eq. tempsvrem) with the
+    penalised M-step of Sec. 3.
+
+    A table ``S_t`` of subset statistics, filled with ``tau_t(f^(0))`` for every
+    ``t`` before the first iteration, and ``s_hat^0 = mean_t S_t = s(f^(0))``.
+    Iteration ``k`` on subset ``t`` with refreshed index ``t~``:
+      * ``s_hat <- (1 - alpha) s_hat + alpha (tau_t(f) - S_t + mean_t' S_t')``;
+      * ``S_t~ <- tau_t~(f)`` (``f`` the image before this update);
+      * ``f <- M-step(s_hat)`` about the current ``f``.
+    """
+
+    def __init__(self, model: Model, f0, alpha: float):
+        self.m = model
+        self.f = np.atleast_2d(np.asarray(f0, dtype=np.float64)).copy()
+        self.alpha = float(alpha)
+        self.k = 0
+        self.s_hat = None
+
+    def init_table(self):
+        m = self.m
+        self.S = [m.tau_t(self.f, t) for t in range(m.Ns)]
+        self.s_hat = sum(self.S) / m.Ns
+
+    def step(self, t: int, t_refresh: int = None):
+        m = self.m
+        if self.k == 0:
+            self.init_table()
+        if t_refresh is None:
+            t_refresh = t
+        tau = m.tau_t(self.f, t)
+        mean_S = sum(self.S) / m.Ns
+        self.s_hat = (1.0 - self.alpha) * self.s_hat + self.alpha * (tau - self.S[t] + mean_S)
+        self.S[t_refresh] = tau if t_refresh == t else m.tau_t(self.f, t_refresh)
+        self.f = m.mstep(self.s_hat, self.f)
+        self.k += 1
+
+    def run(self, order, refresh=None):
+        for i, t in enumerate(order):
+            self.step(int(t), None if refresh is None else int(refresh[i]))
         return self.f

@@ -14,6 +14,7 @@ import oracle.penalty as penalty
 import test_oracle_em as T_em
 import test_oracle_penalty as T_pen
 import test_oracle_siddon as T_sid
+import test_oracle_variants as T_var
 
 
 @pytest.fixture(scope="module")
@@ -96,3 +97,39 @@ def test_missing_half_open_rule_is_caught(monkeypatch):
     monkeypatch.setattr(geometry, "siddon_rays", doubled)
     with pytest.raises(AssertionError):
         T_sid.test_vertical_view_gives_pixel_size_per_pixel()
+
+
+def test_modified_curvature_sign_is_caught(monkeypatch):
+    """A modified ratio with the curvature term's sign flipped (g (2 eps + ybar)
+    / eps^2) breaks the derivative pin."""
+    orig = em.lik_ratio
+
+    def bad(g, yb, w, eps=0.0):
+        out = orig(g, yb, w, eps)
+        if eps > 0:
+            g, yb, w = np.broadcast_arrays(np.asarray(g, float), np.asarray(yb, float), np.asarray(w, float))
+            mod = (g > 0) & (w == 0) & (yb <= eps)
+            out[mod] = g[mod] * (2.0 * eps + yb[mod]) / eps ** 2
+        return out
+    monkeypatch.setattr(em, "lik_ratio", bad)
+    monkeypatch.setattr(oracle, "lik_ratio", bad)
+    with pytest.raises(AssertionError):
+        T_var.test_modified_ratio_is_one_plus_the_derivative()
+
+
+def test_sagaem_refresh_before_use_is_caught(monkeypatch):
+    """Refreshing the table entry before s_hat has used the old one (so the
+    subset term cancels to mean(S)) breaks the refresh pin."""
+    def bad_step(self, t, t_refresh=None):
+        m = self.m
+        if self.k == 0:
+            self.init_table()
+        t_refresh = t if t_refresh is None else t_refresh
+        self.S[t_refresh] = m.tau_t(self.f, t_refresh)
+        tau = m.tau_t(self.f, t)
+        self.s_hat = (1.0 - self.alpha) * self.s_hat + self.alpha * (tau - self.S[t] + sum(self.S) / m.Ns)
+        self.f = m.mstep(self.s_hat, self.f)
+        self.k += 1
+    monkeypatch.setattr(em.SAGAEM, "step", bad_step)
+    with pytest.raises(AssertionError):
+        T_var.test_sagaem_refresh_stores_the_statistic_before_the_update()
