@@ -176,7 +176,7 @@ int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int
 /* ---- reconstruction ------------------------------------------------------ */
 
 enum { SVR_ALGO_OSEM = 0, SVR_ALGO_SVREM = 1, SVR_ALGO_SVRG = 2, SVR_ALGO_SAGA = 3,
-       SVR_ALGO_SGA = 4, SVR_ALGO_BSREM = 5, SVR_ALGO_SEM = 6 };
+       SVR_ALGO_SGA = 4, SVR_ALGO_BSREM = 5, SVR_ALGO_SEM = 6, SVR_ALGO_SAGAEM = 7 };
 /* Potentials of Table 1 (Sec. 3). */
 enum { SVR_PEN_QUADRATIC = 0, SVR_PEN_HUBER = 1, SVR_PEN_LOGCOSH = 2, SVR_PEN_HYPERBOLA = 3 };
 /* Preconditioner of the gradient methods (Sec. 4, eq. preconditioners, frozen
@@ -189,6 +189,11 @@ enum { SVR_PRECOND_SUBSET_FROZEN = 0,  /* d_t = f0 / A_t^T 1 */
 #define SVR_FLAG_PERSISTENT_EPOCH     4 /* run each epoch call as one persistent cooperative
                                            kernel with grid barriers instead of one kernel
                                            per phase (bitwise the same results) */
+#define SVR_FLAG_MODIFIED_LL          8 /* SVRG, SAGA, SGA, BSREM: the modified likelihood of
+                                           Sec. 2.3 (eq. modified_LL) -- rows with w = 0 and
+                                           ybar <= ll_eps use the second-order expansion of
+                                           g log ybar - ybar about ll_eps, in the gradient
+                                           and in svr_objective */
 
 typedef struct {
     int32_t algo;      /* SVR_ALGO_*: which state the recon keeps */
@@ -200,13 +205,16 @@ typedef struct {
     int32_t precond;   /* SVR_PRECOND_* (SVRG, SAGA) */
     int32_t flags;     /* SVR_FLAG_* */
     double  decay;     /* BSREM/SEM step decay (0.001 in the paper) */
+    double  ll_eps;    /* eps of SVR_FLAG_MODIFIED_LL (> 0 when the flag is set) */
 } svr_params;
 
 /* Creates a reconstruction of n_slices images that share A (the slices are
  * coupled only by the optional axial penalty).  g, w and f0 are copied.
  * With n_slices > 1 the data are processed as one sparse-times-dense product
  * per subset (slices as columns) and the recon runs OSEM and SVREM epochs
- * (other algos are rejected with SVR_EINVAL).
+ * (other algos are rejected with SVR_EINVAL).  SVR_FLAG_MODIFIED_LL needs a
+ * gradient algo (SVRG, SAGA, SGA, BSREM) and a finite ll_eps > 0; the
+ * persistent flag is not available with SAGAEM or the modified likelihood.
  *   g_dev  : [S][M] counts (finite, >= 0);  w_dev: [S][M] background (finite, >= 0)
  *   f0_dev : [S][N] starting image (finite, > 0)
  * The matrix must outlive the recon.  Synchronises (validates the data). */
@@ -229,7 +237,9 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
  *  saga : preconditioned proximal SAGA (Sec. 4, eq. saga_update); the table
  *         is filled at f^0 at k = 0.
  *  sga, bsrem, sem: the non-variance-reduced baselines of Sec. 5.1.
- * The call must match params.algo (osem excepted).  Enqueues only. */
+ * The call must match params.algo (osem excepted).  Enqueues only.
+ * Errors: SVR_EINVAL (NULL recon, order outside [0, n_subsets), wrong algo),
+ * SVR_ENUMERIC after a non-finite objective. */
 int svr_osem_epoch (svr_recon *R, const int32_t *order, int32_t n, void *stream);
 int svr_svrem_epoch(svr_recon *R, const int32_t *order, int32_t n, void *stream);
 int svr_svrg_epoch (svr_recon *R, const int32_t *order, int32_t n, void *stream);
@@ -238,8 +248,21 @@ int svr_sga_epoch  (svr_recon *R, const int32_t *order, int32_t n, void *stream)
 int svr_bsrem_epoch(svr_recon *R, const int32_t *order, int32_t n, void *stream);
 int svr_sem_epoch  (svr_recon *R, const int32_t *order, int32_t n, void *stream);
 
+/* SAGA-type online EM (Sec. 2.3, the remark after eq. tempsvrem): a table
+ * S_t of subset statistics (FP32, filled with tau_t(f^0) for every t at k = 0,
+ * with s_hat^0 = mean_t S_t) and its FP64 sum Q.  Iteration k on subset
+ * t = order[i] with refreshed index t~ = refresh[i]:
+ *   s_hat <- (1-alpha) s_hat + alpha (tau_t(f) - S_t + Q/Ns);
+ *   S_t~ <- tau_t~(f), Q += tau_t~(f) - S_t~ (f the image before the update);
+ *   f <- penalised M-step root (Sec. 3).
+ * refresh (host array of n entries in [0, n_subsets)) may be NULL: t~ = t.
+ * A t~ different from t costs a second subset projection.  Enqueues only;
+ * errors as for the other epoch calls. */
+int svr_sagaem_epoch(svr_recon *R, const int32_t *order, const int32_t *refresh, int32_t n, void *stream);
+
 /* Phi(f) = sum_m g_m log(ybar_m) - ybar_m - beta R(f), ybar = A f + w, in FP64
- * over all slices (Sec. 3, eq. PET-MAP; 0 log 0 = 0).  Synchronises.
+ * over all slices (Sec. 3, eq. PET-MAP; 0 log 0 = 0; with SVR_FLAG_MODIFIED_LL
+ * the modified terms of eq. modified_LL).  Synchronises.
  * Returns SVR_ENUMERIC (and marks the recon) if Phi is not finite. */
 int svr_objective(svr_recon *R, double *phi_host, void *stream);
 

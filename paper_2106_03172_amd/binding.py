@@ -24,10 +24,10 @@ SVR_OK, SVR_PENDING, SVR_EINVAL, SVR_ENOMEM, SVR_EDEVICE = 0, 1, -1, -2, -3
 SVR_ENOTFOUND, SVR_ENUMERIC, SVR_ECANCELLED = -4, -5, -6
 SVR_W_F32, SVR_W_F16, SVR_W_BF16 = 0, 1, 2
 SVR_W_INDEX32 = 0x100
-ALGO = dict(osem=0, svrem=1, svrg=2, saga=3, sga=4, bsrem=5, sem=6)
+ALGO = dict(osem=0, svrem=1, svrg=2, saga=3, sga=4, bsrem=5, sem=6, sagaem=7)
 PEN = dict(quadratic=0, huber=1, logcosh=2, hyperbola=3)
 PRECOND = dict(subset_frozen=0, full_frozen=1, iterate=2)
-FLAG_RESET_SHAT_AT_ANCHOR, FLAG_AXIAL_PENALTY, FLAG_PERSISTENT_EPOCH = 1, 2, 4
+FLAG_RESET_SHAT_AT_ANCHOR, FLAG_AXIAL_PENALTY, FLAG_PERSISTENT_EPOCH, FLAG_MODIFIED_LL = 1, 2, 4, 8
 
 
 class SvrError(RuntimeError):
@@ -51,7 +51,8 @@ class svr_matrix_info_t(C.Structure):
 class svr_params(C.Structure):
     _fields_ = [("algo", C.c_int32), ("alpha", C.c_double), ("eta", C.c_int32),
                 ("beta", C.c_double), ("penalty", C.c_int32), ("delta", C.c_double),
-                ("precond", C.c_int32), ("flags", C.c_int32), ("decay", C.c_double)]
+                ("precond", C.c_int32), ("flags", C.c_int32), ("decay", C.c_double),
+                ("ll_eps", C.c_double)]
 
 
 class svr_recon_info_t(C.Structure):
@@ -118,6 +119,7 @@ _SIGS = {
 }
 for _e in ("osem", "svrem", "svrg", "saga", "sga", "bsrem", "sem"):
     _SIGS[f"svr_{_e}_epoch"] = ([_VP, _VP, _I32, _VP], C.c_int)
+_SIGS["svr_sagaem_epoch"] = ([_VP, _VP, _VP, _I32, _VP], C.c_int)
 
 EXPORTED = tuple(_SIGS)
 
@@ -169,11 +171,14 @@ def geometry(geom) -> svr_geometry:
 
 
 def params(algo="svrem", alpha=1.0, eta=1, beta=0.0, penalty="quadratic", delta=1.0,
-           precond="subset_frozen", flags=0, decay=0.001) -> svr_params:
+           precond="subset_frozen", flags=0, decay=0.001, ll_eps=0.0) -> svr_params:
+    """svr_params; ``ll_eps > 0`` also sets FLAG_MODIFIED_LL (the modified likelihood)."""
+    if ll_eps > 0:
+        flags |= FLAG_MODIFIED_LL
     return svr_params(ALGO[algo] if isinstance(algo, str) else int(algo), float(alpha), int(eta),
                       float(beta), PEN[penalty] if isinstance(penalty, str) else int(penalty),
                       float(delta), PRECOND[precond] if isinstance(precond, str) else int(precond),
-                      int(flags), float(decay))
+                      int(flags), float(decay), float(ll_eps))
 
 
 # ---------------------------------------------------------------------------
@@ -214,6 +219,18 @@ def svr_saga_epoch(R, order, stream=None): _epoch("saga", R, order, stream)
 def svr_sga_epoch(R, order, stream=None): _epoch("sga", R, order, stream)
 def svr_bsrem_epoch(R, order, stream=None): _epoch("bsrem", R, order, stream)
 def svr_sem_epoch(R, order, stream=None): _epoch("sem", R, order, stream)
+
+
+def svr_sagaem_epoch(R, order, refresh=None, stream=None):
+    o = np.ascontiguousarray(np.asarray(order, dtype=np.int32))
+    rf = None
+    if refresh is not None:
+        rf = np.ascontiguousarray(np.asarray(refresh, dtype=np.int32))
+        if rf.size != o.size:
+            raise ValueError("refresh must have one entry per order entry")
+    _check(lib().svr_sagaem_epoch(R, o.ctypes.data_as(C.c_void_p),
+                                  None if rf is None else rf.ctypes.data_as(C.c_void_p), int(o.size),
+                                  _stream(stream)))
 
 
 def svr_objective(R, stream=None) -> float:
@@ -321,7 +338,10 @@ class Recon:
         self.h = svr_recon_create(A.h, self.g, self.w, f0, self.S, prm, stream)
 
     def epoch(self, name: str, order, stream=None):
-        _epoch(name, self.h, order, stream)
+        if name == "sagaem":
+            svr_sagaem_epoch(self.h, order, None, stream)
+        else:
+            _epoch(name, self.h, order, stream)
 
     def osem_epoch(self, order, stream=None): _epoch("osem", self.h, order, stream)
     def svrem_epoch(self, order, stream=None): _epoch("svrem", self.h, order, stream)
@@ -330,6 +350,7 @@ class Recon:
     def sga_epoch(self, order, stream=None): _epoch("sga", self.h, order, stream)
     def bsrem_epoch(self, order, stream=None): _epoch("bsrem", self.h, order, stream)
     def sem_epoch(self, order, stream=None): _epoch("sem", self.h, order, stream)
+    def sagaem_epoch(self, order, refresh=None, stream=None): svr_sagaem_epoch(self.h, order, refresh, stream)
 
     def objective(self, stream=None) -> float:
         return svr_objective(self.h, stream)

@@ -57,6 +57,7 @@ int kind_of_algo(int algo) {
         case SVR_ALGO_SGA: return UPD_SGA;
         case SVR_ALGO_BSREM: return UPD_SGA;
         case SVR_ALGO_SEM: return UPD_SEM;
+        case SVR_ALGO_SAGAEM: return UPD_SAGAEM;
     }
     return -1;
 }
@@ -100,6 +101,14 @@ int prof_end(Recon *R, hipStream_t) {
     return SVR_OK;
 }
 
+// eps of the modified likelihood (0 when it is off).  It enters the ratio of
+// the gradient updates and the objective; the EM-type updates (the OSEM
+// initialisation epochs of a gradient recon) keep the EM ratio.
+double ll_eps_of(const Recon *R) { return (R->p.flags & SVR_FLAG_MODIFIED_LL) ? R->p.ll_eps : 0.0; }
+double ll_eps_of(const Recon *R, int kind) {
+    return (kind == UPD_SVRG || kind == UPD_SAGA || kind == UPD_SGA) ? ll_eps_of(R) : 0.0;
+}
+
 PenaltyArgs pen_of(const Recon *R) {
     return PenaltyArgs{R->p.penalty, R->p.delta, R->p.beta, R->A->geom.nx, R->A->geom.ny};
 }
@@ -129,6 +138,7 @@ int check_order(const Recon *R, const int32_t *order, int32_t n) {
 int anchor_iteration(Recon *R, int kind, UpdateArgs &u, hipStream_t s) {
     Matrix &A = *R->A;
     FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
+    fa.eps = ll_eps_of(R, kind);
     int rc = prof_begin(R, 2, s);
     if (!rc) rc = launch_forward(A, 0, A.M, 1, fa, s);
     if (!rc) rc = prof_end(R, s);
@@ -165,7 +175,7 @@ int64_t anchors_in(const Recon *R, int algo, int64_t k0, int n) {
         const int64_t P = (int64_t)R->p.eta * R->Ns;
         return (k0 + n - 1) / P - (k0 - 1 >= 0 ? (k0 - 1) / P : -1);
     }
-    if (algo == SVR_ALGO_SAGA) return k0 == 0 ? 1 : 0;
+    if (algo == SVR_ALGO_SAGA || algo == SVR_ALGO_SAGAEM) return k0 == 0 ? 1 : 0;
     return 0;
 }
 
@@ -202,6 +212,7 @@ int run_epoch_persistent(Recon *R, int algo, int kind, const int32_t *order, int
     e.f0 = R->f[0];
     e.f1 = R->f[1];
     e.cur0 = R->cur;
+    e.eps = ll_eps_of(R, kind);
     e.s_hat = R->s_hat;
     e.s_anc = R->s_anc;
     e.Q = R->Q;
@@ -299,13 +310,18 @@ int check_status(Recon *R, hipStream_t s) {
     return SVR_OK;
 }
 
-int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream) {
+int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream,
+              const int32_t *refresh = nullptr) {
     clear_error();
     SVR_REQUIRE(R, "recon is NULL");
     if (algo != SVR_ALGO_OSEM)
         SVR_REQUIRE(R->p.algo == algo, "recon was created for algo %d, epoch call is for algo %d", R->p.algo, algo);
     int rc = check_order(R, order, n);
     if (rc) return rc;
+    if (refresh) {
+        rc = check_order(R, refresh, n);
+        if (rc) return rc;
+    }
     SVR_HIP(hipSetDevice(R->device));
     hipStream_t s = (hipStream_t)stream;
     Matrix &A = *R->A;
@@ -336,17 +352,26 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream)
         u.shat_zero = (algo == SVR_ALGO_SEM && R->k == 0);
         u.pen = pen_of(R);
         if (algo == SVR_ALGO_OSEM) u.pen.beta = 0.0;
+        const int t2 = refresh ? refresh[i] : t;
+        u.t2 = t2;
+        u.ratio2 = R->ratio + A.row_start[t2];
         const bool anchor = ((algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG) &&
                              R->k % ((int64_t)R->p.eta * R->Ns) == 0) ||
-                            (algo == SVR_ALGO_SAGA && R->k == 0);
+                            ((algo == SVR_ALGO_SAGA || algo == SVR_ALGO_SAGAEM) && R->k == 0);
         if (anchor) {
             rc = anchor_iteration(R, kind, u, s);
             if (rc) return rc;
         } else {
             FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
+            fa.eps = ll_eps_of(R, kind);
             rc = prof_begin(R, 0, s);
             if (!rc) rc = launch_forward(A, A.row_start[t], A.row_start[t + 1], 1, fa, s);
             if (!rc) rc = prof_end(R, s);
+            if (!rc && algo == SVR_ALGO_SAGAEM && t2 != t) {  // the refreshed subset's statistic
+                rc = prof_begin(R, 0, s);
+                if (!rc) rc = launch_forward(A, A.row_start[t2], A.row_start[t2 + 1], 1, fa, s);
+                if (!rc) rc = prof_end(R, s);
+            }
             if (!rc) rc = prof_begin(R, 1, s);
             if (!rc) rc = launch_update(A, kind, u, s);
             if (!rc) rc = prof_end(R, s);
@@ -582,6 +607,17 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
                 "delta must be finite and > 0");
     SVR_REQUIRE(p->precond >= 0 && p->precond <= 2, "unknown precond %d", p->precond);
     SVR_REQUIRE(p->decay >= 0 && std::isfinite(p->decay), "decay must be finite and >= 0");
+    SVR_REQUIRE((p->flags & ~(SVR_FLAG_RESET_SHAT_AT_ANCHOR | SVR_FLAG_AXIAL_PENALTY | SVR_FLAG_PERSISTENT_EPOCH |
+                              SVR_FLAG_MODIFIED_LL)) == 0,
+                "unknown flags 0x%x", p->flags);
+    if (p->flags & SVR_FLAG_MODIFIED_LL) {
+        SVR_REQUIRE(p->algo == SVR_ALGO_SVRG || p->algo == SVR_ALGO_SAGA || p->algo == SVR_ALGO_SGA ||
+                        p->algo == SVR_ALGO_BSREM,
+                    "the modified likelihood (Sec. 2.3) is for the gradient algos SVRG, SAGA, SGA and BSREM");
+        SVR_REQUIRE(p->ll_eps > 0 && std::isfinite(p->ll_eps), "ll_eps must be finite and > 0");
+    }
+    SVR_REQUIRE(!(p->flags & SVR_FLAG_PERSISTENT_EPOCH) || p->algo != SVR_ALGO_SAGAEM,
+                "the persistent epoch kernel does not run SAGAEM");
     SVR_HIP(hipSetDevice(A->device));
     hipStream_t s = (hipStream_t)stream;
     svr_recon *R = new (std::nothrow) svr_recon();
@@ -614,11 +650,12 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     chk(dalloc(&R->d_sync, persistent_sync_words()));
     chk(dalloc(&R->d_status, 1));
     const int algo = p->algo;
-    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SEM) chk(dalloc(&R->s_hat, NS_));
+    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SEM || algo == SVR_ALGO_SAGAEM) chk(dalloc(&R->s_hat, NS_));
     if (algo == SVR_ALGO_SVREM) chk(dalloc(&R->s_anc, NS_));
-    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) chk(dalloc(&R->table, NT));
+    if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA || algo == SVR_ALGO_SAGAEM)
+        chk(dalloc(&R->table, NT));
     if (algo == SVR_ALGO_SVRG) chk(dalloc(&R->g_tilde, N));
-    if (algo == SVR_ALGO_SAGA) chk(dalloc(&R->Q, N));
+    if (algo == SVR_ALGO_SAGA || algo == SVR_ALGO_SAGAEM) chk(dalloc(&R->Q, N));
     if ((algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) && p->precond != SVR_PRECOND_ITERATE) {
         R->dpre_per_subset = (p->precond == SVR_PRECOND_SUBSET_FROZEN);
         chk(dalloc(&R->dpre, R->dpre_per_subset ? NT : (int64_t)N));
@@ -677,6 +714,9 @@ int svr_saga_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return 
 int svr_sga_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_SGA, o, n, s); }
 int svr_bsrem_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_BSREM, o, n, s); }
 int svr_sem_epoch(svr_recon *R, const int32_t *o, int32_t n, void *s) { return run_epoch(R, SVR_ALGO_SEM, o, n, s); }
+int svr_sagaem_epoch(svr_recon *R, const int32_t *o, const int32_t *refresh, int32_t n, void *s) {
+    return run_epoch(R, SVR_ALGO_SAGAEM, o, n, s, refresh);
+}
 
 int svr_objective(svr_recon *R, double *phi_host, void *stream) {
     clear_error();
@@ -688,6 +728,7 @@ int svr_objective(svr_recon *R, double *phi_host, void *stream) {
     int nb = 0, nbp = 0, rc;
     if (R->S == 1) {
         FwdArgs fa{R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad};
+        fa.eps = ll_eps_of(R);
         rc = launch_forward(A, 0, A.M, 2, fa, s, &nb);
     } else {
         rc = ms_forward(A, 0, A.M, 2, R->S, R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad, s, &nb);

@@ -128,6 +128,7 @@ struct FwdArgs {
     float *out;           // mode 0: natural-order sinogram; mode 1: ratio (subset order)
     double *part;         // mode 2: one term per row
     int *bad;             // mode 2: set when g > 0 and ybar <= 0
+    double eps = 0.0;     // > 0: modified likelihood for rows with w = 0 and ybar <= eps
 };
 int launch_forward(const Matrix &A, int r0, int r1, int mode, const FwdArgs &a, hipStream_t s,
                    int *n_blocks_out = nullptr);
@@ -176,17 +177,21 @@ struct UpdateArgs {
     int dpre_per_subset;     // 1 if dpre is Ns*N
     int shat_zero;           // SEM first step: the previous s_hat is taken as 0
     PenaltyArgs pen;
+    int t2;                  // SAGA-EM: refreshed subset (t2 == t: the same back-projection)
+    const float *ratio2;     // SAGA-EM: ratio of subset t2 (subset-local rows)
 };
 
-enum UpdateKind { UPD_OSEM = 0, UPD_SVREM = 1, UPD_SVRG = 2, UPD_SAGA = 3, UPD_SGA = 4, UPD_SEM = 5 };
+enum UpdateKind { UPD_OSEM = 0, UPD_SVREM = 1, UPD_SVRG = 2, UPD_SAGA = 3, UPD_SGA = 4, UPD_SEM = 5,
+                  UPD_SAGAEM = 6 };
 int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s);
 
 // anchor (snapshot) pass at the current image, with the ratio of every row
 // (subset-ordered) already computed.
 //  table kernel: one entry per (subset t, pixel n):
-//    SVREM: tau_t[n] = Ns f_n b_t[n];  SVRG/SAGA: q_t[n] = b_t[n] - beta/Ns grad R(f)_n
+//    SVREM, SAGA-EM: tau_t[n] = Ns f_n b_t[n];  SVRG/SAGA: q_t[n] = b_t[n] - beta/Ns grad R(f)_n
 //  sum kernel (fixed t order, FP64):
 //    SVREM: s_anc = mean_t tau_t (and s_hat = s_anc if init_shat)
+//    SAGA-EM: Q = sum_t tau_t, s_hat = Q / Ns
 //    SVRG : g_tilde = (sum_t q_t - A^T 1) / Ns
 //    SAGA : Q = sum_t q_t
 struct SnapArgs {
@@ -222,6 +227,7 @@ struct EpochArgs {
     float *ratio;
     float *f0, *f1;
     int cur0;
+    double eps;  // modified likelihood (0: off)
     double *s_hat, *s_anc, *Q, *g_tilde;
     float *table;
     float *dpre;

@@ -139,17 +139,27 @@ __device__ inline float em_ratio(float g, double yb) {
     return (g > 0.0f && yb > 0.0) ? (float)((double)g / yb) : 0.0f;
 }
 
-// Forward row r with the EM ratio written to ratio[r]; every lane of the
+// The ratio whose back-projection minus A^T 1 is the likelihood gradient:
+// the EM ratio, or with eps > 0 (the modified likelihood of Sec. 2.3,
+// eq. modified_LL) for rows with w = 0 and ybar <= eps the derivative of the
+// second-order expansion about eps plus one, g (2 eps - ybar) / eps^2.
+__device__ inline float lik_ratio(float g, float w, double yb, double eps) {
+    if (eps > 0.0 && w == 0.0f && yb <= eps)
+        return g > 0.0f ? (float)(((double)g * (2.0 * eps - yb)) / (eps * eps)) : 0.0f;
+    return em_ratio(g, yb);
+}
+
+// Forward row r with the ratio written to ratio[r]; every lane of the
 // wavefront calls it with the same r.
 template <typename WT, typename IT>
 __device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const IT *__restrict__ col,
                                      const WT *__restrict__ val, const float *__restrict__ f,
                                      const float *__restrict__ g, const float *__restrict__ w,
-                                     float *__restrict__ ratio, int r, int lane) {
+                                     float *__restrict__ ratio, int r, int lane, double eps) {
     const float gv = g[r], wv = w[r];
     double acc = row_dot(row_ptr, col, val, f, r, lane);
     acc = wave_sum(acc);
-    if (lane == 0) ratio[r] = em_ratio(gv, acc + (double)wv);
+    if (lane == 0) ratio[r] = lik_ratio(gv, wv, acc + (double)wv, eps);
 }
 
 __device__ inline double group_sum(double acc) {

@@ -52,23 +52,41 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
     // per-pixel operands first: they do not depend on the gather below, so
     // their loads overlap with it
     const float f = u.f[n];
-    constexpr bool EM = (KIND == UPD_SVREM || KIND == UPD_SEM);
-    const float st = (KIND != UPD_SVREM && KIND != UPD_SEM) ? sens_t[q] : 0.0f;
+    constexpr bool EM = (KIND == UPD_SVREM || KIND == UPD_SEM || KIND == UPD_SAGAEM);
+    const float st = !EM ? sens_t[q] : 0.0f;
     const double sh0 = (EM && !u.shat_zero) ? u.s_hat[n] : 0.0;
-    const float tab = (KIND == UPD_SVREM || KIND == UPD_SVRG || KIND == UPD_SAGA) ? u.table[q] : 0.0f;
+    const float tab = (KIND == UPD_SVREM || KIND == UPD_SVRG || KIND == UPD_SAGA || KIND == UPD_SAGAEM) ? u.table[q]
+                                                                                                      : 0.0f;
     const double sanc = (KIND == UPD_SVREM) ? u.s_anc[n] : 0.0;
     const double sn = (EM || KIND == UPD_SAGA) ? sens[n] : 0.0;
     const double gt = (KIND == UPD_SVRG) ? u.g_tilde[n] : 0.0;
-    const double Qn = (KIND == UPD_SAGA) ? u.Q[n] : 0.0;
+    const double Qn = (KIND == UPD_SAGA || KIND == UPD_SAGAEM) ? u.Q[n] : 0.0;
+    // SAGA-EM: the refreshed subset's table entry (its own gather below when t2 != t)
+    const int64_t q2 = (int64_t)u.t2 * N + n;
+    const float tab2 = (KIND == UPD_SAGAEM && u.t2 != u.t) ? u.table[q2] : tab;
     double D = 0.0, E = 0.0, gr = 0.0;
     if (lig == 0 && p.beta > 0.0) {
         if (EM) surrogate_at(u.f, n, p, D, E);
         else if (KIND != UPD_OSEM) gr = penalty_grad_at(u.f, n, p);
     }
     const double b = bp_group(ptrT, rowT, valT, q, u.ratio, lig);
+    double b2 = b;
+    if (KIND == UPD_SAGAEM && u.t2 != u.t) b2 = bp_group(ptrT, rowT, valT, q2, u.ratio2, lig);  // uniform branch
     if (lig != 0) return;
     float out;
-    if (KIND == UPD_OSEM) {
+    if (KIND == UPD_SAGAEM) {
+        // Sec. 2.3, remark after eq. tempsvrem: the statistic uses the old entry
+        // of subset t and the old table mean, then subset t2's entry is refreshed
+        const float tau = tau_of(u.Ns, f, b);
+        const double sh = (1.0 - u.alpha) * sh0 + u.alpha * (((double)tau - (double)tab) + Qn / (double)u.Ns);
+        u.s_hat[n] = sh;
+        const float tau2 = (u.t2 != u.t) ? tau_of(u.Ns, f, b2) : tau;
+        u.Q[n] = Qn + ((double)tau2 - (double)tab2);
+        u.table[q2] = tau2;
+        const double bb = p.beta * D;
+        const double cc = (p.beta * (double)f * D + p.beta * E) - sn;
+        out = (float)mstep_root(sh, bb, cc, sn);
+    } else if (KIND == UPD_OSEM) {
         out = osem_math(f, b, st);
     } else if (KIND == UPD_SVREM) {
         double sh;
@@ -108,8 +126,8 @@ template <int KIND>
 __device__ inline void anchor_finish(const SnapArgs &a, int Ns, int64_t q, int n, float f, double b) {
     const PenaltyArgs &p = a.pen;
     double gr = 0.0;
-    if (KIND != UPD_SVREM && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
-    a.table[q] = (KIND == UPD_SVREM) ? tau_of(Ns, f, b) : q_of(b, gr, p.beta, Ns);
+    if (KIND != UPD_SVREM && KIND != UPD_SAGAEM && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
+    a.table[q] = (KIND == UPD_SVREM || KIND == UPD_SAGAEM) ? tau_of(Ns, f, b) : q_of(b, gr, p.beta, Ns);
 }
 
 template <int KIND, typename WT, typename IT>
@@ -134,6 +152,9 @@ __device__ inline void anchor_sum_pixel(const double *__restrict__ sens, int Ns,
         if (a.init_shat) a.s_hat[n] = sa;
     } else if (KIND == UPD_SVRG) {
         a.g_tilde[n] = (sum - sens[n]) / (double)Ns;
+    } else if (KIND == UPD_SAGAEM) {  // table fill at k = 0: s_hat^0 = s(f^0)
+        a.Q[n] = sum;
+        a.s_hat[n] = sum / (double)Ns;
     } else {
         a.Q[n] = sum;
     }
@@ -144,7 +165,9 @@ __device__ inline void anchor_sum_pixel(const double *__restrict__ sens, int Ns,
 // table entry itself (the same gather and the same expression computed it),
 // and the update needs no forward projection or gather of its own:
 //   SVREM: tau_t(f) - tau_anc_t = 0;  SVRG: q_t(f) - q_anc_t = 0;
-//   SAGA (table fill at k = 0): q_t(f) - q_t = 0 and Q is unchanged.
+//   SAGA (table fill at k = 0): q_t(f) - q_t = 0 and Q is unchanged;
+//   SAGA-EM (table fill at k = 0): tau_t(f) - S_t = 0, and the refreshed
+//   entry S_t2 = tau_t2(f) is already in the table (Q unchanged).
 template <int KIND>
 __device__ inline void anchor_sum_update_pixel(const float *__restrict__ sens_t, const double *__restrict__ sens,
                                                int Ns, int N, const SnapArgs &a, const UpdateArgs &u, int n) {
@@ -160,6 +183,14 @@ __device__ inline void anchor_sum_update_pixel(const float *__restrict__ sens_t,
         double sh;
         out = svrem_math_tau(u.alpha, p.beta, f, tab, u.s_hat[n], tab, u.s_anc[n], sens[n], D, E, &sh);
         u.s_hat[n] = sh;
+    } else if (KIND == UPD_SAGAEM) {
+        double D = 0.0, E = 0.0;
+        if (p.beta > 0.0) surrogate_at(u.f, n, p, D, E);
+        const double sn = sens[n];
+        const double sh =
+            (1.0 - u.alpha) * u.s_hat[n] + u.alpha * (((double)tab - (double)tab) + u.Q[n] / (double)u.Ns);
+        u.s_hat[n] = sh;
+        out = (float)mstep_root(sh, p.beta * D, (p.beta * (double)f * D + p.beta * E) - sn, sn);
     } else {
         const float st = sens_t[q];
         double dir;

@@ -21,9 +21,15 @@
 
 namespace svr {
 
-// g log ybar - ybar of one row (0 log 0 = 0); flags g > 0 with ybar <= 0
-__device__ inline double loglik_term(float g, double yb, int *bad) {
+// g log ybar - ybar of one row (0 log 0 = 0); flags g > 0 with ybar <= 0.
+// With eps > 0, rows with w = 0 and ybar <= eps take the second-order
+// expansion about eps (Sec. 2.3, eq. modified_LL).
+__device__ inline double loglik_term(float g, float w, double yb, double eps, int *bad) {
     if (g > 0.0f) {
+        if (eps > 0.0 && w == 0.0f && yb <= eps) {
+            const double gd = (double)g, d = yb - eps;
+            return ((gd * log(eps) - eps) + (gd / eps - 1.0) * d) - (0.5 * (gd / (eps * eps)) * d) * d;
+        }
         if (yb > 0.0) return (double)g * log(yb) - yb;
         atomicOr(bad, 1);
         return 0.0;
@@ -41,14 +47,14 @@ k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT 
     const int wv = threadIdx.x >> 6;
     const int r = r0 + blockIdx.x * FWD_ROWS_PER_BLOCK + wv;
     if (MODE == 1) {  // wave-uniform: the wave either has a row or not
-        if (r < r1) fwd_ratio_row(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane);
+        if (r < r1) fwd_ratio_row(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane, a.eps);
         return;
     }
     if (r >= r1) return;  // wave-uniform
     const double acc = wave_sum(row_dot(row_ptr, col, val, a.f, r, lane));
     if (lane != 0) return;
     if (MODE == 0) a.out[row_sino[r]] = (float)acc;
-    else a.part[r - r0] = loglik_term(a.g[r], acc + (double)a.w[r], a.bad);
+    else a.part[r - r0] = loglik_term(a.g[r], a.w[r], acc + (double)a.w[r], a.eps, a.bad);
 }
 
 // rows [ra, ra + R) per wavefront, pipelined; the run's per-row operands and
@@ -74,8 +80,8 @@ k_forward_run(const int *__restrict__ row_ptr, const IT *__restrict__ col, const
     fwd_run<WT, IT>(row_ptr, col, val, a.f, ra, nr, lane, [&](int i, double acc) {
         if (lane != i) return;
         if (MODE == 0) outv = (float)acc;
-        else if (MODE == 1) outv = em_ratio(gl, acc + (double)wl);
-        else term = loglik_term(gl, acc + (double)wl, a.bad);
+        else if (MODE == 1) outv = lik_ratio(gl, wl, acc + (double)wl, a.eps);
+        else term = loglik_term(gl, wl, acc + (double)wl, a.eps, a.bad);
     });
     if (lane >= nr) return;
     if (MODE == 0) a.out[sl] = outv;

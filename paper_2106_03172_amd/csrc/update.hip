@@ -13,6 +13,8 @@
 //         Q += q - q_t; q_t = q
 //   SGA / BSREM (Sec. 4 eq. sga, Sec. 5.1) f+ = max(0, f + a (f / A_t^T 1) (b - A_t^T 1 - beta/Ns grad R))
 //   SEM   (Sec. 2.3, eq. tempsem)         s_hat <- (1-a) s_hat + a tau; f+ = root(...)
+//   SAGA-EM (Sec. 2.3, remark after eq. tempsvrem)
+//         s_hat <- (1-a) s_hat + a (tau_t - S_t + Q/Ns); S_t2 <- tau_t2; f+ = root(...)
 // Running statistics and table sums are FP64; tables and the iterate FP32.
 // The quantities stored in a table at an anchor are computed by the same
 // device functions as in the iterations, so they cancel exactly at f = f_anc.
@@ -55,6 +57,7 @@ int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s)
         case UPD_SAGA: return launch_update_k<UPD_SAGA>(A, u, s);
         case UPD_SGA: return launch_update_k<UPD_SGA>(A, u, s);
         case UPD_SEM: return launch_update_k<UPD_SEM>(A, u, s);
+        case UPD_SAGAEM: return launch_update_k<UPD_SAGAEM>(A, u, s);
     }
     set_error("unknown update kind %d", kind);
     return SVR_EINVAL;
@@ -140,6 +143,9 @@ int launch_anchor_sum_update(const Matrix &A, int kind, const SnapArgs &a, const
         case UPD_SAGA:
             e = launch_k(k_anchor_sum_update<UPD_SAGA>, nb, 256, s, A.d_sens_t, A.d_sens, A.Ns, A.N, a, u);
             break;
+        case UPD_SAGAEM:
+            e = launch_k(k_anchor_sum_update<UPD_SAGAEM>, nb, 256, s, A.d_sens_t, A.d_sens, A.Ns, A.N, a, u);
+            break;
         default: set_error("no anchor pass for kind %d", kind); return SVR_EINVAL;
     }
     SVR_HIP(e);
@@ -170,6 +176,7 @@ int launch_anchor_table(const Matrix &A, int kind, const SnapArgs &a, hipStream_
         case UPD_SVREM: return launch_anchor_table_k<UPD_SVREM>(A, a, s);
         case UPD_SVRG: return launch_anchor_table_k<UPD_SVRG>(A, a, s);
         case UPD_SAGA: return launch_anchor_table_k<UPD_SAGA>(A, a, s);
+        case UPD_SAGAEM: return launch_anchor_table_k<UPD_SAGAEM>(A, a, s);
     }
     set_error("no anchor pass for kind %d", kind);
     return SVR_EINVAL;
@@ -182,6 +189,7 @@ int launch_anchor_sum(const Matrix &A, int kind, const SnapArgs &a, hipStream_t 
         case UPD_SVREM: e = launch_k(k_anchor_sum<UPD_SVREM>, nb, 256, s, A.d_sens, A.Ns, A.N, a); break;
         case UPD_SVRG: e = launch_k(k_anchor_sum<UPD_SVRG>, nb, 256, s, A.d_sens, A.Ns, A.N, a); break;
         case UPD_SAGA: e = launch_k(k_anchor_sum<UPD_SAGA>, nb, 256, s, A.d_sens, A.Ns, A.N, a); break;
+        case UPD_SAGAEM: e = launch_k(k_anchor_sum<UPD_SAGAEM>, nb, 256, s, A.d_sens, A.Ns, A.N, a); break;
         default: set_error("no anchor pass for kind %d", kind); return SVR_EINVAL;
     }
     SVR_HIP(e);
