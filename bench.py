@@ -60,7 +60,7 @@ def traffic_from_profile(kernel_kind, wtype):
 
 
 def algorithmic_bytes(kind, A_info, nnz_t_mean, M, Mt_mean, N, Ns, wb):
-    """Bytes each launch of a kernel must move at minimum (see DESIGN.md);
+    """Bytes each launch of a kernel must move at minimum;
     ``ib`` index bytes (2 or 4) and ``wb`` weight bytes per non-zero."""
     ib = A_info.index_bytes
     if kind == "forward":  # index + weight stream, row pointers, image, g, w, ratio
@@ -113,6 +113,67 @@ def cpu_baseline(P, beta, alpha, eta, seconds):
                       f"256x256 / 252x344 / 21-subset workload, FP64 NumPy+SciPy, {el:.1f} s wall"}
 
 
+def bench_convergence(args):
+    """Convergence curves (Sec. 5.1) on a stand-in for the paper's brain slice:
+    114 x 114 (2 mm), 180 views 1 degree apart x 154 bins, 30 subsets, 1e6
+    counts, log cosh penalty with the paper's delta = 0.01 and beta = 60.  All
+    methods start from one OSEM epoch.  f* is a long SVREM run (its last
+    relative change is reported); Delta(f) = ||f - f*|| / ||f*||.  Then the
+    SVREM sweeps of Fig. 3 (alpha, eta and the number of subsets)."""
+    import torch
+
+    import datagen
+    import paper_2106_03172_amd as pkg
+    from paper_2106_03172_amd import convergence as cv
+    beta, pen, delta = 60.0, "logcosh", 0.01
+    P = datagen.make_problem(114, 114, 2.0, 180, 154, 2.0, 30, 1e6, attenuation=False, seed=7)
+    A = pkg.SystemMatrix(P.geom, 30, pkg.SVR_W_F32)
+    t0 = time.perf_counter()
+    ref_m = cv.Method("SVREM", "svrem", dict(alpha=0.7, eta=1, beta=beta, penalty=pen, delta=delta))
+    f_ref, ref_epochs, ref_change = cv.reference_image(A, P.g, P.w, ref_m, max_epochs=3000, tol=1e-7)
+    log(f"reference: {ref_epochs:.0f} epochs, last relative change {ref_change:.1e} "
+        f"({time.perf_counter() - t0:.1f} s)")
+    methods = cv.paper_methods(beta, pen, delta)
+    curves = cv.compare(A, P.g, P.w, methods, args.epochs, f_ref=f_ref)
+    sweeps = []
+    for alpha in (0.3, 0.7, 1.0, 1.4):
+        sweeps.append(("alpha", alpha, 30, cv.Method(f"SVREM alpha={alpha}", "svrem",
+                                                     dict(alpha=alpha, eta=1, beta=beta, penalty=pen, delta=delta))))
+    for eta in (2, 3):
+        sweeps.append(("eta", eta, 30, cv.Method(f"SVREM eta={eta}", "svrem",
+                                                 dict(alpha=0.7, eta=eta, beta=beta, penalty=pen, delta=delta))))
+    for ns in (15, 45):
+        sweeps.append(("n_subsets", ns, ns, cv.Method(f"SVREM Ns={ns}", "svrem",
+                                                      dict(alpha=0.7, eta=1, beta=beta, penalty=pen, delta=delta))))
+    sweep_curves = []
+    mats = {30: A}
+    for kind, val, ns, m in sweeps:
+        if ns not in mats:
+            mats[ns] = pkg.SystemMatrix(P.geom, ns, pkg.SVR_W_F32)
+        sweep_curves.append((kind, val, cv.run_method(mats[ns], P.g, P.w, m, args.epochs, f_ref, seed=900 + len(
+            sweep_curves))))
+    torch.cuda.synchronize()
+
+    def summary(c):
+        at = {}
+        for e_mark in (10, 25, 50):
+            vals = [d for e, d in zip(c.epochs, c.delta) if e <= e_mark]
+            at[str(e_mark)] = round(vals[-1], 6) if vals else None
+        return {"delta_at_epochs": at, "epochs_to_1e-2": c.epochs_to(1e-2), "epochs_to_1e-3": c.epochs_to(1e-3),
+                "final_phi": c.phi[-1] if c.phi else None, "status": c.status,
+                "seconds": round(sum(c.seconds), 4)}
+    out = {"workload": "convergence",
+           "problem": "114x114 (2 mm), 180 views x 154 bins, 30 subsets, 1e6 counts, 10% background, "
+                      "log cosh delta=0.01 beta=60; every method starts from one OSEM epoch",
+           "reference": {"method": "SVREM alpha=0.7 eta=1", "epochs": ref_epochs, "last_change": ref_change},
+           "methods": {c.name: summary(c) for c in curves},
+           "sweeps": [{"param": k, "value": v, **summary(c)} for k, v, c in sweep_curves]}
+    print(json.dumps(out), flush=True)
+    if args.curves_out:
+        with open(args.curves_out, "w") as fh:
+            fh.write(cv.to_json(curves + [c for _, _, c in sweep_curves]))
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -125,8 +186,12 @@ def main():
     ap.add_argument("--eta", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("headline", "multislice", "serve", "copy"), default="headline",
-                    help="headline: the JSON line below; multislice / serve: supplementary measurements")
+    ap.add_argument("--workload", choices=("headline", "multislice", "serve", "copy", "convergence"),
+                    default="headline",
+                    help="headline: the JSON line below; multislice / serve / convergence: supplementary "
+                         "measurements")
+    ap.add_argument("--epochs", type=float, default=50, help="convergence: epochs per curve")
+    ap.add_argument("--curves-out", default="", help="convergence: write every curve as JSON to this file")
     ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
     ap.add_argument("--persistent", action="store_true",
                     help="one persistent cooperative kernel per epoch call instead of one kernel per phase")
@@ -135,8 +200,8 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures a single GPU; --gpus {args.gpus} (WORLD_SIZE={world}) is not supported: "
-              "the reconstruction path runs on one GPU and shards across GPUs only by whole requests "
-              "or slice slabs (see DESIGN.md)", file=sys.stderr)
+              "the reconstruction path runs on one GPU and would shard across GPUs only by whole requests "
+              "or slice slabs", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -150,6 +215,8 @@ def main():
         return bench_multislice(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "convergence":
+        return bench_convergence(args)
     if args.workload == "copy":
         return bench_copy(args)
     wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
