@@ -67,6 +67,12 @@ __host__ __device__ inline float load_w(bf16_t v) {
 // ---------------------------------------------------------------------------
 // matrix object
 // ---------------------------------------------------------------------------
+
+// Zero entries after the last non-zero of every index and weight array, so
+// that a batch of loads may run past the end of the last row: the kernels
+// load unconditionally (a load behind a per-lane branch costs a wait for it
+// before the branches join) and select valid entries afterwards.
+constexpr int64_t NNZ_PAD = 1024;
 struct Matrix {
     svr_geometry geom;
     int Ns = 0, wtype = 0;

@@ -245,10 +245,14 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     A.nnz = nnz;
     WT *val = nullptr, *valT = nullptr;
     int *col = nullptr, *rowT = nullptr;
-    SVR_HIP(dalloc(&col, nnz));
-    SVR_HIP(dalloc(&val, nnz));
-    SVR_HIP(dalloc(&rowT, nnz));
-    SVR_HIP(dalloc(&valT, nnz));
+    SVR_HIP(dalloc(&col, nnz + NNZ_PAD));
+    SVR_HIP(dalloc(&val, nnz + NNZ_PAD));
+    SVR_HIP(dalloc(&rowT, nnz + NNZ_PAD));
+    SVR_HIP(dalloc(&valT, nnz + NNZ_PAD));
+    SVR_HIP(hipMemsetAsync(col + nnz, 0, sizeof(int) * NNZ_PAD, s));
+    SVR_HIP(hipMemsetAsync(val + nnz, 0, sizeof(WT) * NNZ_PAD, s));
+    SVR_HIP(hipMemsetAsync(rowT + nnz, 0, sizeof(int) * NNZ_PAD, s));
+    SVR_HIP(hipMemsetAsync(valT + nnz, 0, sizeof(WT) * NNZ_PAD, s));
     A.d_col = col;
     A.d_rowT = rowT;
     SVR_HIP(dalloc(&cnt, NT));
@@ -288,8 +292,10 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     for (int t = 0; t < Ns; ++t) max_rows = std::max(max_rows, A.rows_of(t));
     if (A.idx16 && N <= 65536 && max_rows <= 65536 && nnz > 0) {
         uint16_t *c16 = nullptr, *r16 = nullptr;
-        SVR_HIP(dalloc(&c16, nnz));
-        SVR_HIP(dalloc(&r16, nnz));
+        SVR_HIP(dalloc(&c16, nnz + NNZ_PAD));
+        SVR_HIP(dalloc(&r16, nnz + NNZ_PAD));
+        SVR_HIP(hipMemsetAsync(c16 + nnz, 0, sizeof(uint16_t) * NNZ_PAD, s));
+        SVR_HIP(hipMemsetAsync(r16 + nnz, 0, sizeof(uint16_t) * NNZ_PAD, s));
         const unsigned gn = (unsigned)((nnz + T - 1) / T);
         k_narrow<<<gn, T, 0, s>>>(col, nnz, c16);
         k_narrow<<<gn, T, 0, s>>>(rowT, nnz, r16);
@@ -302,8 +308,8 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     } else {
         A.idx16 = 0;
     }
-    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + NT + 1 + (Ns + 1)) + (int64_t)A.ibytes() * 2 * nnz +
-              (int64_t)A.wbytes() * 2 * nnz + (int64_t)sizeof(float) * NT + (int64_t)sizeof(double) * N;
+    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + NT + 1 + (Ns + 1)) + (int64_t)A.ibytes() * 2 * (nnz + NNZ_PAD) +
+              (int64_t)A.wbytes() * 2 * (nnz + NNZ_PAD) + (int64_t)sizeof(float) * NT + (int64_t)sizeof(double) * N;
     return SVR_OK;
 }
 

@@ -33,6 +33,14 @@ constexpr int FWD_U = SVR_FWD_U;               // loads in flight per lane (64*8
 constexpr int BP_G = SVR_BP_G;                 // back-projection lanes per pixel
 constexpr int BP_U = SVR_BP_U;                 // loads in flight per lane (4*8 = 32 nnz per batch)
 constexpr int BP_THREADS = 256;
+#ifndef SVR_FWD_RUN_U
+#define SVR_FWD_RUN_U 4
+#endif
+#ifndef SVR_BP_RUN_U
+#define SVR_BP_RUN_U 4
+#endif
+constexpr int FWD_RUN_U = SVR_FWD_RUN_U;       // loads in flight per lane and batch in the row runs
+constexpr int BP_RUN_U = SVR_BP_RUN_U;
 
 // ---- launches, optionally timed by events attached to the dispatch itself ----
 struct LaunchEvents {
@@ -66,17 +74,24 @@ template <int L, int U, typename WT, typename IT>
 struct RowBatch {
     int c[U];
     float v[U];
+    // Every load is unconditional (the arrays carry NNZ_PAD zero entries
+    // after the last row, so a batch may read past a row's end; the image or
+    // ratio gather of an invalid entry reads element 0): a load behind a
+    // per-lane branch makes the compiler wait for it before the branches
+    // join, which would serialise the batch.
     __device__ inline void load(const IT *__restrict__ idx, const WT *__restrict__ val, int base, int end) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int i = base + L * u;
-            c[u] = i < end ? (int)idx[i] : -1;
-            v[u] = i < end ? load_w(val[i]) : 0.0f;
+            const int ci = (int)idx[i];
+            const float vi = load_w(val[i]);
+            c[u] = i < end ? ci : -1;
+            v[u] = vi;
         }
     }
     __device__ inline void gather(const float *__restrict__ x, float (&xv)[U]) const {
 #pragma unroll
-        for (int u = 0; u < U; ++u) xv[u] = c[u] >= 0 ? x[c[u]] : 0.0f;
+        for (int u = 0; u < U; ++u) xv[u] = x[c[u] >= 0 ? c[u] : 0];
     }
     // acc + v*x with one FP64 fused multiply-add: the product of two FP32
     // values is exact in FP64, so this rounds exactly like a multiply
@@ -170,10 +185,8 @@ __device__ inline double group_sum(double acc) {
 // sum over transposed row q of val * y[row], BP_G lanes per row; every lane
 // of the group returns the same value
 template <typename WT, typename IT>
-__device__ inline double bp_group(const int *__restrict__ ptrT, const IT *__restrict__ rowT,
-                                  const WT *__restrict__ valT, int64_t q, const float *__restrict__ y,
-                                  int lig) {
-    const int beg = ptrT[q], end = ptrT[q + 1];
+__device__ inline double bp_range(const IT *__restrict__ rowT, const WT *__restrict__ valT, int beg, int end,
+                                  const float *__restrict__ y, int lig) {
     double acc = 0.0;
     for (int base = beg + lig; base < end; base += BP_G * BP_U) {  // as row_dot
         RowBatch<BP_G, BP_U, WT, IT> b;
@@ -183,6 +196,13 @@ __device__ inline double bp_group(const int *__restrict__ ptrT, const IT *__rest
         acc = b.fma(xv, acc);
     }
     return group_sum(acc);
+}
+
+template <typename WT, typename IT>
+__device__ inline double bp_group(const int *__restrict__ ptrT, const IT *__restrict__ rowT,
+                                  const WT *__restrict__ valT, int64_t q, const float *__restrict__ y,
+                                  int lig) {
+    return bp_range(rowT, valT, ptrT[q], ptrT[q + 1], y, lig);
 }
 
 // ---- pipelined row runs -------------------------------------------------------
@@ -196,20 +216,20 @@ __device__ inline void fwd_run(const int *__restrict__ row_ptr, const IT *__rest
                                const float *__restrict__ f, int ra, int nr, int lane, Fin fin) {
     const int rp = lane <= nr ? row_ptr[ra + lane] : 0;
     int beg = __builtin_amdgcn_readlane(rp, 0), end = __builtin_amdgcn_readlane(rp, 1);
-    RowBatch<64, FWD_U, WT, IT> cur;
+    RowBatch<64, FWD_RUN_U, WT, IT> cur;
     cur.load(col, val, beg + lane, end);
     for (int i = 0; i < nr; ++i) {
-        float xv[FWD_U];
+        float xv[FWD_RUN_U];
         cur.gather(f, xv);
         int nbeg = 0, nend = 0;
-        RowBatch<64, FWD_U, WT, IT> nxt;
+        RowBatch<64, FWD_RUN_U, WT, IT> nxt;
         if (i + 1 < nr) {
             nbeg = __builtin_amdgcn_readlane(rp, i + 1);
             nend = __builtin_amdgcn_readlane(rp, i + 2);
             nxt.load(col, val, nbeg + lane, nend);
         }
         double acc = cur.fma(xv, 0.0);
-        acc = row_rest<64, FWD_U, WT, IT>(col, val, f, beg + lane, end, acc);
+        acc = row_rest<64, FWD_RUN_U, WT, IT>(col, val, f, beg + lane, end, acc);
         fin(i, wave_sum(acc));
         beg = nbeg;
         end = nend;
@@ -222,30 +242,31 @@ __device__ inline void fwd_run(const int *__restrict__ row_ptr, const IT *__rest
 // i+2, the index/weight batch of step i+1 and the gathers of step i are in
 // flight together.  `seq(i, q, y, aux)` names step i's row, the vector it
 // gathers from and loads the per-row operand `aux` (false: no row, the sum
-// is 0); `fin(i, b, aux)` gets the group-reduced sum.  Every lane of the
+// is 0, and the gathers read ydef[0]); `fin(i, b, aux)` gets the
+// group-reduced sum.  Every lane of the
 // group takes the same steps.
 template <typename WT, typename IT, class Seq, class Fin>
 __device__ inline void bp_run(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
-                              int n, int lig, Seq seq, Fin fin) {
+                              int n, int lig, const float *ydef, Seq seq, Fin fin) {
     int64_t q;
-    const float *y0 = nullptr, *y1 = nullptr;
+    const float *y0 = ydef, *y1 = ydef;
     int b0 = 0, e0 = 0, b1 = 0, e1 = 0;
     float a0 = 0.0f, a1 = 0.0f;
     if (n > 0 && seq(0, q, y0, a0)) { b0 = ptrT[q]; e0 = ptrT[q + 1]; }
     if (n > 1 && seq(1, q, y1, a1)) { b1 = ptrT[q]; e1 = ptrT[q + 1]; }
-    RowBatch<BP_G, BP_U, WT, IT> cur;
+    RowBatch<BP_G, BP_RUN_U, WT, IT> cur;
     cur.load(rowT, valT, b0 + lig, e0);
     for (int i = 0; i < n; ++i) {
-        float xv[BP_U];
+        float xv[BP_RUN_U];
         cur.gather(y0, xv);
-        RowBatch<BP_G, BP_U, WT, IT> nxt;
+        RowBatch<BP_G, BP_RUN_U, WT, IT> nxt;
         nxt.load(rowT, valT, b1 + lig, e1);
-        const float *y2 = nullptr;
+        const float *y2 = ydef;
         int b2 = 0, e2 = 0;
         float a2 = 0.0f;
         if (i + 2 < n && seq(i + 2, q, y2, a2)) { b2 = ptrT[q]; e2 = ptrT[q + 1]; }
         double acc = cur.fma(xv, 0.0);
-        acc = row_rest<BP_G, BP_U, WT, IT>(rowT, valT, y0, b0 + lig, e0, acc);
+        acc = row_rest<BP_G, BP_RUN_U, WT, IT>(rowT, valT, y0, b0 + lig, e0, acc);
         fin(i, group_sum(acc), a0);
         b0 = b1; e0 = e1; y0 = y1; a0 = a1;
         b1 = b2; e1 = e2; y1 = y2; a1 = a2;

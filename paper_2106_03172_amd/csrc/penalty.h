@@ -55,55 +55,81 @@ __device__ inline double pot_gamma(int kind, double t, double delta) {
     }
 }
 
-// Visits the existing in-plane neighbours of pixel (ix, iy): fn(j, w_nj).
-template <class F>
-__device__ inline void for_neighbours(int ix, int iy, int nx, int ny, F &&fn) {
+// The 8 in-plane neighbours of pixel n = iy*nx + ix (values at f[j*stride + off])
+// in a fixed order (left,
+// right, down, up, down-left, down-right, up-left, up-right): their values,
+// loaded together and unconditionally (outside the image the coordinate is
+// clamped, so the load stays in bounds, and the neighbour is flagged
+// absent), and their weights w_nj.  Loading them first lets all eight loads
+// be in flight at once; the sums below then add the present neighbours in
+// that order.
+struct Neighbours {
+    float v[8];
+    bool ok[8];  // false for a neighbour outside the image
+};
+
+__device__ inline Neighbours load_neighbours(const float *f, int ix, int iy, int nx, int ny, int64_t stride = 1,
+                                             int64_t off = 0) {
     const bool l = ix > 0, r = ix + 1 < nx, d = iy > 0, u = iy + 1 < ny;
-    const int n = iy * nx + ix;
-    if (l) fn(n - 1, 1.0);
-    if (r) fn(n + 1, 1.0);
-    if (d) fn(n - nx, 1.0);
-    if (u) fn(n + nx, 1.0);
-    if (d && l) fn(n - nx - 1, INV_SQRT2);
-    if (d && r) fn(n - nx + 1, INV_SQRT2);
-    if (u && l) fn(n + nx - 1, INV_SQRT2);
-    if (u && r) fn(n + nx + 1, INV_SQRT2);
+    const int xl = l ? ix - 1 : ix, xr = r ? ix + 1 : ix, yd = d ? iy - 1 : iy, yu = u ? iy + 1 : iy;
+    const int jj[8] = {iy * nx + xl, iy * nx + xr, yd * nx + ix, yu * nx + ix,
+                       yd * nx + xl, yd * nx + xr, yu * nx + xl, yu * nx + xr};
+    Neighbours nb;
+    nb.ok[0] = l; nb.ok[1] = r; nb.ok[2] = d; nb.ok[3] = u;
+    nb.ok[4] = d && l; nb.ok[5] = d && r; nb.ok[6] = u && l; nb.ok[7] = u && r;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) nb.v[k] = f[(int64_t)jj[k] * stride + off];
+    return nb;
 }
 
-// grad R(f)_n = sum_j w_nj rho'(f_n - f_j)
-__device__ inline double penalty_grad_at(const float *f, int n, const PenaltyArgs &p) {
+__device__ inline double nb_weight(int k) { return k < 4 ? 1.0 : INV_SQRT2; }
+
+__device__ inline Neighbours load_neighbours_of(const float *f, int n, const PenaltyArgs &p) {
     const int iy = n / p.nx, ix = n - iy * p.nx;
-    const double fn = (double)f[n];
+    return load_neighbours(f, ix, iy, p.nx, p.ny);
+}
+
+// grad R(f)_n = sum_j w_nj rho'(f_n - f_j), from pixel n's value and its neighbours
+__device__ inline double penalty_grad_nb(double fn, const Neighbours &nb, const PenaltyArgs &p) {
     double g = 0.0;
-    for_neighbours(ix, iy, p.nx, p.ny, [&](int j, double w) {
-        g = g + w * pot_drho(p.potential, fn - (double)f[j], p.delta);
-    });
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (nb.ok[k]) g = g + nb_weight(k) * pot_drho(p.potential, fn - (double)nb.v[k], p.delta);
     return g;
+}
+
+__device__ inline double penalty_grad_at(const float *f, int n, const PenaltyArgs &p) {
+    return penalty_grad_nb((double)f[n], load_neighbours_of(f, n, p), p);
 }
 
 // Surrogate sums of the penalised M-step: D = sum_j d_nj, E = sum_j d_nj f_j,
 // d_nj = w_nj gamma(f_n - f_j) at the expansion point f (Sec. 3, eq. svrsurder).
-__device__ inline void surrogate_at(const float *f, int n, const PenaltyArgs &p, double &D, double &E) {
-    const int iy = n / p.nx, ix = n - iy * p.nx;
-    const double fn = (double)f[n];
+__device__ inline void surrogate_nb(double fn, const Neighbours &nb, const PenaltyArgs &p, double &D, double &E) {
     D = 0.0;
     E = 0.0;
-    for_neighbours(ix, iy, p.nx, p.ny, [&](int j, double w) {
-        const double fj = (double)f[j];
-        const double d = w * pot_gamma(p.potential, fn - fj, p.delta);
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        if (!nb.ok[k]) continue;
+        const double fj = (double)nb.v[k];
+        const double d = nb_weight(k) * pot_gamma(p.potential, fn - fj, p.delta);
         D = D + d;
         E = E + d * fj;
-    });
+    }
+}
+
+__device__ inline void surrogate_at(const float *f, int n, const PenaltyArgs &p, double &D, double &E) {
+    surrogate_nb((double)f[n], load_neighbours_of(f, n, p), p, D, E);
 }
 
 // 1/2 sum_j w_nj rho(f_n - f_j): pixel n's share of R(f)
 __device__ inline double penalty_share_at(const float *f, int n, const PenaltyArgs &p) {
     const int iy = n / p.nx, ix = n - iy * p.nx;
     const double fn = (double)f[n];
+    const Neighbours nb = load_neighbours(f, ix, iy, p.nx, p.ny);
     double r = 0.0;
-    for_neighbours(ix, iy, p.nx, p.ny, [&](int j, double w) {
-        r = r + w * pot_rho(p.potential, fn - (double)f[j], p.delta);
-    });
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (nb.ok[k]) r = r + nb_weight(k) * pot_rho(p.potential, fn - (double)nb.v[k], p.delta);
     return 0.5 * r;
 }
 

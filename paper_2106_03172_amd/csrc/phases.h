@@ -49,12 +49,16 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
                                     const double *__restrict__ sens, int N, const UpdateArgs &u, int n, int lig) {
     const int64_t q = (int64_t)u.t * N + n;
     const PenaltyArgs &p = u.pen;
-    // per-pixel operands first: they do not depend on the gather below, so
-    // their loads overlap with it
+    // The transposed row's bounds first (the gather chain starts there), then
+    // every per-pixel operand and the stencil's neighbour values: none of
+    // them depends on the gather, so all their loads are in flight with it;
+    // the penalty arithmetic runs after the gather.
+    const int beg = ptrT[q], end = ptrT[q + 1];
     const float f = u.f[n];
     constexpr bool EM = (KIND == UPD_SVREM || KIND == UPD_SEM || KIND == UPD_SAGAEM);
     const float st = !EM ? sens_t[q] : 0.0f;
-    const double sh0 = (EM && !u.shat_zero) ? u.s_hat[n] : 0.0;
+    const double sh_ld = EM ? u.s_hat[n] : 0.0;  // loaded unconditionally, selected below
+    const double sh0 = u.shat_zero ? 0.0 : sh_ld;
     const float tab = (KIND == UPD_SVREM || KIND == UPD_SVRG || KIND == UPD_SAGA || KIND == UPD_SAGAEM) ? u.table[q]
                                                                                                       : 0.0f;
     const double sanc = (KIND == UPD_SVREM) ? u.s_anc[n] : 0.0;
@@ -64,15 +68,17 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
     // SAGA-EM: the refreshed subset's table entry (its own gather below when t2 != t)
     const int64_t q2 = (int64_t)u.t2 * N + n;
     const float tab2 = (KIND == UPD_SAGAEM && u.t2 != u.t) ? u.table[q2] : tab;
-    double D = 0.0, E = 0.0, gr = 0.0;
-    if (lig == 0 && p.beta > 0.0) {
-        if (EM) surrogate_at(u.f, n, p, D, E);
-        else if (KIND != UPD_OSEM) gr = penalty_grad_at(u.f, n, p);
-    }
-    const double b = bp_group(ptrT, rowT, valT, q, u.ratio, lig);
+    Neighbours nb;
+    if (KIND != UPD_OSEM) nb = load_neighbours_of(u.f, n, p);
+    const double b = bp_range(rowT, valT, beg, end, u.ratio, lig);
     double b2 = b;
     if (KIND == UPD_SAGAEM && u.t2 != u.t) b2 = bp_group(ptrT, rowT, valT, q2, u.ratio2, lig);  // uniform branch
     if (lig != 0) return;
+    double D = 0.0, E = 0.0, gr = 0.0;
+    if (p.beta > 0.0) {
+        if (EM) surrogate_nb((double)f, nb, p, D, E);
+        else if (KIND != UPD_OSEM) gr = penalty_grad_nb((double)f, nb, p);
+    }
     float out;
     if (KIND == UPD_SAGAEM) {
         // Sec. 2.3, remark after eq. tempsvrem: the statistic uses the old entry

@@ -138,7 +138,7 @@ k_backproject(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const W
     const int n = gid / BP_G, lig = gid % BP_G;
     if (n >= N) return;  // whole groups leave together
     double acc = 0.0;
-    bp_run<WT, IT>(ptrT, rowT, valT, t >= 0 ? 1 : Ns, lig,
+    bp_run<WT, IT>(ptrT, rowT, valT, t >= 0 ? 1 : Ns, lig, y_sub,
                    [&](int i, int64_t &q, const float *&y, float &) {
                        const int tt = t >= 0 ? t : i;
                        q = (int64_t)tt * N + n;

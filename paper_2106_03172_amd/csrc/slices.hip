@@ -32,21 +32,24 @@ __device__ inline float rl_f(float v, int j) { return __int_as_float(__builtin_a
 template <typename WT, typename IT>
 __device__ inline double ms_dot(const IT *__restrict__ idx, const WT *__restrict__ val, int beg, int end,
                                 const float *__restrict__ y, int S, int s, bool act, int lane) {
+    // loads are unconditional (padded index/weight arrays, slice 0 for lanes
+    // past the stack) so a batch's gathers are in flight together; entries
+    // past the row and inactive lanes are masked out of the sum
     double acc = 0.0;
+    const int sc = act ? s : 0;
     for (int base = beg; base < end; base += 64) {
         const int i = base + lane;
-        const int cv = i < end ? (int)idx[i] : 0;
-        const float av = i < end ? load_w(val[i]) : 0.0f;
+        const int ci = (int)idx[i];
+        const float ai = load_w(val[i]);
+        const int cv = i < end ? ci : 0;
         const int cnt = min(64, end - base);
         for (int j = 0; j < cnt; j += MS_U) {
             float x[MS_U], a[MS_U];
 #pragma unroll
             for (int u = 0; u < MS_U; ++u) {
-                if (j + u < cnt) {
-                    const int c = rl_i(cv, j + u);
-                    a[u] = rl_f(av, j + u);
-                    x[u] = act ? y[(int64_t)c * S + s] : 0.0f;
-                }
+                const int c = rl_i(cv, (j + u) & 63);
+                a[u] = rl_f(ai, (j + u) & 63);
+                x[u] = y[(int64_t)c * S + sc];
             }
 #pragma unroll
             for (int u = 0; u < MS_U; ++u)
@@ -57,10 +60,15 @@ __device__ inline double ms_dot(const IT *__restrict__ idx, const WT *__restrict
 }
 
 // ---- penalty with in-plane and optional axial neighbours ---------------------
+// (all neighbour values loaded first, absent ones clamped in bounds and
+// skipped, so the sums are those of the in-plane order then down, up)
 __device__ inline void surrogate_at_ms(const float *X, int n, int s, int S, const PenaltyArgs &p, int axial,
                                        double &D, double &E) {
     const int iy = n / p.nx, ix = n - iy * p.nx;
     const double fn = (double)X[(int64_t)n * S + s];
+    const Neighbours nb = load_neighbours(X, ix, iy, p.nx, p.ny, S, s);
+    const double fd = (double)X[(int64_t)n * S + (s > 0 ? s - 1 : s)];
+    const double fu = (double)X[(int64_t)n * S + (s + 1 < S ? s + 1 : s)];
     D = 0.0;
     E = 0.0;
     auto add = [&](double fj, double w) {
@@ -68,23 +76,28 @@ __device__ inline void surrogate_at_ms(const float *X, int n, int s, int S, cons
         D = D + d;
         E = E + d * fj;
     };
-    for_neighbours(ix, iy, p.nx, p.ny, [&](int j, double w) { add((double)X[(int64_t)j * S + s], w); });
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (nb.ok[k]) add((double)nb.v[k], nb_weight(k));
     if (axial) {
-        if (s > 0) add((double)X[(int64_t)n * S + s - 1], 1.0);
-        if (s + 1 < S) add((double)X[(int64_t)n * S + s + 1], 1.0);
+        if (s > 0) add(fd, 1.0);
+        if (s + 1 < S) add(fu, 1.0);
     }
 }
 
 __device__ inline double penalty_share_at_ms(const float *X, int n, int s, int S, const PenaltyArgs &p, int axial) {
     const int iy = n / p.nx, ix = n - iy * p.nx;
     const double fn = (double)X[(int64_t)n * S + s];
+    const Neighbours nb = load_neighbours(X, ix, iy, p.nx, p.ny, S, s);
+    const double fd = (double)X[(int64_t)n * S + (s > 0 ? s - 1 : s)];
+    const double fu = (double)X[(int64_t)n * S + (s + 1 < S ? s + 1 : s)];
     double r = 0.0;
-    for_neighbours(ix, iy, p.nx, p.ny, [&](int j, double w) {
-        r = r + w * pot_rho(p.potential, fn - (double)X[(int64_t)j * S + s], p.delta);
-    });
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+        if (nb.ok[k]) r = r + nb_weight(k) * pot_rho(p.potential, fn - (double)nb.v[k], p.delta);
     if (axial) {
-        if (s > 0) r = r + pot_rho(p.potential, fn - (double)X[(int64_t)n * S + s - 1], p.delta);
-        if (s + 1 < S) r = r + pot_rho(p.potential, fn - (double)X[(int64_t)n * S + s + 1], p.delta);
+        if (s > 0) r = r + pot_rho(p.potential, fn - fd, p.delta);
+        if (s + 1 < S) r = r + pot_rho(p.potential, fn - fu, p.delta);
     }
     return 0.5 * r;
 }

@@ -89,7 +89,7 @@ k_anchor_table_run(const int *__restrict__ ptrT, const IT *__restrict__ rowT, co
     const int64_t wave = ((int64_t)blockIdx.x * BP_THREADS + threadIdx.x) >> 6;
     const int64_t total = (int64_t)Ns * N;  // < 2^31
     const int64_t q0 = wave * GPW * steps + gi;
-    bp_run<WT, IT>(ptrT, rowT, valT, steps, lig,
+    bp_run<WT, IT>(ptrT, rowT, valT, steps, lig, a.ratio_all,
                    [&](int i, int64_t &q, const float *&y, float &f) {
                        q = q0 + (int64_t)GPW * i;
                        if (q >= total) return false;
