@@ -21,6 +21,7 @@ struct svr_recon {
     int M = 0, N = 0, Ns = 0;
     float *g = nullptr, *w = nullptr;   // subset-ordered data
     float *f[2] = {nullptr, nullptr};   // ping-pong iterate
+    float *ft = nullptr;                // the current iterate in tiled order (single slice; Nt floats)
     int cur = 0;
     float *ratio = nullptr;             // M, subset-ordered
     double *s_hat = nullptr, *s_anc = nullptr, *Q = nullptr, *g_tilde = nullptr;
@@ -66,7 +67,7 @@ void free_recon(Recon *R) {
     if (!R) return;
     AllocStream as(R->owner);
     for (hipEvent_t e : R->ev) (void)hipEventDestroy(e);
-    void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ratio, R->s_hat, R->s_anc, R->Q, R->g_tilde,
+    void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ft, R->ratio, R->s_hat, R->s_anc, R->Q, R->g_tilde,
                     R->table, R->dpre, R->part, R->scal, R->bad, R->d_order, R->d_sync, R->d_status};
     for (void *q : ptrs) dfree(q);
     delete R;
@@ -137,7 +138,7 @@ int check_order(const Recon *R, const int32_t *order, int32_t n) {
 // anchor_sum_update_pixel.
 int anchor_iteration(Recon *R, int kind, UpdateArgs &u, hipStream_t s) {
     Matrix &A = *R->A;
-    FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
+    FwdArgs fa{R->ft, R->g, R->w, R->ratio, nullptr, nullptr};
     fa.eps = ll_eps_of(R, kind);
     int rc = prof_begin(R, 2, s);
     if (!rc) rc = launch_forward(A, 0, A.M, 1, fa, s);
@@ -195,7 +196,7 @@ int run_epoch_persistent(Recon *R, int algo, int kind, const int32_t *order, int
     SVR_HIP(hipMemsetAsync(R->d_sync, 0, sizeof(unsigned) * persistent_sync_words(), s));
     EpochArgs e{};
     e.row_ptr = A.d_row_ptr;
-    e.col = A.d_col;
+    e.col = A.d_colt;
     e.val = A.d_val;
     e.ptrT = A.d_ptrT;
     e.rowT = A.d_rowT;
@@ -212,6 +213,8 @@ int run_epoch_persistent(Recon *R, int algo, int kind, const int32_t *order, int
     e.f0 = R->f[0];
     e.f1 = R->f[1];
     e.cur0 = R->cur;
+    e.ft = R->ft;
+    e.tx = A.tx;
     e.eps = ll_eps_of(R, kind);
     e.s_hat = R->s_hat;
     e.s_anc = R->s_anc;
@@ -339,6 +342,8 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream,
         u.ratio = R->ratio + A.row_start[t];
         u.f = R->f[R->cur];
         u.f_out = R->f[1 - R->cur];
+        u.ft_out = R->ft;
+        u.tx = A.tx;
         u.alpha = R->p.alpha;
         if (algo == SVR_ALGO_BSREM || algo == SVR_ALGO_SEM)
             u.alpha = R->p.alpha / (R->p.decay * (double)R->k + 1.0);
@@ -362,7 +367,7 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream,
             rc = anchor_iteration(R, kind, u, s);
             if (rc) return rc;
         } else {
-            FwdArgs fa{R->f[R->cur], R->g, R->w, R->ratio, nullptr, nullptr};
+            FwdArgs fa{R->ft, R->g, R->w, R->ratio, nullptr, nullptr};
             fa.eps = ll_eps_of(R, kind);
             rc = prof_begin(R, 0, s);
             if (!rc) rc = launch_forward(A, A.row_start[t], A.row_start[t + 1], 1, fa, s);
@@ -545,7 +550,7 @@ void svr_matrix_destroy(svr_matrix *A) {
     if (!A) return;
     (void)hipSetDevice(A->device);
     AllocStream as(A->owner);
-    void *ptrs[] = {A->d_row_start, A->d_row_sino, A->d_row_ptr, A->d_col, A->d_val, A->d_ptrT,
+    void *ptrs[] = {A->d_row_start, A->d_row_sino, A->d_row_ptr, A->d_col, A->d_colt, A->d_val, A->d_ptrT,
                     A->d_rowT, A->d_valT, A->d_sens_t, A->d_sens};
     for (void *q : ptrs) dfree(q);
     delete A;
@@ -561,12 +566,17 @@ int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t
     hipStream_t s = (hipStream_t)stream;
     const int r0 = subset < 0 ? 0 : A->row_start[subset];
     const int r1 = subset < 0 ? A->M : A->row_start[subset + 1];
-    for (int sl = 0; sl < n_slices; ++sl) {
-        FwdArgs fa{x_dev + (int64_t)sl * A->N, nullptr, nullptr, y_dev + (int64_t)sl * A->M, nullptr, nullptr};
-        int rc = launch_forward(*A, r0, r1, 0, fa, s);
-        if (rc) return rc;
+    float *xt = nullptr;  // each slice in the tiled order of the forward indices
+    SVR_HIP(hipMallocAsync((void **)&xt, sizeof(float) * (size_t)A->Nt, s));
+    SVR_HIP(hipMemsetAsync(xt, 0, sizeof(float) * (size_t)A->Nt, s));
+    int rc = SVR_OK;
+    for (int sl = 0; sl < n_slices && rc == SVR_OK; ++sl) {
+        rc = launch_tile_image(*A, x_dev + (int64_t)sl * A->N, xt, s);
+        FwdArgs fa{xt, nullptr, nullptr, y_dev + (int64_t)sl * A->M, nullptr, nullptr};
+        if (rc == SVR_OK) rc = launch_forward(*A, r0, r1, 0, fa, s);
     }
-    return SVR_OK;
+    SVR_HIP(hipFreeAsync(xt, s));
+    return rc;
 }
 
 int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int32_t n_slices, float *x_dev,
@@ -643,6 +653,7 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     chk(dalloc(&R->w, MS_));
     chk(dalloc(&R->f[0], NS_));
     chk(dalloc(&R->f[1], NS_));
+    if (S == 1) chk(dalloc(&R->ft, A->Nt));
     chk(dalloc(&R->ratio, MS_));
     chk(dalloc(&R->part, R->n_part));
     chk(dalloc(&R->scal, 2));
@@ -693,6 +704,8 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
         if (!rc) rc = launch_gather_rows(*A, w_dev, R->w, s);
         if (!rc && hipMemcpyAsync(R->f[0], f0_dev, sizeof(float) * N, hipMemcpyDeviceToDevice, s) != hipSuccess)
             rc = SVR_EDEVICE;
+        if (!rc && hipMemsetAsync(R->ft, 0, sizeof(float) * A->Nt, s) != hipSuccess) rc = SVR_EDEVICE;
+        if (!rc) rc = launch_tile_image(*A, R->f[0], R->ft, s);
     } else {
         rc = ms_pack_sino(*A, (int)S, g_dev, R->g, s);
         if (!rc) rc = ms_pack_sino(*A, (int)S, w_dev, R->w, s);
@@ -727,7 +740,7 @@ int svr_objective(svr_recon *R, double *phi_host, void *stream) {
     SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
     int nb = 0, nbp = 0, rc;
     if (R->S == 1) {
-        FwdArgs fa{R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad};
+        FwdArgs fa{R->ft, R->g, R->w, nullptr, R->part, R->bad};
         fa.eps = ll_eps_of(R);
         rc = launch_forward(A, 0, A.M, 2, fa, s, &nb);
     } else {
@@ -860,6 +873,10 @@ int svr_recon_set_state(svr_recon *R, const void *buf, size_t len, void *stream)
     for (auto &f : fields) {
         SVR_HIP(hipMemcpyAsync(f.dev, p, f.bytes, hipMemcpyHostToDevice, s));
         p += f.bytes;
+    }
+    if (R->ft) {
+        int rc = launch_tile_image(*R->A, R->f[R->cur], R->ft, s);
+        if (rc) return rc;
     }
     SVR_HIP(hipStreamSynchronize(s));
     R->k = h.k;

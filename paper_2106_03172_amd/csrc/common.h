@@ -73,6 +73,21 @@ __host__ __device__ inline float load_w(bf16_t v) {
 // load unconditionally (a load behind a per-lane branch costs a wait for it
 // before the branches join) and select valid entries afterwards.
 constexpr int64_t NNZ_PAD = 1024;
+
+// Tiled pixel order of the image the single-slice forward projection
+// gathers from: 4 x 8-pixel tiles (one 128-byte cache line of FP32 values
+// each), tiles row-major, pixels row-major within a tile.  A ray crosses a
+// tile in several consecutive entries, so a wavefront's gathers touch far
+// fewer cache lines than in row-major order (about 2.6x fewer at 256^2).
+constexpr int TILE_W = 4, TILE_H = 8;
+__host__ __device__ inline int tiles_x(int nx) { return (nx + TILE_W - 1) / TILE_W; }
+__host__ __device__ inline int tiled_count(int nx, int ny) {
+    return tiles_x(nx) * TILE_W * ((ny + TILE_H - 1) / TILE_H) * TILE_H;
+}
+__host__ __device__ inline int tiled_index(int n, int nx, int tx) {
+    const int iy = n / nx, ix = n - iy * nx;
+    return ((iy / TILE_H) * tx + ix / TILE_W) * (TILE_W * TILE_H) + (iy % TILE_H) * TILE_W + (ix % TILE_W);
+}
 struct Matrix {
     svr_geometry geom;
     int Ns = 0, wtype = 0;
@@ -87,6 +102,8 @@ struct Matrix {
     int *d_row_sino = nullptr;      // M: natural sinogram index of each subset-ordered row
     int *d_row_ptr = nullptr;       // M+1
     void *d_col = nullptr;          // nnz pixel indices (int32, or uint16 when idx16)
+    void *d_colt = nullptr;         // the same in tiled pixel order (single-slice forward passes)
+    int Nt = 0, tx = 0;             // tiled image size (>= N) and tiles per image row
     void *d_val = nullptr;          // nnz (float / _Float16 / bf16_t)
     int *d_ptrT = nullptr;          // Ns*N+1
     void *d_rowT = nullptr;         // nnz subset-local rows (int32, or uint16 when idx16)
@@ -129,7 +146,7 @@ int build_matrix(Matrix &A, const float *mu_dev, hipStream_t s);
 //  mode 2: log-likelihood term of row r into part[r - r0], ratio not written
 //          (*n_blocks_out receives the number of terms, r1 - r0)
 struct FwdArgs {
-    const float *f;       // image, N floats
+    const float *f;       // image in tiled order (Nt floats; slice stacks: [N][S] natural)
     const float *g, *w;   // subset-ordered data (modes 1, 2)
     float *out;           // mode 0: natural-order sinogram; mode 1: ratio (subset order)
     double *part;         // mode 2: one term per row
@@ -142,6 +159,9 @@ int launch_forward(const Matrix &A, int r0, int r1, int mode, const FwdArgs &a, 
 // back-projection of subset t (or all subsets with t = -1) of a ratio/data
 // vector in subset-ordered rows: x[n] = sum over the transposed row.
 int launch_backproject(const Matrix &A, int t, const float *y_sub, float *x, hipStream_t s);
+
+// ft[tiled(n)] = f[n] (the pad entries of ft are left as they are)
+int launch_tile_image(const Matrix &A, const float *f, float *ft, hipStream_t s);
 
 // deterministic FP64 reduction of n partials into out[0]
 int launch_reduce_sum(const double *part, int n, double *out, hipStream_t s);
@@ -185,6 +205,8 @@ struct UpdateArgs {
     PenaltyArgs pen;
     int t2;                  // SAGA-EM: refreshed subset (t2 == t: the same back-projection)
     const float *ratio2;     // SAGA-EM: ratio of subset t2 (subset-local rows)
+    float *ft_out;           // f^{k+1} also in tiled order for the next forward pass (nullable)
+    int tx;                  // tiles per image row
 };
 
 enum UpdateKind { UPD_OSEM = 0, UPD_SVREM = 1, UPD_SVRG = 2, UPD_SAGA = 3, UPD_SGA = 4, UPD_SEM = 5,
@@ -233,6 +255,8 @@ struct EpochArgs {
     float *ratio;
     float *f0, *f1;
     int cur0;
+    float *ft;   // the iterate in tiled order: read by the forward phases, written by the updates
+    int tx;
     double eps;  // modified likelihood (0: off)
     double *s_hat, *s_anc, *Q, *g_tilde;
     float *table;

@@ -221,6 +221,25 @@ __global__ void k_subset_offsets(int Ns, const int *row_start, const int *row_pt
     if (t <= Ns) stats[2 + t] = row_ptr[row_start[t]];
 }
 
+// forward indices in tiled pixel order; the pad entries stay 0
+template <typename IT>
+__global__ void k_tile_cols(const IT *col, int64_t n_all, int64_t nnz, int nx, int tx, IT *colt) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n_all) return;
+    colt[i] = i < nnz ? (IT)tiled_index((int)col[i], nx, tx) : (IT)0;
+}
+
+__global__ void k_tile_image(const float *f, int N, int nx, int tx, float *ft) {
+    const int n = blockIdx.x * blockDim.x + threadIdx.x;
+    if (n < N) ft[tiled_index(n, nx, tx)] = f[n];
+}
+
+int launch_tile_image(const Matrix &A, const float *f, float *ft, hipStream_t s) {
+    k_tile_image<<<(A.N + 255) / 256, 256, 0, s>>>(f, A.N, A.geom.nx, A.tx, ft);
+    SVR_HIP(hipGetLastError());
+    return SVR_OK;
+}
+
 template <typename WT>
 static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     const int M = A.M, N = A.N, Ns = A.Ns, B = A.geom.n_bins;
@@ -290,7 +309,9 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     // 16-bit indices when every pixel index and every subset-local row fits
     int max_rows = 0;
     for (int t = 0; t < Ns; ++t) max_rows = std::max(max_rows, A.rows_of(t));
-    if (A.idx16 && N <= 65536 && max_rows <= 65536 && nnz > 0) {
+    A.tx = tiles_x(A.geom.nx);
+    A.Nt = tiled_count(A.geom.nx, A.geom.ny);
+    if (A.idx16 && A.Nt <= 65536 && max_rows <= 65536 && nnz > 0) {
         uint16_t *c16 = nullptr, *r16 = nullptr;
         SVR_HIP(dalloc(&c16, nnz + NNZ_PAD));
         SVR_HIP(dalloc(&r16, nnz + NNZ_PAD));
@@ -308,7 +329,21 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     } else {
         A.idx16 = 0;
     }
-    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + NT + 1 + (Ns + 1)) + (int64_t)A.ibytes() * 2 * (nnz + NNZ_PAD) +
+    // the forward indices in tiled pixel order
+    const unsigned gp = (unsigned)((nnz + NNZ_PAD + T - 1) / T);
+    if (A.idx16) {
+        uint16_t *ct = nullptr;
+        SVR_HIP(dalloc(&ct, nnz + NNZ_PAD));
+        k_tile_cols<uint16_t><<<gp, T, 0, s>>>((const uint16_t *)A.d_col, nnz + NNZ_PAD, nnz, A.geom.nx, A.tx, ct);
+        A.d_colt = ct;
+    } else {
+        int *ct = nullptr;
+        SVR_HIP(dalloc(&ct, nnz + NNZ_PAD));
+        k_tile_cols<int><<<gp, T, 0, s>>>((const int *)A.d_col, nnz + NNZ_PAD, nnz, A.geom.nx, A.tx, ct);
+        A.d_colt = ct;
+    }
+    SVR_HIP(hipGetLastError());
+    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + NT + 1 + (Ns + 1)) + (int64_t)A.ibytes() * 3 * (nnz + NNZ_PAD) +
               (int64_t)A.wbytes() * 2 * (nnz + NNZ_PAD) + (int64_t)sizeof(float) * NT + (int64_t)sizeof(double) * N;
     return SVR_OK;
 }

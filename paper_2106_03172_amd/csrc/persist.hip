@@ -98,7 +98,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
         const bool anchor = vr_anchor ? (k % ((long long)e.eta * Ns) == 0) : (KIND == UPD_SAGA && k == 0);
         if (anchor) {
             for (int r = gwave; r < e.M; r += nwaves)
-                fwd_ratio_row(e.row_ptr, col, val, f, e.g, e.w, e.ratio, r, lane, e.eps);
+                fwd_ratio_row(e.row_ptr, col, val, e.ft, e.g, e.w, e.ratio, r, lane, e.eps);
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
             SnapArgs sa{};
             sa.ratio_all = e.ratio;
@@ -125,7 +125,7 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
         {
             const int r0 = e.row_start[t], r1 = e.row_start[t + 1];
             for (int r = r0 + gwave; r < r1; r += nwaves)
-                fwd_ratio_row(e.row_ptr, col, val, f, e.g, e.w, e.ratio, r, lane, e.eps);
+                fwd_ratio_row(e.row_ptr, col, val, e.ft, e.g, e.w, e.ratio, r, lane, e.eps);
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
             UpdateArgs u{};
             u.t = t;
@@ -133,6 +133,8 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
             u.ratio = e.ratio + r0;
             u.f = f;
             u.f_out = fo;
+            u.ft_out = e.ft;
+            u.tx = e.tx;
             u.alpha = e.decaying ? e.alpha / (e.decay * (double)k + 1.0) : e.alpha;
             u.s_hat = e.s_hat;
             u.s_anc = e.s_anc;

@@ -124,6 +124,7 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
         out = (float)fmax(0.0, (double)f + (u.alpha * d) * dir);
     }
     u.f_out[n] = out;
+    if (u.ft_out) u.ft_out[tiled_index(n, p.nx, u.tx)] = out;
 }
 
 // table entry (subset t, pixel n) from its back-projected sum b and f = f_n;
@@ -211,6 +212,7 @@ __device__ inline void anchor_sum_update_pixel(const float *__restrict__ sens_t,
         out = (float)fmax(0.0, (double)f + (u.alpha * d) * dir);
     }
     u.f_out[n] = out;
+    if (u.ft_out) u.ft_out[tiled_index(n, p.nx, u.tx)] = out;
 }
 
 // frozen preconditioner entry i: d_t[n] = f0[n] / (A_t^T 1)[n] (per subset,

@@ -106,10 +106,10 @@ static int launch_forward_t(const Matrix &A, int r0, int r1, int R, const FwdArg
         using WT = decltype(w);
         using IT = decltype(i);
         if (R == 1)
-            SVR_HIP(launch_k(k_forward<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_col,
+            SVR_HIP(launch_k(k_forward<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
                              (const WT *)A.d_val, A.d_row_sino, r0, r1, a));
         else
-            SVR_HIP(launch_k(k_forward_run<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_col,
+            SVR_HIP(launch_k(k_forward_run<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
                              (const WT *)A.d_val, A.d_row_sino, r0, r1, R, a));
         return SVR_OK;
     });

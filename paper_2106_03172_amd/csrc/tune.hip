@@ -39,7 +39,8 @@ int tune(Matrix &A, hipStream_t s, svr_tuning_t *out) {
             if (e) (void)hipEventDestroy(e);
     };
     const int64_t NT = (int64_t)A.Ns * A.N;
-    if (dalloc(&f, A.N) != hipSuccess || dalloc(&g, A.M) != hipSuccess || dalloc(&w, A.M) != hipSuccess ||
+    const int64_t NF = std::max<int64_t>(A.N, A.Nt);  // the forward reads the tiled order
+    if (dalloc(&f, NF) != hipSuccess || dalloc(&g, A.M) != hipSuccess || dalloc(&w, A.M) != hipSuccess ||
         dalloc(&ratio, A.M) != hipSuccess || dalloc(&table, NT) != hipSuccess) {
         cleanup();
         set_error("tuning buffers: allocation failed");
@@ -51,7 +52,7 @@ int tune(Matrix &A, hipStream_t s, svr_tuning_t *out) {
         set_error("tuning: event creation failed");
         return SVR_EDEVICE;
     }
-    int rc = fill(f, A.N, 1.0f, s);
+    int rc = fill(f, NF, 1.0f, s);
     if (!rc) rc = fill(g, A.M, 1.0f, s);
     if (!rc) rc = fill(w, A.M, 0.1f, s);
     const int keep_f = A.run_fwd, keep_b = A.run_bp;
