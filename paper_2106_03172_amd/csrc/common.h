@@ -84,9 +84,12 @@ __host__ __device__ inline int tiles_x(int nx) { return (nx + TILE_W - 1) / TILE
 __host__ __device__ inline int tiled_count(int nx, int ny) {
     return tiles_x(nx) * TILE_W * ((ny + TILE_H - 1) / TILE_H) * TILE_H;
 }
+__host__ __device__ inline int tiled_index_xy(int ix, int iy, int tx) {
+    return ((iy / TILE_H) * tx + ix / TILE_W) * (TILE_W * TILE_H) + (iy % TILE_H) * TILE_W + (ix % TILE_W);
+}
 __host__ __device__ inline int tiled_index(int n, int nx, int tx) {
     const int iy = n / nx, ix = n - iy * nx;
-    return ((iy / TILE_H) * tx + ix / TILE_W) * (TILE_W * TILE_H) + (iy % TILE_H) * TILE_W + (ix % TILE_W);
+    return tiled_index_xy(ix, iy, tx);
 }
 struct Matrix {
     svr_geometry geom;

@@ -54,6 +54,7 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
     // them depends on the gather, so all their loads are in flight with it;
     // the penalty arithmetic runs after the gather.
     const int beg = ptrT[q], end = ptrT[q + 1];
+    const int iy = n / p.nx, ix = n - iy * p.nx;
     const float f = u.f[n];
     constexpr bool EM = (KIND == UPD_SVREM || KIND == UPD_SEM || KIND == UPD_SAGAEM);
     const float st = !EM ? sens_t[q] : 0.0f;
@@ -69,7 +70,7 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
     const int64_t q2 = (int64_t)u.t2 * N + n;
     const float tab2 = (KIND == UPD_SAGAEM && u.t2 != u.t) ? u.table[q2] : tab;
     Neighbours nb;
-    if (KIND != UPD_OSEM) nb = load_neighbours_of(u.f, n, p);
+    if (KIND != UPD_OSEM) nb = load_neighbours(u.f, ix, iy, p.nx, p.ny);
     const double b = bp_range(rowT, valT, beg, end, u.ratio, lig);
     double b2 = b;
     if (KIND == UPD_SAGAEM && u.t2 != u.t) b2 = bp_group(ptrT, rowT, valT, q2, u.ratio2, lig);  // uniform branch
@@ -124,7 +125,7 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
         out = (float)fmax(0.0, (double)f + (u.alpha * d) * dir);
     }
     u.f_out[n] = out;
-    if (u.ft_out) u.ft_out[tiled_index(n, p.nx, u.tx)] = out;
+    if (u.ft_out) u.ft_out[tiled_index_xy(ix, iy, u.tx)] = out;
 }
 
 // table entry (subset t, pixel n) from its back-projected sum b and f = f_n;
