@@ -65,14 +65,14 @@ def algorithmic_bytes(kind, A_info, nnz_t_mean, M, Mt_mean, N, Ns, wb):
     ib = A_info.index_bytes
     if kind == "forward":  # index + weight stream, row pointers, image, g, w, ratio
         return nnz_t_mean * (ib + wb) + 4 * (Mt_mean + 1) + 4 * N + 12 * Mt_mean
-    if kind == "update":   # transposed stream, pointers, ratio, per-pixel SVREM state
-        return nnz_t_mean * (ib + wb) + 4 * (N + 1) + 4 * Mt_mean + 44 * N
+    if kind == "update":   # transposed stream, pointers, ratio, per-pixel SVREM state, tiled iterate copy
+        return nnz_t_mean * (ib + wb) + 4 * (N + 1) + 4 * Mt_mean + 48 * N
     if kind == "anchor_forward":
         return A_info.nnz * (ib + wb) + 4 * (M + 1) + 4 * N + 12 * M
     if kind == "anchor_table":  # all transposed rows, their pointers, ratio, f, table write
         return A_info.nnz * (ib + wb) + 4 * (Ns * N + 1) + 4 * M + 4 * N + 4 * Ns * N
-    if kind == "anchor_sum":    # table read, A^T 1 (SVRG) or s_hat/s_anc writes
-        return 4 * Ns * N + 8 * N
+    if kind == "anchor_sum":    # table read, s_anc and s_hat writes, then the fused SVREM update
+        return 4 * Ns * N + 8 * N + 48 * N
     raise ValueError(kind)
 
 
