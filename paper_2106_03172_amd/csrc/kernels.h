@@ -25,13 +25,16 @@ namespace svr {
 #define SVR_BP_G 4
 #endif
 #ifndef SVR_BP_U
-#define SVR_BP_U 8
+#define SVR_BP_U 5
 #endif
 constexpr int FWD_THREADS = 256;               // forward: 4 wavefronts per block
 constexpr int FWD_ROWS_PER_BLOCK = FWD_THREADS / 64;
 constexpr int FWD_U = SVR_FWD_U;               // loads in flight per lane (64*8 = 512 nnz per batch)
 constexpr int BP_G = SVR_BP_G;                 // back-projection lanes per pixel
-constexpr int BP_U = SVR_BP_U;                 // loads in flight per lane (4*8 = 32 nnz per batch)
+constexpr int BP_U = SVR_BP_U;                 // loads in flight per lane (4*5 = 20 nnz per batch: one
+                                               // batch covers a whole transposed subset row of a 2 mm
+                                               // 256x256 image, 252 views, 21 subsets, in >99% of rows;
+                                               // 5 beat 4, 6, 7 and 8 in measured anchor-table time)
 constexpr int BP_THREADS = 256;
 #ifndef SVR_FWD_RUN_U
 #define SVR_FWD_RUN_U 4
