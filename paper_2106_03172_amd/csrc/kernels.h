@@ -40,10 +40,10 @@ constexpr int BP_THREADS = 256;
 #define SVR_FWD_RUN_U 4
 #endif
 #ifndef SVR_BP_RUN_U
-#define SVR_BP_RUN_U 4
+#define SVR_BP_RUN_U 5
 #endif
 constexpr int FWD_RUN_U = SVR_FWD_RUN_U;       // loads in flight per lane and batch in the row runs
-constexpr int BP_RUN_U = SVR_BP_RUN_U;
+constexpr int BP_RUN_U = SVR_BP_RUN_U;         // 4*5 = 20, as BP_U (46.5 -> 39 us per whole back-projection)
 
 // ---- launches, optionally timed by events attached to the dispatch itself ----
 struct LaunchEvents {
@@ -68,6 +68,41 @@ __device__ inline double wave_sum(double v) {
     return v;
 }
 
+// ---- range-checked buffer loads ----------------------------------------------
+// A raw buffer resource over `bytes` bytes from p: a buffer load whose byte
+// offset is at or past `bytes` returns 0 and makes no memory request (the
+// hardware's range check of raw buffers, stride 0).  A wavefront that owns a
+// row builds one over the rest of that row, so every slot of a batch is issued
+// unconditionally (no per-lane branch) while the slots past the row's end cost
+// no cache lines.  Word 3 selects a 32-bit data format, which untyped loads
+// need to be non-zero; the offset and swizzle fields stay 0.
+constexpr int BUF_RSRC_WORD3 = 0x00020000;
+__device__ inline __amdgpu_buffer_rsrc_t range_rsrc(const void *p, int bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void *>(p), (short)0, bytes, BUF_RSRC_WORD3);
+}
+template <typename T>
+__device__ inline T buf_load(__amdgpu_buffer_rsrc_t r, int off);
+template <>
+__device__ inline uint16_t buf_load<uint16_t>(__amdgpu_buffer_rsrc_t r, int off) {
+    return (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0);
+}
+template <>
+__device__ inline int buf_load<int>(__amdgpu_buffer_rsrc_t r, int off) {
+    return (int)__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0);
+}
+template <>
+__device__ inline float buf_load<float>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+template <>
+__device__ inline _Float16 buf_load<_Float16>(__amdgpu_buffer_rsrc_t r, int off) {
+    return __builtin_bit_cast(_Float16, (uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0));
+}
+template <>
+__device__ inline bf16_t buf_load<bf16_t>(__amdgpu_buffer_rsrc_t r, int off) {
+    return bf16_t{(uint16_t)__builtin_amdgcn_raw_buffer_load_b16(r, off, 0, 0)};
+}
+
 // One batch of a sparse row held in registers: lane j of an L-lane team
 // holds entries base + j + L*u (u < U) of the row ending at `end`, index -1
 // past the end.  Every sparse sum in the library walks its rows batch by
@@ -89,6 +124,24 @@ struct RowBatch {
             const int ci = (int)idx[i];
             const float vi = load_w(val[i]);
             c[u] = i < end ? ci : -1;
+            v[u] = vi;
+        }
+    }
+    // The batch of a row owned by the whole wavefront (L = 64): entries
+    // bb + lane + 64 u of the row ending at `end` (bb, end wavefront-uniform),
+    // the entries and lanes of load(idx, val, bb + lane, end), read through
+    // range-checked resources that end at the row's end.
+    __device__ inline void load_wave(const IT *__restrict__ idx, const WT *__restrict__ val, int bb, int end,
+                                     int lane) {
+        const int n = end - bb;
+        const __amdgpu_buffer_rsrc_t ri = range_rsrc(idx + bb, n * (int)sizeof(IT));
+        const __amdgpu_buffer_rsrc_t rv = range_rsrc(val + bb, n * (int)sizeof(WT));
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int o = lane + L * u;
+            const int ci = (int)buf_load<IT>(ri, o * (int)sizeof(IT));
+            const float vi = load_w(buf_load<WT>(rv, o * (int)sizeof(WT)));
+            c[u] = o < n ? ci : -1;
             v[u] = vi;
         }
     }
@@ -121,31 +174,19 @@ __device__ inline double row_rest(const IT *__restrict__ idx, const WT *__restri
     return acc;
 }
 
-// sum over entries [beg, end) of val * x[idx], lanes of an L-lane team
-// striding the row; per-lane partial (reduce across the team afterwards)
-template <int L, int U, typename WT, typename IT>
-__device__ inline double row_partial(const IT *__restrict__ idx, const WT *__restrict__ val,
-                                     const float *__restrict__ x, int beg, int end, int lane) {
-    RowBatch<L, U, WT, IT> b;
-    float xv[U];
-    b.load(idx, val, beg + lane, end);
-    b.gather(x, xv);
-    return row_rest<L, U, WT, IT>(idx, val, x, beg + lane, end, b.fma(xv, 0.0));
-}
-
-// (A f)_r: the lanes of a wavefront stride over row r's non-zeros, FP64
-// products.  Written as one loop (not through RowBatch) because this is the
-// per-iteration path, where the peeled first batch of row_partial costs a few
-// percent; the entries, their order and the operations are row_partial's.
+// (A f)_r: the lanes of a wavefront stride over row r's non-zeros in batches
+// of 64 * FWD_U, FP64 products; lane j adds entries beg + j, beg + j + 64, ...
+// in that order (the same entries and order as fwd_run's).
 template <typename WT, typename IT>
 __device__ inline double row_dot(const int *__restrict__ row_ptr, const IT *__restrict__ col,
                                  const WT *__restrict__ val, const float *__restrict__ f, int r, int lane) {
+    r = __builtin_amdgcn_readfirstlane(r);  // one row per wavefront: scalar row bounds
     const int beg = row_ptr[r], end = row_ptr[r + 1];
     double acc = 0.0;
-    for (int base = beg + lane; base < end; base += 64 * FWD_U) {
+    for (int bb = beg; bb < end; bb += 64 * FWD_U) {
         RowBatch<64, FWD_U, WT, IT> b;
         float xv[FWD_U];
-        b.load(col, val, base, end);
+        b.load_wave(col, val, bb, end, lane);
         b.gather(f, xv);
         acc = b.fma(xv, acc);
     }
@@ -220,7 +261,7 @@ __device__ inline void fwd_run(const int *__restrict__ row_ptr, const IT *__rest
     const int rp = lane <= nr ? row_ptr[ra + lane] : 0;
     int beg = __builtin_amdgcn_readlane(rp, 0), end = __builtin_amdgcn_readlane(rp, 1);
     RowBatch<64, FWD_RUN_U, WT, IT> cur;
-    cur.load(col, val, beg + lane, end);
+    cur.load_wave(col, val, beg, end, lane);
     for (int i = 0; i < nr; ++i) {
         float xv[FWD_RUN_U];
         cur.gather(f, xv);
@@ -229,10 +270,15 @@ __device__ inline void fwd_run(const int *__restrict__ row_ptr, const IT *__rest
         if (i + 1 < nr) {
             nbeg = __builtin_amdgcn_readlane(rp, i + 1);
             nend = __builtin_amdgcn_readlane(rp, i + 2);
-            nxt.load(col, val, nbeg + lane, nend);
+            nxt.load_wave(col, val, nbeg, nend, lane);
         }
         double acc = cur.fma(xv, 0.0);
-        acc = row_rest<64, FWD_RUN_U, WT, IT>(col, val, f, beg + lane, end, acc);
+        for (int bb = beg + 64 * FWD_RUN_U; bb < end; bb += 64 * FWD_RUN_U) {  // as row_rest
+            RowBatch<64, FWD_RUN_U, WT, IT> b;
+            b.load_wave(col, val, bb, end, lane);
+            b.gather(f, xv);
+            acc = b.fma(xv, acc);
+        }
         fin(i, wave_sum(acc));
         beg = nbeg;
         end = nend;
