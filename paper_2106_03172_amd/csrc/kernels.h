@@ -63,9 +63,41 @@ inline hipError_t launch_k(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipS
     return hipGetLastError();
 }
 
+// ---- cross-lane sums ------------------------------------------------------------
+// FP64 value of another lane through a DPP move of both halves (CTRL: the
+// GFX9 DPP control; every source lane used here lies in the same 16-lane row
+// and is active whenever the reading lane is).
+template <int CTRL>
+__device__ inline double dpp_f64(double v) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)b, CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int DPP_XOR1 = 0xB1;         // quad_perm [1,0,3,2]: lane ^ 1
+constexpr int DPP_XOR2 = 0x4E;         // quad_perm [2,3,0,1]: lane ^ 2
+constexpr int DPP_HALF_MIRROR = 0x141;  // lane i <-> 7 - i within each 8
+constexpr int DPP_MIRROR = 0x140;       // lane i <-> 15 - i within each 16
+
+__device__ inline double readlane_f64(double v, int l) {
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)b, l), hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Sum over the 64 lanes of a wavefront, the same value in every lane, in a
+// fixed order: lane pairs, quads, 8s and 16s by DPP moves (after each step
+// every lane of the group holds the group's sum: a + b and b + a are the
+// same number), then the four 16-lane rows as (r0 + r1) + (r2 + r3).  Every
+// lane of the wavefront must call it (the rows are read with readlane).
+// DPP moves stay in the vector ALU; a shuffle would go through the LDS
+// crossbar, one round trip per 32-bit half and step.
 __device__ inline double wave_sum(double v) {
-    for (int o = 32; o > 0; o >>= 1) v = v + __shfl_xor(v, o, 64);
-    return v;
+    v = v + dpp_f64<DPP_XOR1>(v);
+    v = v + dpp_f64<DPP_XOR2>(v);
+    v = v + dpp_f64<DPP_HALF_MIRROR>(v);
+    v = v + dpp_f64<DPP_MIRROR>(v);
+    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
 }
 
 // ---- range-checked buffer loads ----------------------------------------------
@@ -221,8 +253,14 @@ __device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const IT *
     if (lane == 0) ratio[r] = lik_ratio(gv, wv, acc + (double)wv, eps);
 }
 
+// Sum over the BP_G lanes of a back-projection group (xor butterfly, every
+// lane of the group gets the same value); groups are aligned to BP_G lanes.
 __device__ inline double group_sum(double acc) {
-    for (int o = BP_G / 2; o > 0; o >>= 1) acc = acc + __shfl_xor(acc, o, 64);
+    static_assert(BP_G == 1 || BP_G == 2 || BP_G == 4 || BP_G == 8 || BP_G == 16, "BP_G: 1, 2, 4, 8 or 16");
+    if constexpr (BP_G >= 16) acc = acc + dpp_f64<DPP_MIRROR>(acc);
+    if constexpr (BP_G >= 8) acc = acc + dpp_f64<DPP_HALF_MIRROR>(acc);
+    if constexpr (BP_G >= 4) acc = acc + dpp_f64<DPP_XOR2>(acc);
+    if constexpr (BP_G >= 2) acc = acc + dpp_f64<DPP_XOR1>(acc);
     return acc;
 }
 
