@@ -568,7 +568,6 @@ int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t
     const int r1 = subset < 0 ? A->M : A->row_start[subset + 1];
     float *xt = nullptr;  // each slice in the tiled order of the forward indices
     SVR_HIP(hipMallocAsync((void **)&xt, sizeof(float) * (size_t)A->Nt, s));
-    SVR_HIP(hipMemsetAsync(xt, 0, sizeof(float) * (size_t)A->Nt, s));
     int rc = SVR_OK;
     for (int sl = 0; sl < n_slices && rc == SVR_OK; ++sl) {
         rc = launch_tile_image(*A, x_dev + (int64_t)sl * A->N, xt, s);
@@ -704,7 +703,6 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
         if (!rc) rc = launch_gather_rows(*A, w_dev, R->w, s);
         if (!rc && hipMemcpyAsync(R->f[0], f0_dev, sizeof(float) * N, hipMemcpyDeviceToDevice, s) != hipSuccess)
             rc = SVR_EDEVICE;
-        if (!rc && hipMemsetAsync(R->ft, 0, sizeof(float) * A->Nt, s) != hipSuccess) rc = SVR_EDEVICE;
         if (!rc) rc = launch_tile_image(*A, R->f[0], R->ft, s);
     } else {
         rc = ms_pack_sino(*A, (int)S, g_dev, R->g, s);

@@ -229,13 +229,20 @@ __global__ void k_tile_cols(const IT *col, int64_t n_all, int64_t nnz, int nx, i
     colt[i] = i < nnz ? (IT)tiled_index((int)col[i], nx, tx) : (IT)0;
 }
 
-__global__ void k_tile_image(const float *f, int N, int nx, int tx, float *ft) {
-    const int n = blockIdx.x * blockDim.x + threadIdx.x;
-    if (n < N) ft[tiled_index(n, nx, tx)] = f[n];
+// Every slot p of the tiled copy: the pixel it holds (the inverse of
+// tiled_index_xy), or 0 for the slots of partial tiles outside the image, so
+// the copy needs no clearing first; the writes are coalesced.
+__global__ void k_tile_image(const float *f, int nx, int ny, int tx, int Nt, float *ft) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= Nt) return;
+    const int tile = p / (TILE_W * TILE_H), w = p - tile * (TILE_W * TILE_H);
+    const int ty = tile / tx, tc = tile - ty * tx;
+    const int iy = ty * TILE_H + w / TILE_W, ix = tc * TILE_W + w % TILE_W;
+    ft[p] = (ix < nx && iy < ny) ? f[iy * nx + ix] : 0.0f;
 }
 
 int launch_tile_image(const Matrix &A, const float *f, float *ft, hipStream_t s) {
-    k_tile_image<<<(A.N + 255) / 256, 256, 0, s>>>(f, A.N, A.geom.nx, A.tx, ft);
+    k_tile_image<<<(A.Nt + 255) / 256, 256, 0, s>>>(f, A.geom.nx, A.geom.ny, A.tx, A.Nt, ft);
     SVR_HIP(hipGetLastError());
     return SVR_OK;
 }

@@ -225,6 +225,23 @@ __device__ inline double row_dot(const int *__restrict__ row_ptr, const IT *__re
     return acc;
 }
 
+// sum over t < Ns of x[t * stride + i], FP64, added in t order.  The loads
+// are issued 16 at a time (indices clamped in bounds, the extra values not
+// added): a load per iteration would wait for each one before the next add.
+__device__ inline double subset_sum(const float *__restrict__ x, int Ns, int64_t stride, int64_t i) {
+    constexpr int B = 16;
+    double sum = 0.0;
+    for (int t0 = 0; t0 < Ns; t0 += B) {
+        float v[B];
+#pragma unroll
+        for (int k = 0; k < B; ++k) v[k] = x[(int64_t)min(t0 + k, Ns - 1) * stride + i];
+#pragma unroll
+        for (int k = 0; k < B; ++k)
+            if (t0 + k < Ns) sum = sum + (double)v[k];
+    }
+    return sum;
+}
+
 // EM ratio g / ybar with the zero-denominator rule (0 if g == 0 or ybar <= 0)
 __device__ inline float em_ratio(float g, double yb) {
     return (g > 0.0f && yb > 0.0) ? (float)((double)g / yb) : 0.0f;

@@ -149,11 +149,12 @@ __device__ inline void anchor_entry(const int *__restrict__ ptrT, const IT *__re
     anchor_finish<KIND>(a, Ns, q, n, f, b);
 }
 
-// FP64 sums over t in increasing order
+// Anchor sums of pixel n from the table: SVREM s_anc (and s_hat at a reset),
+// SVRG g_tilde, SAGA / SAGA-EM Q (SAGA-EM also s_hat^0 = s(f^0)); returns the
+// table sum over the subsets.
 template <int KIND>
-__device__ inline void anchor_sum_pixel(const double *__restrict__ sens, int Ns, int N, const SnapArgs &a, int n) {
-    double sum = 0.0;
-    for (int t = 0; t < Ns; ++t) sum = sum + (double)a.table[(int64_t)t * N + n];
+__device__ inline double anchor_sum_pixel(const double *__restrict__ sens, int Ns, int N, const SnapArgs &a, int n) {
+    const double sum = subset_sum(a.table, Ns, N, n);
     if (KIND == UPD_SVREM) {
         const double sa = sum / (double)Ns;
         a.s_anc[n] = sa;
@@ -166,6 +167,7 @@ __device__ inline void anchor_sum_pixel(const double *__restrict__ sens, int Ns,
     } else {
         a.Q[n] = sum;
     }
+    return sum;
 }
 
 // The anchor sums of pixel n followed by the update of the iteration that
@@ -176,38 +178,41 @@ __device__ inline void anchor_sum_pixel(const double *__restrict__ sens, int Ns,
 //   SAGA (table fill at k = 0): q_t(f) - q_t = 0 and Q is unchanged;
 //   SAGA-EM (table fill at k = 0): tau_t(f) - S_t = 0, and the refreshed
 //   entry S_t2 = tau_t2(f) is already in the table (Q unchanged).
+// `a` and `u` name the same state arrays (iterate, table, s_hat, s_anc, Q,
+// g_tilde): the update takes the anchor quantities just computed instead of
+// reading them back, and issues its own loads before the table sum.
 template <int KIND>
 __device__ inline void anchor_sum_update_pixel(const float *__restrict__ sens_t, const double *__restrict__ sens,
                                                int Ns, int N, const SnapArgs &a, const UpdateArgs &u, int n) {
-    anchor_sum_pixel<KIND>(sens, Ns, N, a, n);
     const int64_t q = (int64_t)u.t * N + n;
     const PenaltyArgs &p = u.pen;
+    constexpr bool EM = (KIND == UPD_SVREM || KIND == UPD_SAGAEM);
     const float f = u.f[n];
     const float tab = u.table[q];
+    const double sn = sens[n];
+    const double sh_prev = (KIND == UPD_SVREM) ? u.s_hat[n] : 0.0;  // before a reset overwrites it
+    const float st = !EM ? sens_t[q] : 0.0f;
+    double D = 0.0, E = 0.0;
+    if (EM && p.beta > 0.0) surrogate_at(u.f, n, p, D, E);
+    const double sum = anchor_sum_pixel<KIND>(sens, Ns, N, a, n);
     float out;
     if (KIND == UPD_SVREM) {
-        double D = 0.0, E = 0.0;
-        if (p.beta > 0.0) surrogate_at(u.f, n, p, D, E);
+        const double sa = sum / (double)Ns;  // s_anc[n], and s_hat[n] at a reset
         double sh;
-        out = svrem_math_tau(u.alpha, p.beta, f, tab, u.s_hat[n], tab, u.s_anc[n], sens[n], D, E, &sh);
+        out = svrem_math_tau(u.alpha, p.beta, f, tab, a.init_shat ? sa : sh_prev, tab, sa, sn, D, E, &sh);
         u.s_hat[n] = sh;
     } else if (KIND == UPD_SAGAEM) {
-        double D = 0.0, E = 0.0;
-        if (p.beta > 0.0) surrogate_at(u.f, n, p, D, E);
-        const double sn = sens[n];
         const double sh =
-            (1.0 - u.alpha) * u.s_hat[n] + u.alpha * (((double)tab - (double)tab) + u.Q[n] / (double)u.Ns);
+            (1.0 - u.alpha) * (sum / (double)Ns) + u.alpha * (((double)tab - (double)tab) + sum / (double)u.Ns);
         u.s_hat[n] = sh;
         out = (float)mstep_root(sh, p.beta * D, (p.beta * (double)f * D + p.beta * E) - sn, sn);
     } else {
-        const float st = sens_t[q];
         double dir;
         if (KIND == UPD_SVRG) {
-            dir = ((double)tab - (double)tab) + u.g_tilde[n];
+            dir = ((double)tab - (double)tab) + (sum - sn) / (double)Ns;  // g_tilde[n]
         } else {
-            const double Qn = u.Q[n];
-            dir = ((double)tab - (double)tab) + (Qn - sens[n]) / (double)u.Ns;
-            u.Q[n] = Qn + ((double)tab - (double)tab);
+            dir = ((double)tab - (double)tab) + (sum - sn) / (double)u.Ns;  // Q[n] = sum
+            u.Q[n] = sum + ((double)tab - (double)tab);
         }
         const double d = precond_of(u, q, n, f, st);
         out = (float)fmax(0.0, (double)f + (u.alpha * d) * dir);

@@ -209,8 +209,7 @@ k_ms_anchor_sum(int Ns, int64_t NS, const float *__restrict__ table, double *__r
                 double *__restrict__ s_hat, int init_shat) {
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (i >= NS) return;
-    double sum = 0.0;
-    for (int t = 0; t < Ns; ++t) sum = sum + (double)table[(int64_t)t * NS + i];
+    const double sum = subset_sum(table, Ns, NS, i);
     const double sa = sum / (double)Ns;
     s_anc[i] = sa;
     if (init_shat) s_hat[i] = sa;
