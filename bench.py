@@ -335,7 +335,7 @@ def main():
                                f"alpha={args.alpha}, eta={args.eta}; {args.wtype} weights and FP32 iterate, "
                                f"FP64 products, sums and statistics",
                    "epochs_per_step": epochs_per_step, "nnz": int(inf.nnz), "build_s": round(build_s, 4),
-                   "tuning": {"fwd_rows_per_wave": tuning[0], "bp_rows_per_group": tuning[1]},
+                   "tuning": {"fwd_pairs_per_wave": tuning[0], "bp_rows_per_group": tuning[1]},
                    "objective_after": phi, "parallelism": "single GPU",
                    "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                                for k, v in kernels.items()},

@@ -131,16 +131,20 @@ void svr_matrix_destroy(svr_matrix *A);
 
 /* Run lengths of the passes over the whole matrix (the anchor pass of
  * eq. tempsvrem / eq. svrg_update / eq. saga_update, the objective, and the
- * projectors over all subsets).  A wavefront that owns a run of rows keeps the
- * next row's loads in flight while it sums the current one; the run length
+ * projectors over all subsets).  A forward wavefront sums a pair of
+ * consecutive rows (32 lanes each); one that owns a run of pairs keeps the
+ * next pair's loads in flight while it sums the current one; the run length
  * never changes a row's arithmetic, so every result is bitwise the same under
  * any tuning.  0 means "chosen from the sizes and the device's compute units".
- * A forward pass over no more rows than the device holds wavefronts at once
- * (the per-subset passes at the usual sizes) always runs one row per
+ * A forward pass over no more row pairs than the device holds wavefronts at
+ * once (the per-subset passes at the usual sizes) always runs one pair per
  * wavefront. */
 typedef struct {
-    int32_t fwd_rows_per_wave;   /* rows of A per wavefront, 0..63 */
+    int32_t fwd_pairs_per_wave;  /* pairs of rows of A per wavefront, 0..31 */
     int32_t bp_rows_per_group;   /* (subset, pixel) transposed rows per lane group, 0..1024 */
+    int32_t fwd_pair_rows;       /* forward passes over more rows than this run a pair of rows per
+                                    wavefront, others one row (0: twice the wavefronts the device
+                                    holds at once, 2 * 32 * compute units); >= 0 */
     double  fwd_us, bp_us;       /* svr_matrix_tune: measured duration of the chosen runs */
 } svr_tuning_t;
 

@@ -66,8 +66,8 @@ class svr_kernel_times_t(C.Structure):
 
 
 class svr_tuning_t(C.Structure):
-    _fields_ = [("fwd_rows_per_wave", C.c_int32), ("bp_rows_per_group", C.c_int32),
-                ("fwd_us", C.c_double), ("bp_us", C.c_double)]
+    _fields_ = [("fwd_pairs_per_wave", C.c_int32), ("bp_rows_per_group", C.c_int32),
+                ("fwd_pair_rows", C.c_int32), ("fwd_us", C.c_double), ("bp_us", C.c_double)]
 
 
 class svr_serve_config(C.Structure):
@@ -278,20 +278,29 @@ class SystemMatrix:
         return out
 
     def tuning(self):
-        """Effective run lengths of the whole-matrix passes: (rows per wavefront, rows per lane group)."""
+        """Effective run lengths of the whole-matrix passes: (row pairs per wavefront, rows per lane group)."""
         t = svr_tuning_t()
         _check(lib().svr_matrix_get_tuning(self.h, C.byref(t)))
-        return int(t.fwd_rows_per_wave), int(t.bp_rows_per_group)
+        return int(t.fwd_pairs_per_wave), int(t.bp_rows_per_group)
 
-    def set_tuning(self, fwd_rows_per_wave: int = 0, bp_rows_per_group: int = 0):
-        t = svr_tuning_t(int(fwd_rows_per_wave), int(bp_rows_per_group), 0.0, 0.0)
+    def set_tuning(self, fwd_pairs_per_wave: int = 0, bp_rows_per_group: int = 0, fwd_pair_rows=None):
+        """Sets the run lengths (0: size-based); fwd_pair_rows (None: unchanged) is the row count above
+        which a forward pass runs a pair of rows per wavefront (0: from the device)."""
+        pr = self.pair_rows() if fwd_pair_rows is None else int(fwd_pair_rows)
+        t = svr_tuning_t(int(fwd_pairs_per_wave), int(bp_rows_per_group), pr, 0.0, 0.0)
         _check(lib().svr_matrix_set_tuning(self.h, C.byref(t)))
+
+    def pair_rows(self) -> int:
+        """Effective row count above which a forward pass runs a pair of rows per wavefront."""
+        t = svr_tuning_t()
+        _check(lib().svr_matrix_get_tuning(self.h, C.byref(t)))
+        return int(t.fwd_pair_rows)
 
     def tune(self, stream=None):
         """Autotunes the run lengths on the device; returns (fwd, bp, fwd_us, bp_us)."""
         t = svr_tuning_t()
         _check(lib().svr_matrix_tune(self.h, _stream(stream), C.byref(t)))
-        return int(t.fwd_rows_per_wave), int(t.bp_rows_per_group), float(t.fwd_us), float(t.bp_us)
+        return int(t.fwd_pairs_per_wave), int(t.bp_rows_per_group), float(t.fwd_us), float(t.bp_us)
 
     def project(self, x, subset: int = -1, y=None, stream=None):
         import torch

@@ -205,6 +205,7 @@ int run_epoch_persistent(Recon *R, int algo, int kind, const int32_t *order, int
     e.sens_t = A.d_sens_t;
     e.sens = A.d_sens;
     e.M = A.M;
+    e.pair_rows = A.pair_rows_eff();
     e.N = A.N;
     e.Ns = A.Ns;
     e.g = R->g;

@@ -87,6 +87,11 @@ __host__ __device__ inline int tiled_count(int nx, int ny) {
 __host__ __device__ inline int tiled_index_xy(int ix, int iy, int tx) {
     return ((iy / TILE_H) * tx + ix / TILE_W) * (TILE_W * TILE_H) + (iy % TILE_H) * TILE_W + (ix % TILE_W);
 }
+// Whether a forward pass over `rows` rows runs a pair of rows per wavefront
+// (32 lanes each) instead of one: when it has more rows than `pair_rows`
+// (Matrix::pair_rows_eff: by default twice the wavefronts the device holds
+// at once, 8 per SIMD).
+__host__ __device__ inline bool forward_pairs_for(int64_t rows, int64_t pair_rows) { return rows > pair_rows; }
 __host__ __device__ inline int tiled_index(int n, int nx, int tx) {
     const int iy = n / nx, ix = n - iy * nx;
     return tiled_index_xy(ix, iy, tx);
@@ -116,7 +121,9 @@ struct Matrix {
     double *d_sens = nullptr;       // N
     int64_t bytes = 0;
     int cus = 0;                    // compute units of the device (sizes the whole-matrix runs)
-    int run_fwd = 0;                // rows per wavefront in whole-matrix forward passes (0: by size)
+    int pair_rows = 0;              // forward passes over more rows run in row pairs (0: 2 * 32 * cus)
+    int pair_rows_eff() const { return pair_rows > 0 ? pair_rows : 2 * 32 * (cus > 1 ? cus : 1); }
+    int run_fwd = 0;                // row pairs per wavefront in whole-matrix forward passes (0: by size)
     int run_bp = 0;                 // transposed rows per lane group in whole-matrix back-projections (0: by size)
     int wbytes() const { return wtype == SVR_W_F32 ? 4 : 2; }
     int ibytes() const { return idx16 ? 2 : 4; }
@@ -254,6 +261,7 @@ struct EpochArgs {
     const float *sens_t;
     const double *sens;
     int M, N, Ns;
+    int pair_rows;  // forward phases over more rows run in pairs (forward_pairs_for)
     const float *g, *w;
     float *ratio;
     float *f0, *f1;

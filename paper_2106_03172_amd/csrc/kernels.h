@@ -21,6 +21,9 @@ namespace svr {
 #ifndef SVR_FWD_U
 #define SVR_FWD_U 8
 #endif
+#ifndef SVR_FWD_PAIR_U
+#define SVR_FWD_PAIR_U 12
+#endif
 #ifndef SVR_BP_G
 #define SVR_BP_G 4
 #endif
@@ -28,8 +31,10 @@ namespace svr {
 #define SVR_BP_U 5
 #endif
 constexpr int FWD_THREADS = 256;               // forward: 4 wavefronts per block
-constexpr int FWD_ROWS_PER_BLOCK = FWD_THREADS / 64;
-constexpr int FWD_U = SVR_FWD_U;               // loads in flight per lane (64*8 = 512 nnz per batch)
+constexpr int FWD_WAVES_PER_BLOCK = FWD_THREADS / 64;
+constexpr int FWD_U = SVR_FWD_U;               // loads in flight per lane, one row per wavefront (64*8 = 512
+                                               // entries per batch: the longest row of the 256x256 matrix)
+constexpr int FWD_PAIR_U = SVR_FWD_PAIR_U;     // the same for a pair of rows (32*12 = 384 entries of each)
 constexpr int BP_G = SVR_BP_G;                 // back-projection lanes per pixel
 constexpr int BP_U = SVR_BP_U;                 // loads in flight per lane (4*5 = 20 nnz per batch: one
                                                // batch covers a whole transposed subset row of a 2 mm
@@ -37,7 +42,7 @@ constexpr int BP_U = SVR_BP_U;                 // loads in flight per lane (4*5 
                                                // 5 beat 4, 6, 7 and 8 in measured anchor-table time)
 constexpr int BP_THREADS = 256;
 #ifndef SVR_FWD_RUN_U
-#define SVR_FWD_RUN_U 4
+#define SVR_FWD_RUN_U 8
 #endif
 #ifndef SVR_BP_RUN_U
 #define SVR_BP_RUN_U 5
@@ -85,19 +90,28 @@ __device__ inline double readlane_f64(double v, int l) {
     return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
 }
 
-// Sum over the 64 lanes of a wavefront, the same value in every lane, in a
-// fixed order: lane pairs, quads, 8s and 16s by DPP moves (after each step
-// every lane of the group holds the group's sum: a + b and b + a are the
-// same number), then the four 16-lane rows as (r0 + r1) + (r2 + r3).  Every
-// lane of the wavefront must call it (the rows are read with readlane).
-// DPP moves stay in the vector ALU; a shuffle would go through the LDS
-// crossbar, one round trip per 32-bit half and step.
-__device__ inline double wave_sum(double v) {
+// Sums over the two 32-lane halves of a wavefront, the same values in every
+// lane, in a fixed order: lane pairs, quads, 8s and 16s by DPP moves (after
+// each step every lane of the group holds the group's sum: a + b and b + a
+// are the same number), then the 16-lane rows as s0 = r0 + r1 (lanes 0-31)
+// and s1 = r2 + r3 (lanes 32-63).  Every lane of the wavefront must call it
+// (the rows are read with readlane).  DPP moves stay in the vector ALU; a
+// shuffle would go through the LDS crossbar, one round trip per 32-bit half
+// and step.
+__device__ inline void half_sums(double v, double &s0, double &s1) {
     v = v + dpp_f64<DPP_XOR1>(v);
     v = v + dpp_f64<DPP_XOR2>(v);
     v = v + dpp_f64<DPP_HALF_MIRROR>(v);
     v = v + dpp_f64<DPP_MIRROR>(v);
-    return (readlane_f64(v, 0) + readlane_f64(v, 16)) + (readlane_f64(v, 32) + readlane_f64(v, 48));
+    s0 = readlane_f64(v, 0) + readlane_f64(v, 16);
+    s1 = readlane_f64(v, 32) + readlane_f64(v, 48);
+}
+
+// Sum over the 64 lanes of a wavefront, (r0 + r1) + (r2 + r3) as above.
+__device__ inline double wave_sum(double v) {
+    double s0, s1;
+    half_sums(v, s0, s1);
+    return s0 + s1;
 }
 
 // ---- range-checked buffer loads ----------------------------------------------
@@ -177,6 +191,31 @@ struct RowBatch {
             v[u] = vi;
         }
     }
+    // One batch of a pair of consecutive rows owned by a wavefront (L = 32):
+    // the row of half h = lane >> 5 spans [b0, e0) (h = 0) or [e0, e1)
+    // (h = 1), and lane hl = lane & 31 holds its entries beg_h + k + hl + 32 u.
+    // Both halves read through one range-checked resource from the first
+    // row's batch start b0 + k to the second row's end, so slots past a row's
+    // end fetch the other row's entries (masked) or nothing.  b0, e0, e1 and
+    // k are wavefront-uniform.
+    __device__ inline void load_pair(const IT *__restrict__ idx, const WT *__restrict__ val, int b0, int e0, int e1,
+                                     int k, int lane) {
+        static_assert(L == 32, "a pair batch has 32 lanes per row");
+        const int h = lane >> 5, hl = lane & 31;
+        const int wb = b0 + k, n = max(e1 - wb, 0);
+        const __amdgpu_buffer_rsrc_t ri = range_rsrc(idx + wb, n * (int)sizeof(IT));
+        const __amdgpu_buffer_rsrc_t rv = range_rsrc(val + wb, n * (int)sizeof(WT));
+        const int beg = h ? e0 : b0, end = h ? e1 : e0;
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int i = beg + k + hl + L * u;
+            const int o = i - wb;
+            const int ci = (int)buf_load<IT>(ri, o * (int)sizeof(IT));
+            const float vi = load_w(buf_load<WT>(rv, o * (int)sizeof(WT)));
+            c[u] = i < end ? ci : -1;
+            v[u] = vi;
+        }
+    }
     __device__ inline void gather(const float *__restrict__ x, float (&xv)[U]) const {
 #pragma unroll
         for (int u = 0; u < U; ++u) xv[u] = x[c[u] >= 0 ? c[u] : 0];
@@ -206,9 +245,12 @@ __device__ inline double row_rest(const IT *__restrict__ idx, const WT *__restri
     return acc;
 }
 
+// ---- forward rows ----------------------------------------------------------------
 // (A f)_r: the lanes of a wavefront stride over row r's non-zeros in batches
 // of 64 * FWD_U, FP64 products; lane j adds entries beg + j, beg + j + 64, ...
-// in that order (the same entries and order as fwd_run's).
+// in that order.  The per-subset passes, whose rows fit in the wavefronts the
+// device holds at once, run one row per wavefront: their time is one
+// wavefront's latency chain, which a pair per wavefront lengthens.
 template <typename WT, typename IT>
 __device__ inline double row_dot(const int *__restrict__ row_ptr, const IT *__restrict__ col,
                                  const WT *__restrict__ val, const float *__restrict__ f, int r, int lane) {
@@ -219,6 +261,32 @@ __device__ inline double row_dot(const int *__restrict__ row_ptr, const IT *__re
         RowBatch<64, FWD_U, WT, IT> b;
         float xv[FWD_U];
         b.load_wave(col, val, bb, end, lane);
+        b.gather(f, xv);
+        acc = b.fma(xv, acc);
+    }
+    return acc;
+}
+
+// ---- forward rows in pairs ------------------------------------------------------
+// A wavefront owns a pair of consecutive rows r, r + 1 of A: the 32 lanes of
+// half h = lane >> 5 take row r + h, lane hl = lane & 31 adding the entries
+// beg + hl, beg + hl + 32, ... of its row in that order (FP64 fused
+// multiply-adds), and half_sums adds each half's lanes.  A whole-matrix pass
+// is bounded by the index/weight bytes a wavefront streams per lifetime (row
+// pointers -> index/weight -> gathers -> sum); a pair per wavefront doubles
+// them.
+
+// lane partial of the pair with bounds b0 <= e0 <= e1 (e1 == e0: no second
+// row), all wavefront-uniform
+template <typename WT, typename IT>
+__device__ inline double pair_dot(const IT *__restrict__ col, const WT *__restrict__ val,
+                                  const float *__restrict__ f, int b0, int e0, int e1, int lane) {
+    const int len = max(e0 - b0, e1 - e0);
+    double acc = 0.0;
+    for (int k = 0; k < len; k += 32 * FWD_PAIR_U) {
+        RowBatch<32, FWD_PAIR_U, WT, IT> b;
+        float xv[FWD_PAIR_U];
+        b.load_pair(col, val, b0, e0, e1, k, lane);
         b.gather(f, xv);
         acc = b.fma(xv, acc);
     }
@@ -270,6 +338,24 @@ __device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const IT *
     if (lane == 0) ratio[r] = lik_ratio(gv, wv, acc + (double)wv, eps);
 }
 
+// Forward of rows r and r + 1 (the second only if r + 1 < r1) with each
+// row's ratio written to ratio[row]; every lane of the wavefront calls it
+// with the same r < r1.
+template <typename WT, typename IT>
+__device__ inline void fwd_ratio_pair(const int *__restrict__ row_ptr, const IT *__restrict__ col,
+                                      const WT *__restrict__ val, const float *__restrict__ f,
+                                      const float *__restrict__ g, const float *__restrict__ w,
+                                      float *__restrict__ ratio, int r, int r1, int lane, double eps) {
+    r = __builtin_amdgcn_readfirstlane(r);  // scalar row bounds
+    const int h = lane >> 5, rh = r + h;
+    const int rl = min(rh, r1 - 1);  // in bounds; a missing second row writes nothing
+    const float gv = g[rl], wv = w[rl];
+    const int b0 = row_ptr[r], e0 = row_ptr[r + 1], e1 = row_ptr[min(r + 2, r1)];
+    double s0, s1;
+    half_sums(pair_dot(col, val, f, b0, e0, e1, lane), s0, s1);
+    if ((lane & 31) == 0 && rh < r1) ratio[rh] = lik_ratio(gv, wv, (h ? s1 : s0) + (double)wv, eps);
+}
+
 // Sum over the BP_G lanes of a back-projection group (xor butterfly, every
 // lane of the group gets the same value); groups are aligned to BP_G lanes.
 __device__ inline double group_sum(double acc) {
@@ -287,7 +373,7 @@ template <typename WT, typename IT>
 __device__ inline double bp_range(const IT *__restrict__ rowT, const WT *__restrict__ valT, int beg, int end,
                                   const float *__restrict__ y, int lig) {
     double acc = 0.0;
-    for (int base = beg + lig; base < end; base += BP_G * BP_U) {  // as row_dot
+    for (int base = beg + lig; base < end; base += BP_G * BP_U) {
         RowBatch<BP_G, BP_U, WT, IT> b;
         float xv[BP_U];
         b.load(rowT, valT, base, end);
@@ -305,38 +391,50 @@ __device__ inline double bp_group(const int *__restrict__ ptrT, const IT *__rest
 }
 
 // ---- pipelined row runs -------------------------------------------------------
-// A wavefront that owns a run of rows [ra, ra + nr) of A walks them with the
-// first index/weight batch of row i+1 in flight while it gathers and sums
-// row i (the run's row pointers are loaded up front, one per lane), so each
-// row costs about one memory latency instead of three.  `fin(i, acc)` gets
-// the wavefront-reduced sum of row ra + i; nr <= 63.
+// A wavefront that owns a run of rows [ra, ra + nr) of A (nr <= 62) walks it
+// in pairs (ra + 2i, ra + 2i + 1) with the first index/weight batch of pair
+// i + 1 in flight while it gathers and sums pair i (the run's row pointers
+// are loaded up front, one per lane), so each pair costs about one memory
+// latency instead of three.  The entries each lane adds, and their order, are
+// pair_dot's.  `fin(i, s0, s1)` gets the sums of pair i's two rows (s1 = 0
+// for a missing second row).
 template <typename WT, typename IT, class Fin>
 __device__ inline void fwd_run(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
                                const float *__restrict__ f, int ra, int nr, int lane, Fin fin) {
-    const int rp = lane <= nr ? row_ptr[ra + lane] : 0;
-    int beg = __builtin_amdgcn_readlane(rp, 0), end = __builtin_amdgcn_readlane(rp, 1);
-    RowBatch<64, FWD_RUN_U, WT, IT> cur;
-    cur.load_wave(col, val, beg, end, lane);
-    for (int i = 0; i < nr; ++i) {
+    const int rp = row_ptr[ra + min(lane, nr)];  // lanes past nr repeat the run's end
+    const int np = (nr + 1) / 2;
+    auto bounds = [&](int i, int &b0, int &e0, int &e1) {
+        b0 = __builtin_amdgcn_readlane(rp, 2 * i);
+        e0 = __builtin_amdgcn_readlane(rp, min(2 * i + 1, nr));
+        e1 = __builtin_amdgcn_readlane(rp, min(2 * i + 2, nr));
+    };
+    int b0, e0, e1;
+    bounds(0, b0, e0, e1);
+    RowBatch<32, FWD_RUN_U, WT, IT> cur;
+    cur.load_pair(col, val, b0, e0, e1, 0, lane);
+    for (int i = 0; i < np; ++i) {
         float xv[FWD_RUN_U];
         cur.gather(f, xv);
-        int nbeg = 0, nend = 0;
-        RowBatch<64, FWD_RUN_U, WT, IT> nxt;
-        if (i + 1 < nr) {
-            nbeg = __builtin_amdgcn_readlane(rp, i + 1);
-            nend = __builtin_amdgcn_readlane(rp, i + 2);
-            nxt.load_wave(col, val, nbeg, nend, lane);
+        int nb0 = 0, ne0 = 0, ne1 = 0;
+        RowBatch<32, FWD_RUN_U, WT, IT> nxt;
+        if (i + 1 < np) {
+            bounds(i + 1, nb0, ne0, ne1);
+            nxt.load_pair(col, val, nb0, ne0, ne1, 0, lane);
         }
         double acc = cur.fma(xv, 0.0);
-        for (int bb = beg + 64 * FWD_RUN_U; bb < end; bb += 64 * FWD_RUN_U) {  // as row_rest
-            RowBatch<64, FWD_RUN_U, WT, IT> b;
-            b.load_wave(col, val, bb, end, lane);
+        const int len = max(e0 - b0, e1 - e0);
+        for (int k = 32 * FWD_RUN_U; k < len; k += 32 * FWD_RUN_U) {  // as pair_dot
+            RowBatch<32, FWD_RUN_U, WT, IT> b;
+            b.load_pair(col, val, b0, e0, e1, k, lane);
             b.gather(f, xv);
             acc = b.fma(xv, acc);
         }
-        fin(i, wave_sum(acc));
-        beg = nbeg;
-        end = nend;
+        double s0, s1;
+        half_sums(acc, s0, s1);
+        fin(i, s0, s1);
+        b0 = nb0;
+        e0 = ne0;
+        e1 = ne1;
         cur = nxt;
     }
 }

@@ -97,8 +97,13 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
         float *fo = cur ? e.f0 : e.f1;
         const bool anchor = vr_anchor ? (k % ((long long)e.eta * Ns) == 0) : (KIND == UPD_SAGA && k == 0);
         if (anchor) {
-            for (int r = gwave; r < e.M; r += nwaves)
-                fwd_ratio_row(e.row_ptr, col, val, e.ft, e.g, e.w, e.ratio, r, lane, e.eps);
+            if (forward_pairs_for(e.M, e.pair_rows)) {
+                for (int r = 2 * gwave; r < e.M; r += 2 * nwaves)
+                    fwd_ratio_pair(e.row_ptr, col, val, e.ft, e.g, e.w, e.ratio, r, e.M, lane, e.eps);
+            } else {
+                for (int r = gwave; r < e.M; r += nwaves)
+                    fwd_ratio_row(e.row_ptr, col, val, e.ft, e.g, e.w, e.ratio, r, lane, e.eps);
+            }
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
             SnapArgs sa{};
             sa.ratio_all = e.ratio;
@@ -124,8 +129,13 @@ __global__ void __launch_bounds__(PT_THREADS) k_epoch(EpochArgs e) {
         }
         {
             const int r0 = e.row_start[t], r1 = e.row_start[t + 1];
-            for (int r = r0 + gwave; r < r1; r += nwaves)
-                fwd_ratio_row(e.row_ptr, col, val, e.ft, e.g, e.w, e.ratio, r, lane, e.eps);
+            if (forward_pairs_for(r1 - r0, e.pair_rows)) {
+                for (int r = r0 + 2 * gwave; r < r1; r += 2 * nwaves)
+                    fwd_ratio_pair(e.row_ptr, col, val, e.ft, e.g, e.w, e.ratio, r, r1, lane, e.eps);
+            } else {
+                for (int r = r0 + gwave; r < r1; r += nwaves)
+                    fwd_ratio_row(e.row_ptr, col, val, e.ft, e.g, e.w, e.ratio, r, lane, e.eps);
+            }
             if (!grid_barrier(e.sync, gen, &abort_lds)) goto aborted;
             UpdateArgs u{};
             u.t = t;

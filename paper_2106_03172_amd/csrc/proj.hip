@@ -1,17 +1,19 @@
 // Projectors: forward rows of A (with the fused EM ratio or log-likelihood)
 // and the gather-only transposed back-projection.
 //
-// Forward: one 64-lane wavefront per row of A, lanes striding over the row's
-// non-zeros (coalesced reads of the index and weight streams, image gathers
-// from L2), FP64 products and a fixed butterfly reduction, so a row always
-// sums in the same order whichever call computes it.
+// Forward: one 64-lane wavefront per row of A (passes that fit in the
+// wavefronts the device holds at once: the per-subset passes) or per pair of
+// consecutive rows, 32 lanes per row (larger passes: the whole matrix), lanes
+// striding over the row's non-zeros (coalesced, range-checked reads of the
+// index and weight streams, image gathers from L2), FP64 products and a fixed
+// reduction, so a row sums in the same order in every pass of its kind.
 //
 // Back-projection: BP_G lanes per pixel over that pixel's transposed row of
 // subset t, FP64 products, fixed butterfly reduction.
 //
 // Passes over many more rows than the device holds wavefronts (the whole
-// matrix) give each wavefront a run of consecutive rows and pipeline them
-// (fwd_run, bp_run): per row the arithmetic is the one-row code's, so the
+// matrix) can give each wavefront a run of consecutive rows and pipeline them
+// (fwd_run, bp_run): per row the arithmetic is the one-pair code's, so the
 // results do not depend on the run length.
 #include <cmath>
 
@@ -37,36 +39,54 @@ __device__ inline double loglik_term(float g, float w, double yb, double eps, in
     return -yb;
 }
 
-// one wavefront per row; mode 2 writes the row's log-likelihood term to
+// one wavefront per row r (PAIR: per pair of rows r, r + 1); mode 0 writes
+// y[row_sino[r]], mode 1 the ratio, mode 2 the row's log-likelihood term to
 // part[r - r0] (summed afterwards in a fixed order)
-template <int MODE, typename WT, typename IT>
+template <int MODE, bool PAIR, typename WT, typename IT>
 __global__ void __launch_bounds__(FWD_THREADS)
 k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
           const int *__restrict__ row_sino, int r0, int r1, FwdArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int r = r0 + blockIdx.x * FWD_ROWS_PER_BLOCK + wv;
-    if (MODE == 1) {  // wave-uniform: the wave either has a row or not
-        if (r < r1) fwd_ratio_row(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane, a.eps);
+    const int r = r0 + (PAIR ? 2 : 1) * (blockIdx.x * FWD_WAVES_PER_BLOCK + wv);
+    if (r >= r1) return;  // wave-uniform
+    if constexpr (!PAIR) {
+        if (MODE == 1) {
+            fwd_ratio_row(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane, a.eps);
+            return;
+        }
+        const double acc = wave_sum(row_dot(row_ptr, col, val, a.f, r, lane));
+        if (lane != 0) return;
+        if (MODE == 0) a.out[row_sino[r]] = (float)acc;
+        else a.part[r - r0] = loglik_term(a.g[r], a.w[r], acc + (double)a.w[r], a.eps, a.bad);
         return;
     }
-    if (r >= r1) return;  // wave-uniform
-    const double acc = wave_sum(row_dot(row_ptr, col, val, a.f, r, lane));
-    if (lane != 0) return;
-    if (MODE == 0) a.out[row_sino[r]] = (float)acc;
-    else a.part[r - r0] = loglik_term(a.g[r], a.w[r], acc + (double)a.w[r], a.eps, a.bad);
+    if (MODE == 1) {
+        fwd_ratio_pair(row_ptr, col, val, a.f, a.g, a.w, a.out, r, r1, lane, a.eps);
+        return;
+    }
+    const int ru = __builtin_amdgcn_readfirstlane(r);
+    const int b0 = row_ptr[ru], e0 = row_ptr[ru + 1], e1 = row_ptr[min(ru + 2, r1)];
+    double s0, s1;
+    half_sums(pair_dot(col, val, a.f, b0, e0, e1, lane), s0, s1);
+    const int h = lane >> 5, rh = ru + h;
+    if ((lane & 31) != 0 || rh >= r1) return;
+    const double acc = h ? s1 : s0;
+    if (MODE == 0) a.out[row_sino[rh]] = (float)acc;
+    else a.part[rh - r0] = loglik_term(a.g[rh], a.w[rh], acc + (double)a.w[rh], a.eps, a.bad);
 }
 
-// rows [ra, ra + R) per wavefront, pipelined; the run's per-row operands and
-// results are held one per lane, so they are read and written coalesced
+// R pairs of rows [ra, ra + 2R) per wavefront, pipelined; the run's per-row
+// operands and results are held one per lane, so they are read and written
+// coalesced
 template <int MODE, typename WT, typename IT>
 __global__ void __launch_bounds__(FWD_THREADS)
 k_forward_run(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
               const int *__restrict__ row_sino, int r0, int r1, int R, FwdArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int64_t ra64 = (int64_t)r0 + ((int64_t)blockIdx.x * FWD_ROWS_PER_BLOCK + wv) * R;
-    const int nr = ra64 < r1 ? (int)min((int64_t)R, (int64_t)r1 - ra64) : 0;
+    const int64_t ra64 = (int64_t)r0 + ((int64_t)blockIdx.x * FWD_WAVES_PER_BLOCK + wv) * 2 * R;
+    const int nr = ra64 < r1 ? (int)min((int64_t)2 * R, (int64_t)r1 - ra64) : 0;
     const int ra = nr > 0 ? (int)ra64 : r0;
     float gl = 0.0f, wl = 0.0f;
     int sl = 0;
@@ -77,8 +97,9 @@ k_forward_run(const int *__restrict__ row_ptr, const IT *__restrict__ col, const
     if (nr == 0) return;  // wave-uniform
     float outv = 0.0f;
     double term = 0.0;
-    fwd_run<WT, IT>(row_ptr, col, val, a.f, ra, nr, lane, [&](int i, double acc) {
-        if (lane != i) return;
+    fwd_run<WT, IT>(row_ptr, col, val, a.f, ra, nr, lane, [&](int i, double s0, double s1) {
+        if (lane != 2 * i && lane != 2 * i + 1) return;
+        const double acc = lane == 2 * i ? s0 : s1;
         if (MODE == 0) outv = (float)acc;
         else if (MODE == 1) outv = lik_ratio(gl, wl, acc + (double)wl, a.eps);
         else term = loglik_term(gl, wl, acc + (double)wl, a.eps, a.bad);
@@ -89,24 +110,34 @@ k_forward_run(const int *__restrict__ row_ptr, const IT *__restrict__ col, const
     else a.part[ra - r0 + lane] = term;
 }
 
-// Rows per wavefront for a pass over `rows` rows: 1 while the rows fit in the
-// wavefronts the device holds at once (8 per SIMD; the per-subset passes),
-// else the tuned run length, by default 2 (the run kernel holds two rows'
-// operands in registers, which costs occupancy; longer runs lose more than
-// the overlap gains at the sizes measured).
+// Whether a forward pass over `rows` rows runs a pair of rows per wavefront:
+// by default when the rows are more than twice the wavefronts the device
+// holds at once (8 per SIMD), i.e. the whole-matrix passes at the usual
+// sizes, whose time is set by the bytes each wavefront streams per lifetime.
+// A pass that fits runs one row per wavefront (its time is one wavefront's
+// latency chain).  The persistent epoch kernel takes the same decision for
+// its passes.
+bool forward_pairs(const Matrix &A, int rows) { return forward_pairs_for(rows, A.pair_rows_eff()); }
+
+// Row pairs per wavefront of a pass that runs in pairs: the tuned run length,
+// by default 1 (the run kernel holds two pairs' operands in registers, which
+// costs occupancy; svr_matrix_tune measures whether runs pay off).
 int forward_run_length(const Matrix &A, int rows) {
-    const int64_t slots = (int64_t)std::max(A.cus, 1) * 32;
-    if (rows <= slots) return 1;
-    return A.run_fwd > 0 ? std::min(A.run_fwd, 63) : 2;
+    (void)rows;
+    return A.run_fwd > 0 ? std::min(A.run_fwd, 31) : 1;
 }
 
 template <int MODE>
-static int launch_forward_t(const Matrix &A, int r0, int r1, int R, const FwdArgs &a, hipStream_t s, int nb) {
+static int launch_forward_t(const Matrix &A, int r0, int r1, bool pair, int R, const FwdArgs &a, hipStream_t s,
+                            int nb) {
     return with_types(A, [&](auto w, auto i) {
         using WT = decltype(w);
         using IT = decltype(i);
-        if (R == 1)
-            SVR_HIP(launch_k(k_forward<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
+        if (!pair)
+            SVR_HIP(launch_k(k_forward<MODE, false, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
+                             (const WT *)A.d_val, A.d_row_sino, r0, r1, a));
+        else if (R == 1)
+            SVR_HIP(launch_k(k_forward<MODE, true, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
                              (const WT *)A.d_val, A.d_row_sino, r0, r1, a));
         else
             SVR_HIP(launch_k(k_forward_run<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
@@ -117,14 +148,15 @@ static int launch_forward_t(const Matrix &A, int r0, int r1, int R, const FwdArg
 
 int launch_forward(const Matrix &A, int r0, int r1, int mode, const FwdArgs &a, hipStream_t s, int *nbo) {
     const int rows = r1 - r0;
-    const int R = rows > 0 ? forward_run_length(A, rows) : 1;
-    const int64_t waves = rows > 0 ? ((int64_t)rows + R - 1) / R : 0;
-    const int nb = (int)((waves + FWD_ROWS_PER_BLOCK - 1) / FWD_ROWS_PER_BLOCK);
+    const bool pair = rows > 0 && forward_pairs(A, rows);
+    const int R = pair ? forward_run_length(A, rows) : 1;
+    const int64_t waves = !pair ? (int64_t)std::max(rows, 0) : (((int64_t)rows + 1) / 2 + R - 1) / R;
+    const int nb = (int)((waves + FWD_WAVES_PER_BLOCK - 1) / FWD_WAVES_PER_BLOCK);
     if (nbo) *nbo = mode == 2 ? rows : nb;
     if (nb == 0) return SVR_OK;
-    if (mode == 0) return launch_forward_t<0>(A, r0, r1, R, a, s, nb);
-    if (mode == 1) return launch_forward_t<1>(A, r0, r1, R, a, s, nb);
-    return launch_forward_t<2>(A, r0, r1, R, a, s, nb);
+    if (mode == 0) return launch_forward_t<0>(A, r0, r1, pair, R, a, s, nb);
+    if (mode == 1) return launch_forward_t<1>(A, r0, r1, pair, R, a, s, nb);
+    return launch_forward_t<2>(A, r0, r1, pair, R, a, s, nb);
 }
 
 // x[n] = sum over subset t's transposed row (t = -1: all subsets, in t order,

@@ -96,7 +96,7 @@ int tune(Matrix &A, hipStream_t s, svr_tuning_t *out) {
     A.run_bp = 1;
     for (int R : {1, 2, 3, 4, 6, 8, 12, 16}) {
         if (rc) break;
-        if (R > 1 && (int64_t)A.M < (int64_t)R * std::max(A.cus, 1) * 4) break;  // fewer waves than SIMDs
+        if (R > 1 && ((int64_t)A.M + 1) / 2 < (int64_t)R * std::max(A.cus, 1) * 4) break;  // fewer waves than SIMDs
         A.run_fwd = R;
         double uf = 0.0, ut = 0.0;
         rc = pair_time(&uf, &ut);
@@ -118,8 +118,9 @@ int tune(Matrix &A, hipStream_t s, svr_tuning_t *out) {
         A.run_fwd = best_f;
         A.run_bp = best_b;
         if (out) {
-            out->fwd_rows_per_wave = best_f;
+            out->fwd_pairs_per_wave = best_f;
             out->bp_rows_per_group = best_b;
+            out->fwd_pair_rows = A.pair_rows_eff();
             out->fwd_us = us_f;
             out->bp_us = us_b;
         }
@@ -137,8 +138,9 @@ extern "C" {
 int svr_matrix_get_tuning(const svr_matrix *A, svr_tuning_t *t) {
     svr::clear_error();
     SVR_REQUIRE(A && t, "NULL argument");
-    t->fwd_rows_per_wave = A->run_fwd > 0 ? A->run_fwd : svr::forward_run_length(*A, A->M);
+    t->fwd_pairs_per_wave = A->run_fwd > 0 ? A->run_fwd : svr::forward_run_length(*A, A->M);
     t->bp_rows_per_group = svr::table_run_length(*A);
+    t->fwd_pair_rows = A->pair_rows_eff();
     t->fwd_us = 0.0;
     t->bp_us = 0.0;
     return SVR_OK;
@@ -147,9 +149,11 @@ int svr_matrix_get_tuning(const svr_matrix *A, svr_tuning_t *t) {
 int svr_matrix_set_tuning(svr_matrix *A, const svr_tuning_t *t) {
     svr::clear_error();
     SVR_REQUIRE(A && t, "NULL argument");
-    SVR_REQUIRE(t->fwd_rows_per_wave >= 0 && t->fwd_rows_per_wave <= 63, "fwd_rows_per_wave must be in [0, 63]");
+    SVR_REQUIRE(t->fwd_pairs_per_wave >= 0 && t->fwd_pairs_per_wave <= 31, "fwd_pairs_per_wave must be in [0, 31]");
     SVR_REQUIRE(t->bp_rows_per_group >= 0 && t->bp_rows_per_group <= 1024, "bp_rows_per_group must be in [0, 1024]");
-    A->run_fwd = t->fwd_rows_per_wave;
+    SVR_REQUIRE(t->fwd_pair_rows >= 0, "fwd_pair_rows must be >= 0");
+    A->run_fwd = t->fwd_pairs_per_wave;
+    A->pair_rows = t->fwd_pair_rows;
     A->run_bp = t->bp_rows_per_group;
     return SVR_OK;
 }

@@ -1,8 +1,9 @@
 """GPU: the run lengths of the whole-matrix passes (svr_matrix_set_tuning /
 svr_matrix_tune) never change a result.
 
-A run length only decides which wavefront (or lane group) sums a row; the
-row's own arithmetic is the same code at every setting, so projections over
+A run length only decides which wavefront (or lane group) sums a row (a
+forward wavefront sums pairs of rows, 32 lanes each); the row's own
+arithmetic is the same code at every setting, so projections over
 all subsets, back-projections, the objective and whole epochs of the
 variance-reduced methods must be bitwise identical under every tuning,
 including ragged last runs (rows not a multiple of the run length) and runs
@@ -21,7 +22,7 @@ pytestmark = pytest.mark.gpu
 
 import paper_2106_03172_amd as pkg  # noqa: E402
 
-TUNINGS = [(1, 1), (2, 3), (7, 5), (13, 16), (63, 1024), (0, 0)]
+TUNINGS = [(1, 1), (2, 3), (7, 5), (13, 16), (31, 1024), (0, 0)]
 
 
 def rel(a, b):
@@ -74,7 +75,7 @@ def test_results_are_bitwise_independent_of_tuning(shape):
             assert np.array_equal(np.asarray(got[k]), np.asarray(ref[k])), (k, fw, bp)
     tuned = A.tune()
     print("tuned", tuned, flush=True)
-    assert 1 <= tuned[0] <= 63 and 1 <= tuned[1] <= 1024 and tuned[2] > 0 and tuned[3] > 0
+    assert 1 <= tuned[0] <= 31 and 1 <= tuned[1] <= 1024 and tuned[2] > 0 and tuned[3] > 0
     assert A.tuning() == tuned[:2]
     got = run_all(P, A, x, y, f0, order)
     for k in ref:
@@ -91,11 +92,11 @@ def test_results_are_bitwise_independent_of_tuning(shape):
 def test_tuning_rejects_out_of_range():
     P = datagen.make_problem(**datagen.CONFIG_SMALL)
     A = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32, mu=P.mu)
-    for bad in ((-1, 0), (64, 0), (0, -1), (0, 1025)):
+    for bad in ((-1, 0), (32, 0), (0, -1), (0, 1025)):
         with pytest.raises(pkg.SvrError):
             A.set_tuning(*bad)
-    A.set_tuning(63, 1024)
-    assert A.tuning() == (63, 1024)
+    A.set_tuning(31, 1024)
+    assert A.tuning() == (31, 1024)
     A.set_tuning(0, 0)
     fw, bp = A.tuning()
     assert fw >= 1 and bp >= 1
