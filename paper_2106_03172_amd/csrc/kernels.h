@@ -1,7 +1,8 @@
 // Device building blocks shared by the projector and update kernels.  Every
-// reduction here has a fixed order, so a quantity computed by two different
-// kernels (an anchor table entry and the same quantity in a later iteration)
-// is bitwise identical.
+// reduction here has a fixed order, so a quantity computed by two kernels
+// through the same function (a back-projected table entry at an anchor and
+// the same back-projection in a later iteration; a forward row in the
+// per-phase and in the persistent kernels) is bitwise identical.
 //
 // The sparse loops are written load-phase-first: each lane issues all index
 // and weight loads of a batch, then all gathers, then the FP64 products, so a

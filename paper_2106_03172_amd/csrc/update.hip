@@ -17,7 +17,9 @@
 //         s_hat <- (1-a) s_hat + a (tau_t - S_t + Q/Ns); S_t2 <- tau_t2; f+ = root(...)
 // Running statistics and table sums are FP64; tables and the iterate FP32.
 // The quantities stored in a table at an anchor are computed by the same
-// device functions as in the iterations, so they cancel exactly at f = f_anc.
+// back-projection and update expressions as in the iterations; the iteration
+// that takes the anchor uses the table entry itself (anchor_sum_update_pixel),
+// so its anchor terms cancel exactly.
 #include <cmath>
 
 #include "common.h"
