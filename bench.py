@@ -186,13 +186,14 @@ def main():
     ap.add_argument("--eta", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--workload", choices=("headline", "multislice", "serve", "copy", "convergence"),
+    ap.add_argument("--workload", choices=("headline", "multislice", "serve", "serve-compare", "copy",
+                                           "convergence"),
                     default="headline",
-                    help="headline: the JSON line below; multislice / serve / convergence: supplementary "
-                         "measurements")
+                        help="headline: the JSON line below; multislice / serve / serve-compare / convergence: "
+                         "supplementary measurements")
     ap.add_argument("--epochs", type=float, default=50, help="convergence: epochs per curve")
     ap.add_argument("--curves-out", default="", help="convergence: write every curve as JSON to this file")
-    ap.add_argument("--requests", type=int, default=48, help="serve: number of requests")
+    ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
     ap.add_argument("--persistent", action="store_true",
                     help="one persistent cooperative kernel per epoch call instead of one kernel per phase")
     args = ap.parse_args()
@@ -215,6 +216,8 @@ def main():
         return bench_multislice(args)
     if args.workload == "serve":
         return bench_serve(args)
+    if args.workload == "serve-compare":
+        return bench_serve_compare(args)
     if args.workload == "convergence":
         return bench_convergence(args)
     if args.workload == "copy":
@@ -486,6 +489,90 @@ def bench_serve(args):
                       "achieved_rps": round(n / total, 3), "p50_ms": round(float(np.percentile(lat, 50)), 2),
                       "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2),
                       "all_ok": ok, "epochs_per_request": specs[0]["epochs"]}), flush=True)
+
+
+def bench_serve_compare(args):
+    """The same set of serving requests (sizes and counts as bench_serve, SVREM, 30 epochs each, the
+    subset sequence of each request from its seed) three ways: the plain per-request path (FP32
+    weights; build the matrix, one OSEM epoch, the SVREM epochs, one request after the other,
+    through SystemMatrix / Recon), and the continuous-batching server with every request submitted
+    at once, with FP32, BF16 and FP16 weights.  Reports SVREM epochs/s of each and, over the
+    requests, the relative L2 difference of the batched half-precision results from the per-request
+    FP32 ones (the GPU tests pin each weight type against the FP64 oracle)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2106_03172_amd as pkg
+    n = min(args.requests, 64)
+    specs = datagen.serving_requests(n, 1.0, seed=0)
+    log(f"generating {n} requests")
+    data = [datagen.make_problem(r["nx"], r["ny"], r["pixel_mm"], r["n_views"], r["n_bins"], r["bin_mm"],
+                                 r["n_subsets"], r["counts"], seed=r["seed"]) for r in specs]
+    prm = pkg.params("svrem", alpha=args.alpha, eta=1, beta=1e-3)
+    epochs = [int(r["epochs"]) for r in specs]
+    total_epochs = sum(epochs)
+
+    def per_request():
+        out = []
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for i, P in enumerate(data):
+            A = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32)
+            R = pkg.Recon(A, P.g, P.w, np.ones((1, P.geom.n_pixels), np.float32), prm)
+            R.osem_epoch(list(range(P.n_subsets)))
+            R.svrem_epoch(np.concatenate(pkg.splitmix64_orders(1000 + i, P.n_subsets, epochs[i])))
+            out.append(R.image().cpu().numpy()[0])
+            R.close()
+            A.close()
+        return out, time.perf_counter() - t0
+
+    def served(wtype):
+        S = pkg.Server(64 << 30, max_slots=16, n_streams=8)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, epochs[i], 1000 + i, wtype=wtype)
+                   for i, P in enumerate(data)]
+        res = {}
+        while len(res) < n:
+            S.step(1)
+            for i, t in enumerate(tickets):
+                if i not in res:
+                    r = S.poll(t)
+                    if r is not None:
+                        res[i] = r
+        total = time.perf_counter() - t0
+        S.close()
+        assert all(res[i]["status"] == 0 for i in range(n))
+        return [res[i]["f"] for i in range(n)], total
+
+    per_request()  # warm-up: code objects, allocator pools
+    f_req, t_req = per_request()
+    log(f"per-request FP32: {t_req:.3f} s")
+    f32_srv, t_f32 = served(pkg.SVR_W_F32)
+    log(f"batched FP32: {t_f32:.3f} s")
+    f_bf, t_bf = served(pkg.SVR_W_BF16)
+    log(f"batched BF16: {t_bf:.3f} s")
+    f_h, t_h = served(pkg.SVR_W_F16)
+    log(f"batched FP16: {t_h:.3f} s")
+
+    def rel(a, b):
+        return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
+    d_bf = [rel(f_bf[i], f_req[i]) for i in range(n)]
+    d_h = [rel(f_h[i], f_req[i]) for i in range(n)]
+    d_32 = [rel(f32_srv[i], f_req[i]) for i in range(n)]
+    print(json.dumps({"workload": "serve-compare", "metric": "SVREM epochs/s over a set of serving requests",
+                      "requests": n, "epochs": total_epochs,
+                      "per_request_f32": {"seconds": round(t_req, 4), "epochs_per_s": round(total_epochs / t_req, 1)},
+                      "batched_f32": {"seconds": round(t_f32, 4), "epochs_per_s": round(total_epochs / t_f32, 1)},
+                      "batched_bf16": {"seconds": round(t_bf, 4), "epochs_per_s": round(total_epochs / t_bf, 1)},
+                      "batched_f16": {"seconds": round(t_h, 4), "epochs_per_s": round(total_epochs / t_h, 1)},
+                      "speedup_bf16_batched_vs_f32_per_request": round(t_req / t_bf, 3),
+                      "speedup_f16_batched_vs_f32_per_request": round(t_req / t_h, 3),
+                      "max_rel_diff_bf16_vs_f32": float(max(d_bf)),
+                      "median_rel_diff_bf16_vs_f32": float(np.median(d_bf)),
+                      "max_rel_diff_f16_vs_f32": float(max(d_h)),
+                      "max_rel_diff_batched_f32_vs_per_request": float(max(d_32))}), flush=True)
 
 
 if __name__ == "__main__":

@@ -9,6 +9,7 @@
 // midpoint and length is the correctly rounded result of the operations as
 // written (the pixel a piece falls in is an integer decision taken in FP64).
 #include <algorithm>
+#include <climits>
 #include <cmath>
 
 #include "common.h"
@@ -139,25 +140,31 @@ __global__ void k_siddon_fill(svr_geometry g, int M, const int *row_sino, const 
 }
 
 // ---- transposition (per subset), deterministic ------------------------------
+// entries per (subset, pixel); a wavefront per row of A, lanes over its entries
 __global__ void k_col_count(int M, int B, int Ns, int N, const int *row_sino, const int *row_ptr,
                             const int *col, int *cnt) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = (int)(gid >> 6), lane = (int)(gid & 63);
     if (r >= M) return;
-    int t = (row_sino[r] / B) % Ns;
+    const int t = (row_sino[r] / B) % Ns;
     int *c = cnt + (int64_t)t * N;
-    for (int i = row_ptr[r]; i < row_ptr[r + 1]; ++i) atomicAdd(&c[col[i]], 1);
+    for (int i = row_ptr[r] + lane; i < row_ptr[r + 1]; i += 64) atomicAdd(&c[col[i]], 1);
 }
 
+// every entry of A into its transposed row, in whatever order the atomic
+// cursors give (k_rank_T orders each row afterwards); a wavefront per row of
+// A, lanes over its entries
 template <typename WT>
 __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const int *row_start,
                          const int *row_ptr, const int *col, const WT *val, const int *ptrT,
                          int *cursor, int *rowT, WT *valT) {
-    int r = blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int r = (int)(gid >> 6), lane = (int)(gid & 63);
     if (r >= M) return;
-    int t = (row_sino[r] / B) % Ns;
-    int local = r - row_start[t];
-    int64_t base = (int64_t)t * N;
-    for (int i = row_ptr[r]; i < row_ptr[r + 1]; ++i) {
+    const int t = (row_sino[r] / B) % Ns;
+    const int local = r - row_start[t];
+    const int64_t base = (int64_t)t * N;
+    for (int i = row_ptr[r] + lane; i < row_ptr[r + 1]; i += 64) {
         int n = col[i];
         int p = ptrT[base + n] + atomicAdd(&cursor[base + n], 1);
         rowT[p] = local;
@@ -165,23 +172,39 @@ __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const
     }
 }
 
-// each transposed row sorted by subset-local row (view, then bin); keys are unique
+// Each transposed row in subset-local row order (view, then bin), read from
+// the unordered fill (keys, vals) and written to (rowT, valT): a 32-lane group
+// per row, two rows per wavefront; the lane holding an entry counts the keys
+// of its row that are smaller (every key broadcast lane by lane) and writes
+// the entry at beg + that rank.  Keys of a row are unique, so the ranks are a
+// permutation and the order is the ascending one, whatever order the fill
+// left.  Every lane of a wavefront runs the loops (their bounds are the
+// longer of the wavefront's two rows).
 template <typename WT>
-__global__ void k_sort_T(int64_t nrows, const int *ptrT, int *rowT, WT *valT) {
-    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (q >= nrows) return;
-    int beg = ptrT[q], end = ptrT[q + 1];
-    for (int i = beg + 1; i < end; ++i) {
-        int k = rowT[i];
-        WT vv = valT[i];
-        int j = i - 1;
-        while (j >= beg && rowT[j] > k) {
-            rowT[j + 1] = rowT[j];
-            valT[j + 1] = valT[j];
-            --j;
+__global__ void __launch_bounds__(256)
+k_rank_T(int64_t nrows, const int *ptrT, const int *keys, const WT *vals, int *rowT, WT *valT) {
+    const int lane = threadIdx.x & 63, h = lane >> 5, gl = lane & 31;
+    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
+    const bool has_row = q < nrows;
+    const int beg = has_row ? ptrT[q] : 0, len = has_row ? ptrT[q + 1] - beg : 0;
+    const int lmax = max(__builtin_amdgcn_readlane(len, 0), __builtin_amdgcn_readlane(len, 32));
+    for (int c = 0; c < lmax; c += 32) {
+        const int e = c + gl;
+        const bool has = e < len;
+        const int key = has ? keys[beg + e] : INT_MAX;
+        int rank = 0;
+        for (int d = 0; d < lmax; d += 32) {
+            const int kd = d + gl < len ? keys[beg + d + gl] : INT_MAX;
+#pragma unroll 8
+            for (int j = 0; j < 32; ++j) {
+                const int k0 = __builtin_amdgcn_readlane(kd, j), k1 = __builtin_amdgcn_readlane(kd, 32 + j);
+                rank += (h ? k1 : k0) < key;
+            }
         }
-        rowT[j + 1] = k;
-        valT[j + 1] = vv;
+        if (has) {
+            rowT[beg + rank] = key;
+            valT[beg + rank] = vals[beg + e];
+        }
     }
 }
 
@@ -253,11 +276,14 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     const int T = 256;
     const int gM = (M + T - 1) / T;
     const int64_t NT = (int64_t)Ns * N;
-    int *counts = nullptr, *cnt = nullptr, *stats = nullptr;
+    int *counts = nullptr, *cnt = nullptr, *stats = nullptr, *fillR = nullptr;
+    WT *fillV = nullptr;
     auto cleanup = [&]() {
         dfree(counts);
         dfree(cnt);
         dfree(stats);
+        dfree(fillR);
+        dfree(fillV);
     };
     SVR_HIP(dalloc(&counts, M));
     SVR_HIP(dalloc(&stats, Ns + 3));
@@ -292,7 +318,8 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     k_subset_offsets<<<(Ns + 1 + T - 1) / T, T, 0, s>>>(Ns, A.d_row_start, A.d_row_ptr, stats);
     // transposed rows per subset
     SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
-    k_col_count<<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt);
+    const unsigned gW = (unsigned)(((int64_t)M * 64 + T - 1) / T);  // a wavefront per row
+    k_col_count<<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt);
     k_max_count<<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, cnt, stats);
     SVR_HIP(hipGetLastError());
     int64_t nnzT = 0;
@@ -300,9 +327,15 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     if (rc) { cleanup(); return rc; }
     if (nnzT != nnz) { cleanup(); set_error("transpose count mismatch"); return SVR_EDEVICE; }
     SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
-    k_fill_T<WT><<<gM, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
-                                  val, A.d_ptrT, cnt, rowT, valT);
-    k_sort_T<WT><<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, rowT, valT);
+    SVR_HIP(dalloc(&fillR, nnz));
+    SVR_HIP(dalloc(&fillV, nnz));
+    k_fill_T<WT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
+                                  val, A.d_ptrT, cnt, fillR, fillV);
+    k_rank_T<WT><<<(unsigned)((NT * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, fillR, fillV, rowT, valT);
+    dfree(fillR);
+    dfree(fillV);
+    fillR = nullptr;
+    fillV = nullptr;
     k_sens<WT><<<(N + T - 1) / T, T, 0, s>>>(Ns, N, A.d_ptrT, valT, A.d_sens_t, A.d_sens);
     SVR_HIP(hipGetLastError());
     std::vector<int> h(Ns + 3);

@@ -1,10 +1,11 @@
 // Continuous-batching server for independent SVREM reconstructions.
 //
-// Requests queue at submit; each scheduler tick admits queued requests (FIFO)
-// while a slot is free and their device footprint fits the memory budget,
-// then enqueues one epoch of subset updates for every resident request, each
-// request on one of the server's streams, so that the work of all resident
-// requests overlaps on the device.  A request's kernels touch only its own
+// Requests queue at submit; each scheduler tick enqueues one epoch of subset
+// updates for every resident request, each request on one of the server's
+// streams, so that the work of all resident requests overlaps on the device,
+// then admits queued requests (FIFO) while a slot is free and their device
+// footprint fits the memory budget (their matrix builds and initial epochs
+// overlap the enqueued epochs).  A request's kernels touch only its own
 // buffers and every reduction has a fixed order, so its result is the same
 // whichever requests share the device with it.  Finished requests release
 // their memory, which lets the next queued ones in.
@@ -242,7 +243,20 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
     SVR_REQUIRE(S, "NULL server");
     SVR_HIP(hipSetDevice(S->device));
     for (int tick = 0; max_ticks <= 0 || tick < max_ticks; ++tick) {
-        // admission: FIFO while a slot is free and the estimate fits the budget
+        // one epoch of SVREM for every resident request, overlapped over streams
+        const size_t running = S->resident.size();
+        for (uint64_t tk : S->resident) {
+            Request *q = S->reqs[tk].get();
+            const int Ns = q->req.n_subsets;
+            std::vector<int32_t> order(Ns);
+            for (int i = 0; i < Ns; ++i) order[i] = q->rng.below(Ns);
+            int rc = svr_svrem_epoch(q->R, order.data(), Ns, S->streams[q->stream]);
+            if (rc) q->status = rc;
+            q->epochs_done++;
+        }
+        // admission, FIFO while a slot is free and the estimate fits the budget, after the epochs
+        // are enqueued: a new request's matrix build (which waits on the host for its sizes) and
+        // OSEM epoch then overlap the resident requests' epochs on the other streams
         while (!S->queue.empty() && (int)S->resident.size() < S->cfg.max_slots) {
             Request *q = S->reqs[S->queue.front()].get();
             if (S->used_bytes + q->est_bytes > S->cfg.mem_budget_bytes) break;
@@ -259,21 +273,12 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
             S->resident.push_back(q->ticket);
         }
         if (S->resident.empty()) return SVR_OK;
-        // one epoch of SVREM for every resident request, overlapped over streams
-        for (uint64_t tk : S->resident) {
-            Request *q = S->reqs[tk].get();
-            const int Ns = q->req.n_subsets;
-            std::vector<int32_t> order(Ns);
-            for (int i = 0; i < Ns; ++i) order[i] = q->rng.below(Ns);
-            int rc = svr_svrem_epoch(q->R, order.data(), Ns, S->streams[q->stream]);
-            if (rc) q->status = rc;
-            q->epochs_done++;
-        }
         for (hipStream_t st : S->streams) SVR_HIP(hipStreamSynchronize(st));
         std::vector<uint64_t> still;
-        for (uint64_t tk : S->resident) {
+        for (size_t i = 0; i < S->resident.size(); ++i) {
+            const uint64_t tk = S->resident[i];
             Request *q = S->reqs[tk].get();
-            if (q->status != SVR_OK || q->epochs_done >= q->req.epochs) {
+            if (i < running && (q->status != SVR_OK || q->epochs_done >= q->req.epochs)) {
                 int st = q->status;
                 finish(S, q, S->streams[q->stream]);
                 if (st != SVR_OK) q->status = st;
