@@ -317,13 +317,20 @@ int svr_recon_kernel_times(svr_recon *R, svr_kernel_times_t *out);
 /* A continuous-batching server for independent SVREM reconstruction requests
  * of different sizes.  Requests are admitted while their device footprint
  * fits in the memory budget and a slot is free; every scheduler tick advances
- * each resident request by one subset update, with the work of all resident
- * requests enqueued together so that it overlaps on the device.  A request's
- * result does not depend on which other requests share the device. */
+ * each resident request by one epoch of subset updates.  With batch = 1 the
+ * subset iterations of all resident requests with the same weight and index
+ * types run as one forward and one update launch per iteration (work items
+ * (request, row block) and (request, pixel block), up to 8 requests a launch;
+ * anchor iterations run per request); with batch = 0 each request's epoch is
+ * enqueued on one of the streams so that requests overlap.  A request's
+ * result does not depend on which other requests share the device, nor on
+ * batch. */
 typedef struct {
     int64_t mem_budget_bytes;  /* device bytes the server may hold (> 0) */
     int32_t max_slots;         /* max resident requests (>= 1) */
-    int32_t n_streams;         /* device streams used for overlap (>= 1) */
+    int32_t n_streams;         /* device streams (>= 1): matrix builds, and per-request epochs when batch = 0 */
+    int32_t batch;             /* 1: batched subset iterations (requests may not set
+                                  SVR_FLAG_PERSISTENT_EPOCH); 0: one request's epoch per stream */
 } svr_serve_config;
 
 typedef struct {

@@ -71,7 +71,8 @@ class svr_tuning_t(C.Structure):
 
 
 class svr_serve_config(C.Structure):
-    _fields_ = [("mem_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("n_streams", C.c_int32)]
+    _fields_ = [("mem_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("n_streams", C.c_int32),
+                ("batch", C.c_int32)]
 
 
 class svr_serve_request(C.Structure):
@@ -411,8 +412,8 @@ class Recon:
 class Server:
     """Continuous-batching SVREM server (``svr_serve_*``)."""
 
-    def __init__(self, mem_budget_bytes: int, max_slots: int = 8, n_streams: int = 4):
-        cfg = svr_serve_config(int(mem_budget_bytes), int(max_slots), int(n_streams))
+    def __init__(self, mem_budget_bytes: int, max_slots: int = 8, n_streams: int = 4, batch: bool = True):
+        cfg = svr_serve_config(int(mem_budget_bytes), int(max_slots), int(n_streams), 1 if batch else 0)
         self.h = C.c_void_p()
         _check(lib().svr_serve_create(C.byref(cfg), C.byref(self.h)))
         self._keep = {}

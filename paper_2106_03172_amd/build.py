@@ -21,7 +21,8 @@ LIBDIR = os.path.join(HERE, "_lib")
 BUILDDIR = os.path.join(os.path.dirname(HERE), "_build")
 LIB = os.path.join(LIBDIR, "libsvr.so")
 
-SOURCES = ["util.hip", "geom.hip", "proj.hip", "update.hip", "persist.hip", "slices.hip", "api.hip", "serve.hip", "tune.hip"]
+SOURCES = ["util.hip", "geom.hip", "proj.hip", "update.hip", "persist.hip", "slices.hip", "api.hip", "serve.hip", "tune.hip",
+           "batch.hip"]
 ARCH = os.environ.get("SVR_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",

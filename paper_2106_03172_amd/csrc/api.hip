@@ -9,6 +9,7 @@
 #include "common.h"
 #include "kernels.h"
 #include "util.h"
+#include "batch.h"
 
 using namespace svr;
 
@@ -180,6 +181,47 @@ int64_t anchors_in(const Recon *R, int algo, int64_t k0, int n) {
     return 0;
 }
 
+// The update arguments of the iteration on subset t (SAGA-EM: refreshed
+// subset t2) at the recon's current iterate and iteration count.
+UpdateArgs iteration_args(const Recon *R, int algo, int t, int t2) {
+    const Matrix &A = *R->A;
+    UpdateArgs u{};
+    u.t = t;
+    u.Ns = R->Ns;
+    u.ratio = R->ratio + A.row_start[t];
+    u.f = R->f[R->cur];
+    u.f_out = R->f[1 - R->cur];
+    u.ft_out = R->ft;
+    u.tx = A.tx;
+    u.alpha = R->p.alpha;
+    if (algo == SVR_ALGO_BSREM || algo == SVR_ALGO_SEM) u.alpha = R->p.alpha / (R->p.decay * (double)R->k + 1.0);
+    u.s_hat = R->s_hat;
+    u.s_anc = R->s_anc;
+    u.table = R->table;
+    u.Q = R->Q;
+    u.g_tilde = R->g_tilde;
+    u.dpre = (R->p.precond == SVR_PRECOND_ITERATE) ? nullptr : R->dpre;
+    u.dpre_per_subset = R->dpre_per_subset;
+    u.shat_zero = (algo == SVR_ALGO_SEM && R->k == 0);
+    u.pen = pen_of(R);
+    if (algo == SVR_ALGO_OSEM) u.pen.beta = 0.0;
+    u.t2 = t2;
+    u.ratio2 = R->ratio + A.row_start[t2];
+    return u;
+}
+
+// whether the next iteration takes an anchor (SVREM, SVRG: every eta*Ns
+// iterations) or fills the table (SAGA, SAGA-EM: the first)
+bool is_anchor(const Recon *R, int algo) {
+    return ((algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG) && R->k % ((int64_t)R->p.eta * R->Ns) == 0) ||
+           ((algo == SVR_ALGO_SAGA || algo == SVR_ALGO_SAGAEM) && R->k == 0);
+}
+
+void advance_iteration(Recon *R, int algo) {
+    R->cur = 1 - R->cur;
+    if (algo != SVR_ALGO_OSEM) R->k++;
+}
+
 int run_epoch_persistent(Recon *R, int algo, int kind, const int32_t *order, int32_t n, hipStream_t s) {
     Matrix &A = *R->A;
     if (n > R->order_cap) {
@@ -337,34 +379,9 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream,
     if (n > 0 && (R->p.flags & SVR_FLAG_PERSISTENT_EPOCH)) return run_epoch_persistent(R, algo, kind, order, n, s);
     for (int i = 0; i < n; ++i) {
         const int t = order[i];
-        UpdateArgs u{};
-        u.t = t;
-        u.Ns = R->Ns;
-        u.ratio = R->ratio + A.row_start[t];
-        u.f = R->f[R->cur];
-        u.f_out = R->f[1 - R->cur];
-        u.ft_out = R->ft;
-        u.tx = A.tx;
-        u.alpha = R->p.alpha;
-        if (algo == SVR_ALGO_BSREM || algo == SVR_ALGO_SEM)
-            u.alpha = R->p.alpha / (R->p.decay * (double)R->k + 1.0);
-        u.s_hat = R->s_hat;
-        u.s_anc = R->s_anc;
-        u.table = R->table;
-        u.Q = R->Q;
-        u.g_tilde = R->g_tilde;
-        u.dpre = (R->p.precond == SVR_PRECOND_ITERATE) ? nullptr : R->dpre;
-        u.dpre_per_subset = R->dpre_per_subset;
-        u.shat_zero = (algo == SVR_ALGO_SEM && R->k == 0);
-        u.pen = pen_of(R);
-        if (algo == SVR_ALGO_OSEM) u.pen.beta = 0.0;
         const int t2 = refresh ? refresh[i] : t;
-        u.t2 = t2;
-        u.ratio2 = R->ratio + A.row_start[t2];
-        const bool anchor = ((algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG) &&
-                             R->k % ((int64_t)R->p.eta * R->Ns) == 0) ||
-                            ((algo == SVR_ALGO_SAGA || algo == SVR_ALGO_SAGAEM) && R->k == 0);
-        if (anchor) {
+        UpdateArgs u = iteration_args(R, algo, t, t2);
+        if (is_anchor(R, algo)) {
             rc = anchor_iteration(R, kind, u, s);
             if (rc) return rc;
         } else {
@@ -383,13 +400,40 @@ int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream,
             if (!rc) rc = prof_end(R, s);
             if (rc) return rc;
         }
-        R->cur = 1 - R->cur;
-        if (algo != SVR_ALGO_OSEM) R->k++;
+        advance_iteration(R, algo);
     }
     return SVR_OK;
 }
 
 }  // namespace
+
+// ---- one iteration at a time (the batched server) ------------------------------
+namespace svr {
+
+int plan_iteration(svr_recon *R, int t, IterPlan *p) {
+    SVR_REQUIRE(R && p, "NULL argument");
+    SVR_REQUIRE(R->S == 1 && !(R->p.flags & SVR_FLAG_PERSISTENT_EPOCH) && R->p.algo != SVR_ALGO_SAGAEM,
+                "iteration plans are for single-slice recons without the persistent flag or SAGA-EM");
+    SVR_REQUIRE(t >= 0 && t < R->Ns, "subset %d outside [0, %d)", t, R->Ns);
+    const Matrix &A = *R->A;
+    const int algo = R->p.algo;
+    p->A = &A;
+    p->kind = kind_of_algo(algo);
+    p->anchor = is_anchor(R, algo);
+    p->r0 = A.row_start[t];
+    p->r1 = A.row_start[t + 1];
+    p->pair = forward_pairs_for(p->r1 - p->r0, A.pair_rows_eff());
+    p->fa = FwdArgs{R->ft, R->g, R->w, R->ratio, nullptr, nullptr};
+    p->fa.eps = ll_eps_of(R, p->kind);
+    p->u = iteration_args(R, algo, t, t);
+    return SVR_OK;
+}
+
+int run_anchor_plan(svr_recon *R, IterPlan &p, hipStream_t s) { return anchor_iteration(R, p.kind, p.u, s); }
+
+void end_iteration(svr_recon *R) { advance_iteration(R, R->p.algo); }
+
+}  // namespace svr
 
 // ===========================================================================
 // C ABI

@@ -1,0 +1,75 @@
+// Batched subset iterations for the server: one launch per phase runs the
+// current iteration of several independent reconstructions.  Work items are
+// (request, row block) for the forward and (request, pixel block) for the
+// update; each item calls the single-request device functions with that
+// request's own arguments, so every request's result is bitwise the one of
+// its own epoch calls.
+#pragma once
+
+#include "common.h"
+
+struct svr_recon;
+
+namespace svr {
+
+// The next iteration of a single-slice recon on subset t: either an anchor
+// (or table fill), which runs on its own (run_anchor_plan), or the arguments
+// of the subset forward and update.  end_iteration advances the recon after
+// either.
+struct IterPlan {
+    const Matrix *A;
+    int kind;
+    bool anchor;
+    int r0, r1;  // rows of subset t
+    bool pair;   // the forward pass runs a pair of rows per wavefront
+    FwdArgs fa;
+    UpdateArgs u;
+};
+int plan_iteration(svr_recon *R, int t, IterPlan *p);
+int run_anchor_plan(svr_recon *R, IterPlan &p, hipStream_t s);
+void end_iteration(svr_recon *R);
+
+// Requests per batched launch (their arguments travel in the kernel
+// arguments: about 100 B per forward item, 230 B per update item).
+constexpr int BATCH_MAX = 8;
+
+struct FwdItem {
+    const int *row_ptr;
+    const void *col;  // forward indices in tiled pixel order
+    const void *val;
+    FwdArgs a;
+    int r0, r1;
+    int pair;
+    int blk0;  // first block of this item
+};
+struct FwdBatch {
+    int n;
+    int blocks;  // total blocks of the launch
+    FwdItem it[BATCH_MAX];
+};
+
+struct UpdItem {
+    const int *ptrT;
+    const void *rowT;
+    const void *valT;
+    const float *sens_t;
+    const double *sens;
+    int N;
+    int blk0;
+    UpdateArgs u;
+};
+struct UpdBatch {
+    int n;
+    int blocks;
+    UpdItem it[BATCH_MAX];
+};
+
+// Appends the plan's forward (update) work to the batch; the matrices of one
+// batch share their weight and index types.
+void add_forward(FwdBatch &b, const IterPlan &p);
+void add_update(UpdBatch &b, const IterPlan &p);
+// Launch the batch (types from `types`, a matrix of the batch); SVREM updates.
+int launch_forward_batch(const Matrix &types, const FwdBatch &b, hipStream_t s);
+int launch_update_batch(const Matrix &types, const UpdBatch &b, hipStream_t s);
+
+}  // namespace svr

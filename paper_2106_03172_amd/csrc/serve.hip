@@ -1,14 +1,15 @@
 // Continuous-batching server for independent SVREM reconstructions.
 //
 // Requests queue at submit; each scheduler tick enqueues one epoch of subset
-// updates for every resident request, each request on one of the server's
-// streams, so that the work of all resident requests overlaps on the device,
-// then admits queued requests (FIFO) while a slot is free and their device
-// footprint fits the memory budget (their matrix builds and initial epochs
-// overlap the enqueued epochs).  A request's kernels touch only its own
+// updates for every resident request (batched: one forward and one update
+// launch per iteration for all requests of the same storage types; else each
+// request on one of the server's streams), then admits queued requests (FIFO)
+// while a slot is free and their device footprint fits the memory budget
+// (their matrix builds and initial epochs overlap the enqueued epochs).  A request's kernels touch only its own
 // buffers and every reduction has a fixed order, so its result is the same
 // whichever requests share the device with it.  Finished requests release
 // their memory, which lets the next queued ones in.
+#include <algorithm>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -18,6 +19,7 @@
 #include <new>
 #include <vector>
 
+#include "batch.h"
 #include "common.h"
 #include "util.h"
 
@@ -152,6 +154,70 @@ int admit(svr_server *S, Request *q, hipStream_t s) {
     return SVR_OK;
 }
 
+// One epoch of every resident request with the subset iterations batched:
+// for each iteration index, the requests at an anchor take it on their own;
+// the others run as one forward and one update launch per group of requests
+// with the same weight and index types (up to BATCH_MAX a launch), all on
+// the first stream.
+void batched_epoch(svr_server *S) {
+    hipStream_t s0 = S->streams[0];
+    struct Res {
+        Request *q;
+        std::vector<int32_t> order;
+    };
+    std::vector<Res> rs;
+    int max_ns = 0;
+    for (uint64_t tk : S->resident) {
+        Request *q = S->reqs[tk].get();
+        const int Ns = q->req.n_subsets;
+        Res r{q, std::vector<int32_t>(Ns)};
+        for (int i = 0; i < Ns; ++i) r.order[i] = q->rng.below(Ns);
+        max_ns = std::max(max_ns, Ns);
+        rs.push_back(std::move(r));
+    }
+    for (int j = 0; j < max_ns; ++j) {
+        std::map<int, std::vector<std::pair<Request *, IterPlan>>> groups;  // key: weight type, index width
+        for (Res &r : rs) {
+            Request *q = r.q;
+            if (j >= (int)r.order.size() || q->status != SVR_OK) continue;
+            IterPlan pl;
+            int rc = plan_iteration(q->R, r.order[j], &pl);
+            if (rc) {
+                q->status = rc;
+                continue;
+            }
+            if (pl.anchor) {
+                rc = run_anchor_plan(q->R, pl, s0);
+                if (rc) q->status = rc;
+                end_iteration(q->R);
+                continue;
+            }
+            groups[pl.A->wtype * 2 + pl.A->idx16].push_back({q, pl});
+        }
+        for (auto &kv : groups) {
+            auto &v = kv.second;
+            for (size_t c = 0; c < v.size(); c += BATCH_MAX) {
+                const size_t e = std::min(v.size(), c + BATCH_MAX);
+                FwdBatch fb{};
+                for (size_t i = c; i < e; ++i) add_forward(fb, v[i].second);
+                const int rc = launch_forward_batch(*v[c].second.A, fb, s0);
+                if (rc)
+                    for (size_t i = c; i < e; ++i) v[i].first->status = rc;
+            }
+            for (size_t c = 0; c < v.size(); c += BATCH_MAX) {
+                const size_t e = std::min(v.size(), c + BATCH_MAX);
+                UpdBatch ub{};
+                for (size_t i = c; i < e; ++i) add_update(ub, v[i].second);
+                const int rc = launch_update_batch(*v[c].second.A, ub, s0);
+                if (rc)
+                    for (size_t i = c; i < e; ++i) v[i].first->status = rc;
+            }
+            for (auto &qp : v) end_iteration(qp.first->R);
+        }
+    }
+    for (Res &r : rs) r.q->epochs_done++;
+}
+
 int finish(svr_server *S, Request *q, hipStream_t s) {
     const int64_t N = (int64_t)q->req.geom.nx * q->req.geom.ny;
     double phi = 0.0;
@@ -184,6 +250,7 @@ int svr_serve_create(const svr_serve_config *cfg, svr_server **out) {
     SVR_REQUIRE(cfg && out, "NULL argument");
     SVR_REQUIRE(cfg->mem_budget_bytes > 0 && cfg->max_slots >= 1 && cfg->n_streams >= 1,
                 "mem_budget_bytes > 0, max_slots >= 1 and n_streams >= 1 are required");
+    SVR_REQUIRE(cfg->batch == 0 || cfg->batch == 1, "batch must be 0 or 1");
     *out = nullptr;
     svr_server *S = new (std::nothrow) svr_server();
     SVR_REQUIRE(S, "host allocation failed");
@@ -212,6 +279,8 @@ int svr_serve_submit(svr_server *S, const svr_serve_request *r, uint64_t *ticket
                 "invalid geometry");
     SVR_REQUIRE(r->n_subsets >= 1 && r->n_subsets <= g.n_views, "n_subsets must be in [1, n_views]");
     SVR_REQUIRE(r->params.algo == SVR_ALGO_SVREM, "the server runs SVREM requests");
+    SVR_REQUIRE(!(S->cfg.batch && (r->params.flags & SVR_FLAG_PERSISTENT_EPOCH)),
+                "a batching server runs the per-phase kernels: SVR_FLAG_PERSISTENT_EPOCH is not available");
     SVR_REQUIRE(r->epochs >= 1, "epochs must be >= 1");
     SVR_REQUIRE(r->g_host && r->w_host, "g_host and w_host are required");
     SVR_REQUIRE(r->f0_value > 0 && std::isfinite(r->f0_value), "f0_value must be finite and > 0");
@@ -243,16 +312,21 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
     SVR_REQUIRE(S, "NULL server");
     SVR_HIP(hipSetDevice(S->device));
     for (int tick = 0; max_ticks <= 0 || tick < max_ticks; ++tick) {
-        // one epoch of SVREM for every resident request, overlapped over streams
+        // one epoch of SVREM for every resident request: batched, or each
+        // request's epoch on its own stream, overlapped over streams
         const size_t running = S->resident.size();
-        for (uint64_t tk : S->resident) {
-            Request *q = S->reqs[tk].get();
-            const int Ns = q->req.n_subsets;
-            std::vector<int32_t> order(Ns);
-            for (int i = 0; i < Ns; ++i) order[i] = q->rng.below(Ns);
-            int rc = svr_svrem_epoch(q->R, order.data(), Ns, S->streams[q->stream]);
-            if (rc) q->status = rc;
-            q->epochs_done++;
+        if (S->cfg.batch) {
+            batched_epoch(S);
+        } else {
+            for (uint64_t tk : S->resident) {
+                Request *q = S->reqs[tk].get();
+                const int Ns = q->req.n_subsets;
+                std::vector<int32_t> order(Ns);
+                for (int i = 0; i < Ns; ++i) order[i] = q->rng.below(Ns);
+                int rc = svr_svrem_epoch(q->R, order.data(), Ns, S->streams[q->stream]);
+                if (rc) q->status = rc;
+                q->epochs_done++;
+            }
         }
         // admission, FIFO while a slot is free and the estimate fits the budget, after the epochs
         // are enqueued: a new request's matrix build (which waits on the host for its sizes) and

@@ -94,6 +94,35 @@ def test_thirty_epochs_served_against_oracle(wtype, bar):
     assert err <= bar
 
 
+def test_batched_kernels_equal_per_request_streams():
+    """batch = 1 runs the subset iterations of all resident requests of one
+    storage type as one forward and one update launch; every request's result
+    must be bitwise the one of the per-request path (batch = 0), across a mix
+    of FP32, BF16 and FP16 weights and of 16- and 32-bit indices (two type
+    groups run their own launches), with more requests than one launch holds."""
+    probs = [_req(s) for s in SPECS] * 3
+    wts = [pkg.SVR_W_F32, pkg.SVR_W_BF16, pkg.SVR_W_F32 | pkg.binding.SVR_W_INDEX32, pkg.SVR_W_F16] * 3
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+    out = []
+    for batch in (True, False):
+        S = pkg.Server(1 << 32, max_slots=12, n_streams=3, batch=batch)
+        tk = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS, 500 + i, wtype=wts[i])
+              for i, P in enumerate(probs)]
+        S.step(0)
+        out.append([S.poll(t) for t in tk])
+        S.close()
+    for a, b in zip(*out):
+        assert a["status"] == 0 and b["status"] == 0
+        np.testing.assert_array_equal(a["f"], b["f"])
+        assert a["phi"] == b["phi"]
+    # a batching server runs the per-phase kernels only
+    S = pkg.Server(1 << 31, max_slots=2, n_streams=1, batch=True)
+    with pytest.raises(pkg.SvrError):
+        S.submit(probs[0].geom, probs[0].n_subsets, probs[0].g, probs[0].w,
+                 pkg.params("svrem", flags=pkg.binding.FLAG_PERSISTENT_EPOCH), 2, 1)
+    S.close()
+
+
 def test_alone_equals_in_the_mix():
     probs = [_req(s) for s in SPECS]
     mixed = _serve(probs, max_slots=3, seeds=[11, 12, 13, 14])
