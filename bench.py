@@ -323,6 +323,26 @@ def main():
     projector = {"forward_gbs": round(fwd_b / fwd_s / 1e9, 1), "back_gbs": round(bwd_b / bwd_s / 1e9, 1),
                  "forward_us": round(fwd_s * 1e6, 2), "back_us": round(bwd_s * 1e6, 2),
                  "matrix_mb": round(inf.nnz * (ib + wb) / 1e6, 1), "index_bytes": ib}
+    # one subset (t = 0): the calls take natural-order sinograms, so the back-projection call
+    # also permutes the whole sinogram into subset order (8M bytes)
+    nnz0 = int(np.asarray(per_subset)[0])
+    M0 = ((P.geom.n_views + Ns - 1) // Ns) * P.geom.n_bins  # views v = 0 (mod Ns)
+    reps = 50
+    ev[0].record()
+    for _ in range(reps):
+        A.project(x, 0, yo)
+    ev[1].record()
+    for _ in range(reps):
+        A.backproject(y, 0, xo)
+    ev[2].record()
+    torch.cuda.synchronize()
+    f0_s = ev[0].elapsed_time(ev[1]) / reps / 1e3
+    b0_s = ev[1].elapsed_time(ev[2]) / reps / 1e3
+    f0_b = nnz0 * (ib + wb) + 4 * (M0 + 1) + 4 * N + 4 * M0
+    b0_b = nnz0 * (ib + wb) + 4 * (N + 1) + 4 * N + 8 * M + 4 * M0
+    projector["subset0"] = {"forward_us": round(f0_s * 1e6, 2), "back_us": round(b0_s * 1e6, 2),
+                            "forward_gbs": round(f0_b / f0_s / 1e9, 1), "back_gbs": round(b0_b / b0_s / 1e9, 1),
+                            "rows": M0, "nnz": nnz0}
 
     cpu = None
     if not args.no_cpu_baseline:

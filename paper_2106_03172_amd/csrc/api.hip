@@ -458,6 +458,12 @@ int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t
                 "unknown wtype %d", wtype);
     svr_matrix *A = new (std::nothrow) svr_matrix();
     SVR_REQUIRE(A, "host allocation failed");
+    A->proj_mu = new (std::nothrow) std::mutex();
+    if (!A->proj_mu) {
+        delete A;
+        set_error("host allocation failed");
+        return SVR_ENOMEM;
+    }
     A->geom = *geom;
     A->Ns = n_subsets;
     A->wtype = wbase;
@@ -470,14 +476,14 @@ int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t
         AllocStream as(s);
         int *cnt = nullptr;
         hipError_t e = dalloc(&cnt, 1);
-        if (e != hipSuccess) { delete A; set_error("allocation failed"); return SVR_ENOMEM; }
+        if (e != hipSuccess) { svr_matrix_destroy(A); set_error("allocation failed"); return SVR_ENOMEM; }
         (void)hipMemsetAsync(cnt, 0, sizeof(int), s);
         launch_count_bad(mu_dev, (int64_t)geom->nx * geom->ny, 0, cnt, s);
         int h = 0;
         (void)hipMemcpyAsync(&h, cnt, sizeof(int), hipMemcpyDeviceToHost, s);
         (void)hipStreamSynchronize(s);
         dfree(cnt);
-        if (h) { delete A; set_error("mu has %d negative or non-finite entries", h); return SVR_EINVAL; }
+        if (h) { svr_matrix_destroy(A); set_error("mu has %d negative or non-finite entries", h); return SVR_EINVAL; }
     }
     rc = build_matrix(*A, mu_dev, s);
     if (rc) {
@@ -594,12 +600,73 @@ int svr_sensitivity(const svr_matrix *A, int32_t subset, double *out_dev, void *
 void svr_matrix_destroy(svr_matrix *A) {
     if (!A) return;
     (void)hipSetDevice(A->device);
+    if (A->proj_scratch) {  // the last projector call that used it has finished with it
+        (void)hipEventSynchronize(A->proj_done);
+        (void)hipFree(A->proj_scratch);
+        (void)hipEventDestroy(A->proj_done);
+    }
+    delete A->proj_mu;
     AllocStream as(A->owner);
     void *ptrs[] = {A->d_row_start, A->d_row_sino, A->d_row_ptr, A->d_col, A->d_colt, A->d_val, A->d_ptrT,
                     A->d_rowT, A->d_valT, A->d_sens_t, A->d_sens};
     for (void *q : ptrs) dfree(q);
     delete A;
 }
+
+}  // extern "C"
+
+namespace {
+
+// n floats of scratch for a projector call on stream s: the matrix's kept buffer when it is idle
+// and its last use was on s (stream order) or has completed, else a stream-ordered allocation of
+// the call's own (*own = true).  Returns null when no memory could be had.
+float *acquire_proj_scratch(const Matrix &A, size_t n, hipStream_t s, bool *own) {
+    *own = false;
+    {
+        std::lock_guard<std::mutex> lk(*A.proj_mu);
+        const size_t cap = std::max<size_t>((size_t)A.Nt, (size_t)A.M);
+        if (!A.proj_busy && n <= cap) {
+            if (!A.proj_scratch) {
+                float *p = nullptr;
+                hipEvent_t e = nullptr;
+                if (hipMalloc((void **)&p, sizeof(float) * cap) == hipSuccess &&
+                    hipEventCreateWithFlags(&e, hipEventDisableTiming) == hipSuccess) {
+                    A.proj_scratch = p;
+                    A.proj_done = e;
+                    A.proj_stream = s;  // no earlier use to wait for
+                } else {
+                    if (p) (void)hipFree(p);
+                    (void)hipGetLastError();
+                }
+            }
+            if (A.proj_scratch && (A.proj_stream == s || hipEventQuery(A.proj_done) == hipSuccess)) {
+                A.proj_busy = true;
+                return A.proj_scratch;
+            }
+            (void)hipGetLastError();  // hipEventQuery's "not ready"
+        }
+    }
+    *own = true;
+    float *p = nullptr;
+    if (hipMallocAsync((void **)&p, sizeof(float) * n, s) != hipSuccess) return nullptr;
+    return p;
+}
+
+void release_proj_scratch(const Matrix &A, float *p, bool own, hipStream_t s) {
+    if (!p) return;
+    if (own) {
+        (void)hipFreeAsync(p, s);
+        return;
+    }
+    std::lock_guard<std::mutex> lk(*A.proj_mu);
+    (void)hipEventRecord(A.proj_done, s);
+    A.proj_stream = s;
+    A.proj_busy = false;
+}
+
+}  // namespace
+
+extern "C" {
 
 int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t n_slices, float *y_dev,
                 void *stream) {
@@ -611,15 +678,16 @@ int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t
     hipStream_t s = (hipStream_t)stream;
     const int r0 = subset < 0 ? 0 : A->row_start[subset];
     const int r1 = subset < 0 ? A->M : A->row_start[subset + 1];
-    float *xt = nullptr;  // each slice in the tiled order of the forward indices
-    SVR_HIP(hipMallocAsync((void **)&xt, sizeof(float) * (size_t)A->Nt, s));
+    bool own = false;
+    float *xt = acquire_proj_scratch(*A, (size_t)A->Nt, s, &own);  // each slice in the tiled order
+    SVR_REQUIRE(xt, "no device memory for the projector's scratch");
     int rc = SVR_OK;
     for (int sl = 0; sl < n_slices && rc == SVR_OK; ++sl) {
         rc = launch_tile_image(*A, x_dev + (int64_t)sl * A->N, xt, s);
         FwdArgs fa{xt, nullptr, nullptr, y_dev + (int64_t)sl * A->M, nullptr, nullptr};
         if (rc == SVR_OK) rc = launch_forward(*A, r0, r1, 0, fa, s);
     }
-    SVR_HIP(hipFreeAsync(xt, s));
+    release_proj_scratch(*A, xt, own, s);
     return rc;
 }
 
@@ -631,14 +699,15 @@ int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int
     SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
     SVR_HIP(hipSetDevice(A->device));
     hipStream_t s = (hipStream_t)stream;
-    float *ysub = nullptr;
-    SVR_HIP(hipMallocAsync((void **)&ysub, sizeof(float) * (size_t)A->M, s));
+    bool own = false;
+    float *ysub = acquire_proj_scratch(*A, (size_t)A->M, s, &own);  // each slice in subset order
+    SVR_REQUIRE(ysub, "no device memory for the projector's scratch");
     int rc = SVR_OK;
     for (int sl = 0; sl < n_slices && rc == SVR_OK; ++sl) {
         rc = launch_gather_rows(*A, y_dev + (int64_t)sl * A->M, ysub, s);
         if (rc == SVR_OK) rc = launch_backproject(*A, subset, ysub, x_dev + (int64_t)sl * A->N, s);
     }
-    SVR_HIP(hipFreeAsync(ysub, s));
+    release_proj_scratch(*A, ysub, own, s);
     return rc;
 }
 

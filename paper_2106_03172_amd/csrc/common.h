@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -125,6 +126,14 @@ struct Matrix {
     int pair_rows_eff() const { return pair_rows > 0 ? pair_rows : 2 * 32 * (cus > 1 ? cus : 1); }
     int run_fwd = 0;                // row pairs per wavefront in whole-matrix forward passes (0: by size)
     int run_bp = 0;                 // transposed rows per lane group in whole-matrix back-projections (0: by size)
+    // scratch of the projector calls (svr_project / svr_backproject), max(Nt, M) floats kept
+    // between calls: a call takes it when it is idle and its last use was on the call's stream
+    // or has completed (proj_done), else allocates its own
+    mutable float *proj_scratch = nullptr;
+    mutable hipStream_t proj_stream = nullptr;
+    mutable hipEvent_t proj_done = nullptr;
+    mutable bool proj_busy = false;
+    std::mutex *proj_mu = nullptr;  // created with the matrix
     int wbytes() const { return wtype == SVR_W_F32 ? 4 : 2; }
     int ibytes() const { return idx16 ? 2 : 4; }
     int rows_of(int t) const { return row_start[t + 1] - row_start[t]; }
