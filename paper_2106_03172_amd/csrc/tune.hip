@@ -1,7 +1,7 @@
-// Autotuner for the run lengths of the whole-matrix passes: rows of A per
-// wavefront in the forward projection over every row (the anchor pass, the
-// objective, svr_project over all subsets) and (subset, pixel) rows per lane
-// group in the anchor table.  Each candidate is timed with HIP events on the
+// Autotuner for the run lengths of the whole-matrix passes: pairs of rows of
+// A per wavefront in the forward projection over every row (the anchor pass,
+// the objective, svr_project over all subsets) and (subset, pixel) rows per
+// lane group in the anchor table.  Each candidate is timed with HIP events on the
 // matrix itself, on synthetic operands (image 1, data 1, background 0.1); the
 // fastest is kept in the matrix.  The run length changes only which
 // wavefront computes a row, never the row's arithmetic, so every result is
