@@ -89,31 +89,57 @@ __device__ inline Neighbours load_neighbours_of(const float *f, int n, const Pen
     return load_neighbours(f, ix, iy, p.nx, p.ny);
 }
 
-// grad R(f)_n = sum_j w_nj rho'(f_n - f_j), from pixel n's value and its neighbours
-__device__ inline double penalty_grad_nb(double fn, const Neighbours &nb, const PenaltyArgs &p) {
+// The stencil sums below take the potential as a template argument (one
+// switch per pixel, outside the loop) and add every neighbour without a
+// branch: an absent one contributes +0.0, which leaves each sum unchanged
+// (none of them can be -0.0 at that point), so the sums equal those over the
+// present neighbours in the fixed order, bitwise.
+template <int POT>
+__device__ inline double penalty_grad_pot(double fn, const Neighbours &nb, double delta) {
     double g = 0.0;
 #pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (nb.ok[k]) g = g + nb_weight(k) * pot_drho(p.potential, fn - (double)nb.v[k], p.delta);
+    for (int k = 0; k < 8; ++k) {
+        const double term = nb_weight(k) * pot_drho(POT, fn - (double)nb.v[k], delta);
+        g = g + (nb.ok[k] ? term : 0.0);
+    }
     return g;
+}
+
+// grad R(f)_n = sum_j w_nj rho'(f_n - f_j), from pixel n's value and its neighbours
+__device__ inline double penalty_grad_nb(double fn, const Neighbours &nb, const PenaltyArgs &p) {
+    switch (p.potential) {
+        case SVR_PEN_HUBER: return penalty_grad_pot<SVR_PEN_HUBER>(fn, nb, p.delta);
+        case SVR_PEN_LOGCOSH: return penalty_grad_pot<SVR_PEN_LOGCOSH>(fn, nb, p.delta);
+        case SVR_PEN_HYPERBOLA: return penalty_grad_pot<SVR_PEN_HYPERBOLA>(fn, nb, p.delta);
+        default: return penalty_grad_pot<SVR_PEN_QUADRATIC>(fn, nb, p.delta);
+    }
 }
 
 __device__ inline double penalty_grad_at(const float *f, int n, const PenaltyArgs &p) {
     return penalty_grad_nb((double)f[n], load_neighbours_of(f, n, p), p);
 }
 
-// Surrogate sums of the penalised M-step: D = sum_j d_nj, E = sum_j d_nj f_j,
-// d_nj = w_nj gamma(f_n - f_j) at the expansion point f (Sec. 3, eq. svrsurder).
-__device__ inline void surrogate_nb(double fn, const Neighbours &nb, const PenaltyArgs &p, double &D, double &E) {
+template <int POT>
+__device__ inline void surrogate_pot(double fn, const Neighbours &nb, double delta, double &D, double &E) {
     D = 0.0;
     E = 0.0;
 #pragma unroll
     for (int k = 0; k < 8; ++k) {
-        if (!nb.ok[k]) continue;
         const double fj = (double)nb.v[k];
-        const double d = nb_weight(k) * pot_gamma(p.potential, fn - fj, p.delta);
-        D = D + d;
-        E = E + d * fj;
+        const double d = nb_weight(k) * pot_gamma(POT, fn - fj, delta);
+        D = D + (nb.ok[k] ? d : 0.0);
+        E = E + (nb.ok[k] ? d * fj : 0.0);
+    }
+}
+
+// Surrogate sums of the penalised M-step: D = sum_j d_nj, E = sum_j d_nj f_j,
+// d_nj = w_nj gamma(f_n - f_j) at the expansion point f (Sec. 3, eq. svrsurder).
+__device__ inline void surrogate_nb(double fn, const Neighbours &nb, const PenaltyArgs &p, double &D, double &E) {
+    switch (p.potential) {
+        case SVR_PEN_HUBER: surrogate_pot<SVR_PEN_HUBER>(fn, nb, p.delta, D, E); break;
+        case SVR_PEN_LOGCOSH: surrogate_pot<SVR_PEN_LOGCOSH>(fn, nb, p.delta, D, E); break;
+        case SVR_PEN_HYPERBOLA: surrogate_pot<SVR_PEN_HYPERBOLA>(fn, nb, p.delta, D, E); break;
+        default: surrogate_pot<SVR_PEN_QUADRATIC>(fn, nb, p.delta, D, E);
     }
 }
 
@@ -121,16 +147,28 @@ __device__ inline void surrogate_at(const float *f, int n, const PenaltyArgs &p,
     surrogate_nb((double)f[n], load_neighbours_of(f, n, p), p, D, E);
 }
 
+template <int POT>
+__device__ inline double penalty_share_pot(double fn, const Neighbours &nb, double delta) {
+    double r = 0.0;
+#pragma unroll
+    for (int k = 0; k < 8; ++k) {
+        const double term = nb_weight(k) * pot_rho(POT, fn - (double)nb.v[k], delta);
+        r = r + (nb.ok[k] ? term : 0.0);
+    }
+    return 0.5 * r;
+}
+
 // 1/2 sum_j w_nj rho(f_n - f_j): pixel n's share of R(f)
 __device__ inline double penalty_share_at(const float *f, int n, const PenaltyArgs &p) {
     const int iy = n / p.nx, ix = n - iy * p.nx;
     const double fn = (double)f[n];
     const Neighbours nb = load_neighbours(f, ix, iy, p.nx, p.ny);
-    double r = 0.0;
-#pragma unroll
-    for (int k = 0; k < 8; ++k)
-        if (nb.ok[k]) r = r + nb_weight(k) * pot_rho(p.potential, fn - (double)nb.v[k], p.delta);
-    return 0.5 * r;
+    switch (p.potential) {
+        case SVR_PEN_HUBER: return penalty_share_pot<SVR_PEN_HUBER>(fn, nb, p.delta);
+        case SVR_PEN_LOGCOSH: return penalty_share_pot<SVR_PEN_LOGCOSH>(fn, nb, p.delta);
+        case SVR_PEN_HYPERBOLA: return penalty_share_pot<SVR_PEN_HYPERBOLA>(fn, nb, p.delta);
+        default: return penalty_share_pot<SVR_PEN_QUADRATIC>(fn, nb, p.delta);
+    }
 }
 
 // Non-negative root of a/f - 2 b f + c = 0 (Sec. 3, below eq. svrsurder).
