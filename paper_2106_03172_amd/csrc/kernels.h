@@ -384,6 +384,30 @@ __device__ inline double bp_range(const IT *__restrict__ rowT, const WT *__restr
     return group_sum(acc);
 }
 
+// The same sum with `mid()` run once per lane while the lane's first
+// index/weight batch is in flight (after the loop for a lane with no entries):
+// work that does not depend on the sum, such as the penalty's stencil sums,
+// then takes none of the gather's latency.
+template <typename WT, typename IT, class Mid>
+__device__ inline double bp_range_mid(const IT *__restrict__ rowT, const WT *__restrict__ valT, int beg, int end,
+                                      const float *__restrict__ y, int lig, Mid mid) {
+    double acc = 0.0;
+    bool done = false;
+    for (int base = beg + lig; base < end; base += BP_G * BP_U) {
+        RowBatch<BP_G, BP_U, WT, IT> b;
+        float xv[BP_U];
+        b.load(rowT, valT, base, end);
+        if (!done) {
+            mid();
+            done = true;
+        }
+        b.gather(y, xv);
+        acc = b.fma(xv, acc);
+    }
+    if (!done) mid();
+    return group_sum(acc);
+}
+
 template <typename WT, typename IT>
 __device__ inline double bp_group(const int *__restrict__ ptrT, const IT *__restrict__ rowT,
                                   const WT *__restrict__ valT, int64_t q, const float *__restrict__ y,

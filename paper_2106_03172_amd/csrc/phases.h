@@ -71,15 +71,18 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
     const float tab2 = (KIND == UPD_SAGAEM && u.t2 != u.t) ? u.table[q2] : tab;
     Neighbours nb;
     if (KIND != UPD_OSEM) nb = load_neighbours(u.f, ix, iy, p.nx, p.ny);
-    const double b = bp_range(rowT, valT, beg, end, u.ratio, lig);
+    // the stencil sums need only f and its neighbours: they run while the
+    // first index/weight batch of the gather is in flight
+    double D = 0.0, E = 0.0, gr = 0.0;
+    const double b = bp_range_mid(rowT, valT, beg, end, u.ratio, lig, [&] {
+        if (p.beta > 0.0) {
+            if (EM) surrogate_nb((double)f, nb, p, D, E);
+            else if (KIND != UPD_OSEM) gr = penalty_grad_nb((double)f, nb, p);
+        }
+    });
     double b2 = b;
     if (KIND == UPD_SAGAEM && u.t2 != u.t) b2 = bp_group(ptrT, rowT, valT, q2, u.ratio2, lig);  // uniform branch
     if (lig != 0) return;
-    double D = 0.0, E = 0.0, gr = 0.0;
-    if (p.beta > 0.0) {
-        if (EM) surrogate_nb((double)f, nb, p, D, E);
-        else if (KIND != UPD_OSEM) gr = penalty_grad_nb((double)f, nb, p);
-    }
     float out;
     if (KIND == UPD_SAGAEM) {
         // Sec. 2.3, remark after eq. tempsvrem: the statistic uses the old entry
