@@ -297,18 +297,24 @@ __device__ inline double pair_dot(const IT *__restrict__ col, const WT *__restri
 // sum over t < Ns of x[t * stride + i], FP64, added in t order.  The loads
 // are issued 16 at a time (indices clamped in bounds, the extra values not
 // added): a load per iteration would wait for each one before the next add.
-__device__ inline double subset_sum(const float *__restrict__ x, int Ns, int64_t stride, int64_t i) {
+template <class Mid>
+__device__ inline double subset_sum_mid(const float *__restrict__ x, int Ns, int64_t stride, int64_t i, Mid mid) {
     constexpr int B = 16;
     double sum = 0.0;
     for (int t0 = 0; t0 < Ns; t0 += B) {
         float v[B];
 #pragma unroll
         for (int k = 0; k < B; ++k) v[k] = x[(int64_t)min(t0 + k, Ns - 1) * stride + i];
+        if (t0 == 0) mid();  // while the first batch is in flight
 #pragma unroll
         for (int k = 0; k < B; ++k)
             if (t0 + k < Ns) sum = sum + (double)v[k];
     }
     return sum;
+}
+
+__device__ inline double subset_sum(const float *__restrict__ x, int Ns, int64_t stride, int64_t i) {
+    return subset_sum_mid(x, Ns, stride, i, [] {});
 }
 
 // EM ratio g / ybar with the zero-denominator rule (0 if g == 0 or ybar <= 0)

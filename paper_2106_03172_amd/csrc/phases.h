@@ -154,10 +154,12 @@ __device__ inline void anchor_entry(const int *__restrict__ ptrT, const IT *__re
 
 // Anchor sums of pixel n from the table: SVREM s_anc (and s_hat at a reset),
 // SVRG g_tilde, SAGA / SAGA-EM Q (SAGA-EM also s_hat^0 = s(f^0)); returns the
-// table sum over the subsets.
-template <int KIND>
-__device__ inline double anchor_sum_pixel(const double *__restrict__ sens, int Ns, int N, const SnapArgs &a, int n) {
-    const double sum = subset_sum(a.table, Ns, N, n);
+// table sum over the subsets.  `mid()` runs while the first batch of table
+// loads is in flight.
+template <int KIND, class Mid>
+__device__ inline double anchor_sum_pixel(const double *__restrict__ sens, int Ns, int N, const SnapArgs &a, int n,
+                                         Mid mid) {
+    const double sum = subset_sum_mid(a.table, Ns, N, n, mid);
     if (KIND == UPD_SVREM) {
         const double sa = sum / (double)Ns;
         a.s_anc[n] = sa;
@@ -171,6 +173,11 @@ __device__ inline double anchor_sum_pixel(const double *__restrict__ sens, int N
         a.Q[n] = sum;
     }
     return sum;
+}
+
+template <int KIND>
+__device__ inline double anchor_sum_pixel(const double *__restrict__ sens, int Ns, int N, const SnapArgs &a, int n) {
+    return anchor_sum_pixel<KIND>(sens, Ns, N, a, n, [] {});
 }
 
 // The anchor sums of pixel n followed by the update of the iteration that
@@ -195,9 +202,13 @@ __device__ inline void anchor_sum_update_pixel(const float *__restrict__ sens_t,
     const double sn = sens[n];
     const double sh_prev = (KIND == UPD_SVREM) ? u.s_hat[n] : 0.0;  // before a reset overwrites it
     const float st = !EM ? sens_t[q] : 0.0f;
+    Neighbours nb;
+    if (EM && p.beta > 0.0) nb = load_neighbours_of(u.f, n, p);
     double D = 0.0, E = 0.0;
-    if (EM && p.beta > 0.0) surrogate_at(u.f, n, p, D, E);
-    const double sum = anchor_sum_pixel<KIND>(sens, Ns, N, a, n);
+    // the stencil sums run while the first batch of table loads is in flight
+    const double sum = anchor_sum_pixel<KIND>(sens, Ns, N, a, n, [&] {
+        if (EM && p.beta > 0.0) surrogate_nb((double)f, nb, p, D, E);
+    });
     float out;
     if (KIND == UPD_SVREM) {
         const double sa = sum / (double)Ns;  // s_anc[n], and s_hat[n] at a reset
