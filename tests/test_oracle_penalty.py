@@ -39,6 +39,7 @@ def _rand_img(rng, S, ny, nx):
 @pytest.mark.parametrize("kind", POTS)
 @pytest.mark.parametrize("axial", [False, True])
 def test_grad_is_finite_difference(kind, axial):
+    """P12: grad R equals a central finite difference of R."""
     rng = np.random.default_rng(5)
     S, ny, nx = (3 if axial else 1), 5, 6
     f = _rand_img(rng, S, ny, nx)
@@ -55,13 +56,14 @@ def test_grad_is_finite_difference(kind, axial):
 
 @pytest.mark.parametrize("kind", POTS)
 def test_grad_of_constant_is_zero(kind):
+    """P12: grad R(const) = 0 and R(const) = 0."""
     f = np.full((2, 30), 1.7)
     np.testing.assert_array_equal(oracle.penalty_grad(f, 5, 6, kind, 0.5, True), 0.0)
     assert oracle.penalty_value(f, 5, 6, kind, 0.5, True) == 0.0
 
 
 def test_quadratic_homogeneity():
-    """For rho = t^2/2, R is 2-homogeneous: <grad R(f), f> = 2 R(f)."""
+    """P12: for rho = t^2/2, R is 2-homogeneous: <grad R(f), f> = 2 R(f)."""
     rng = np.random.default_rng(2)
     f = _rand_img(rng, 1, 7, 9)
     g = oracle.penalty_grad(f, 7, 9)
@@ -104,7 +106,7 @@ def test_parabolic_surrogate_majorises(kind):
 
 
 def test_mstep_root_golden():
-    """Hand-solved roots of a/f - 2bf + c = 0 (tests/golden/mstep_roots.json)."""
+    """P11: hand-solved roots of a/f - 2bf + c = 0 (tests/golden/mstep_roots.json)."""
     with open(os.path.join(GOLDEN, "mstep_roots.json")) as fh:
         cases = json.load(fh)["cases"]
     for cse in cases:
@@ -113,6 +115,8 @@ def test_mstep_root_golden():
 
 
 def test_mstep_root_residual_and_limits():
+    """P11: residual of a/f - 2bf + c at the root, the b -> 0 limit -a/c, and the
+    stable and textbook forms agreeing where both are well conditioned."""
     rng = np.random.default_rng(1)
     a = rng.uniform(1e-3, 10, 10000)
     b = 10 ** rng.uniform(-8, 2, 10000)
