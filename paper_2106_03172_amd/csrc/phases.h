@@ -146,10 +146,19 @@ __device__ inline void anchor_entry(const int *__restrict__ ptrT, const IT *__re
                                     const WT *__restrict__ valT, const int *__restrict__ row_start, int Ns, int N,
                                     const SnapArgs &a, int64_t q, int lig) {
     const int t = (int)(q / N), n = (int)(q - (int64_t)t * N);
+    const PenaltyArgs &p = a.pen;
+    constexpr bool GRAD = (KIND != UPD_SVREM && KIND != UPD_SAGAEM);  // q_t carries -(beta/Ns) grad R
     const float f = a.f[n];
-    const double b = bp_group(ptrT, rowT, valT, q, a.ratio_all + row_start[t], lig);
+    Neighbours nb;
+    if (GRAD && p.beta > 0.0) nb = load_neighbours_of(a.f, n, p);
+    // the penalty gradient (anchor_finish's, from the same values) runs while
+    // the first index/weight batch of the gather is in flight
+    double gr = 0.0;
+    const double b = bp_range_mid(rowT, valT, ptrT[q], ptrT[q + 1], a.ratio_all + row_start[t], lig, [&] {
+        if (GRAD && p.beta > 0.0) gr = penalty_grad_nb((double)f, nb, p);
+    });
     if (lig != 0) return;
-    anchor_finish<KIND>(a, Ns, q, n, f, b);
+    a.table[q] = GRAD ? q_of(b, gr, p.beta, Ns) : tau_of(Ns, f, b);
 }
 
 // Anchor sums of pixel n from the table: SVREM s_anc (and s_hat at a reset),
