@@ -1,6 +1,7 @@
 // Per-pixel and per-(subset, pixel) bodies of the fused update and anchor
-// kernels, shared by the one-kernel-per-phase path (update.hip) and the
-// persistent epoch kernel (persist.hip), so both compute bitwise the same.
+// kernels, shared by the one-kernel-per-phase path (update.hip), the
+// persistent epoch kernel (persist.hip) and the batched serving kernels
+// (batch.hip), so all of them compute bitwise the same.
 #pragma once
 
 #include "common.h"
@@ -52,7 +53,7 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
     // The transposed row's bounds first (the gather chain starts there), then
     // every per-pixel operand and the stencil's neighbour values: none of
     // them depends on the gather, so all their loads are in flight with it;
-    // the penalty arithmetic runs after the gather.
+    // the penalty's stencil sums run while the gather's first batch is.
     const int beg = ptrT[q], end = ptrT[q + 1];
     const int iy = n / p.nx, ix = n - iy * p.nx;
     const float f = u.f[n];
