@@ -187,10 +187,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=("headline", "multislice", "serve", "serve-compare", "copy",
-                                           "convergence"),
+                                           "convergence", "algos"),
                     default="headline",
-                        help="headline: the JSON line below; multislice / serve / serve-compare / convergence: "
-                         "supplementary measurements")
+                        help="headline: the JSON line below; multislice / serve / serve-compare / convergence / "
+                         "algos: supplementary measurements")
     ap.add_argument("--epochs", type=float, default=50, help="convergence: epochs per curve")
     ap.add_argument("--curves-out", default="", help="convergence: write every curve as JSON to this file")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
@@ -222,6 +222,8 @@ def main():
         return bench_convergence(args)
     if args.workload == "copy":
         return bench_copy(args)
+    if args.workload == "algos":
+        return bench_algos(args)
     wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
     wb = 4 if args.wtype == "f32" else 2
     cfg = dict(datagen.CONFIG_HEADLINE)
@@ -367,6 +369,60 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+
+
+def bench_algos(args):
+    """Every update rule of the library on the headline workload (256 x 256,
+    252 x 344, 21 subsets, 1e6 counts, quadratic beta = 0.01), one after another
+    on one matrix: subset iterations per second and epochs per second in the
+    paper's accounting (Sec. 5.1: a pass over the data, i.e. Ns subset updates
+    or one anchor / table fill, counts one epoch).  SVREM alpha = 0.7, eta = 1;
+    SVRG alpha = 2, eta = 2 and SAGA alpha = 2 with the frozen subset
+    preconditioner (Sec. 5.1); SGA, BSREM (a_k = 1/(0.001 k + 1)) and SEM with
+    the decaying step; OSEM unpenalised.  Each figure is the median of five
+    timed blocks of --steps epoch calls."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2106_03172_amd as pkg
+    P = datagen.make_problem(**datagen.CONFIG_HEADLINE)
+    Ns, N = P.n_subsets, P.geom.n_pixels
+    A = pkg.SystemMatrix(P.geom, Ns, pkg.SVR_W_F32)
+    A.tune()
+    cases = [("osem", dict(), 1), ("svrem", dict(alpha=0.7, eta=1, beta=1e-2), 1),
+             ("svrg", dict(alpha=2.0, eta=2, beta=1e-2), 2), ("saga", dict(alpha=2.0, beta=1e-2), 1),
+             ("sga", dict(alpha=1.0, beta=1e-2), 1), ("bsrem", dict(alpha=1.0, beta=1e-2), 1),
+             ("sem", dict(alpha=1.0, beta=1e-2), 1)]
+    calls = max(1, args.steps)
+    reps = 5  # the median of five timed blocks of `calls` epoch calls
+    out = {}
+    for algo, kw, eta in cases:
+        R = pkg.Recon(A, P.g, P.w, np.ones((1, N), np.float32), pkg.params(algo, **kw))
+        R.osem_epoch(list(range(Ns)))
+        per = eta * Ns  # iterations per call: one anchor period for SVREM / SVRG
+        orders = [datagen.make_order(Ns, per, seed=4000 + i) for i in range(calls * reps + 5)]
+        for i in range(5):
+            R.epoch(algo, orders[i])
+        times = []
+        for r in range(reps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for i in range(calls):
+                R.epoch(algo, orders[5 + r * calls + i])
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        el = sorted(times)[reps // 2]
+        anchors = 1 if algo in ("svrem", "svrg") else 0  # one anchor pass per call
+        epochs = calls * (eta + anchors)
+        out[algo] = {"iterations_per_s": round(calls * per / el, 1), "epochs_per_s": round(epochs / el, 1),
+                     "ms_per_call": round(el / calls * 1e3, 4), "iterations_per_call": per,
+                     "epochs_per_call": eta + anchors}
+        log(f"{algo}: {out[algo]}")
+        R.close()
+    print(json.dumps({"workload": "algos", "metric": "subset iterations/s and epochs/s per update rule",
+                      "config": "SVREM 256x256 (2 mm), 252 views x 344 bins, 21 subsets, counts 1e6, FP32 weights",
+                      "calls": calls, "repetitions": reps, "results": out}), flush=True)
 
 
 def bench_copy(args):
