@@ -380,7 +380,8 @@ def bench_algos(args):
     SVRG alpha = 2, eta = 2 and SAGA alpha = 2 with the frozen subset
     preconditioner (Sec. 5.1); SGA, BSREM (a_k = 1/(0.001 k + 1)) and SEM with
     the decaying step; OSEM unpenalised.  Each figure is the median of five
-    timed blocks of --steps epoch calls."""
+    timed blocks of --steps epoch calls.  Also the wall time of one objective
+    evaluation (svr_objective, which synchronises) on the SVREM recon."""
     import numpy as np
     import torch
 
@@ -419,10 +420,18 @@ def bench_algos(args):
                      "ms_per_call": round(el / calls * 1e3, 4), "iterations_per_call": per,
                      "epochs_per_call": eta + anchors}
         log(f"{algo}: {out[algo]}")
+        if algo == "svrem":  # the objective (whole forward + log terms + penalty, FP64 sums; synchronises)
+            for _ in range(3):
+                R.objective()
+            t0 = time.perf_counter()
+            for _ in range(50):
+                R.objective()
+            objective_ms = (time.perf_counter() - t0) / 50 * 1e3
         R.close()
     print(json.dumps({"workload": "algos", "metric": "subset iterations/s and epochs/s per update rule",
                       "config": "SVREM 256x256 (2 mm), 252 views x 344 bins, 21 subsets, counts 1e6, FP32 weights",
-                      "calls": calls, "repetitions": reps, "results": out}), flush=True)
+                      "calls": calls, "repetitions": reps, "results": out,
+                      "objective_ms_per_call": round(objective_ms, 4)}), flush=True)
 
 
 def bench_copy(args):
