@@ -85,14 +85,14 @@ def epoch_bytes(A_info, nnz_t_mean, M, Mt_mean, N, Ns, wb, per):
             + per * (algorithmic_bytes("forward", *args) + algorithmic_bytes("update", *args)))
 
 
-def cpu_baseline(P, beta, alpha, eta, seconds):
+def cpu_baseline(P, beta, alpha, eta, seconds, label="256x256 / 252x344 / 21-subset", max_loops=200):
     """The FP64 oracle (as it stands) on the same workload, for ~``seconds``."""
     import numpy as np
 
     import datagen
     import oracle
     log("cpu baseline: building the oracle model")
-    Ao = oracle.system_matrix(P.geom)
+    Ao = oracle.system_matrix(P.geom, P.mu)
     m = oracle.Model(Ao, P.g, P.w, P.geom, P.n_subsets, beta=beta)
     f0 = oracle.osem_epoch(m, np.ones((1, P.geom.n_pixels)), range(P.n_subsets))
     alg = oracle.SVREM(m, f0, alpha, eta)
@@ -103,14 +103,14 @@ def cpu_baseline(P, beta, alpha, eta, seconds):
         alg.run(datagen.make_order(P.n_subsets, per, seed=9000 + loops))
         loops += 1
         el = time.perf_counter() - t0
-        if el >= seconds or loops >= 200:
+        if el >= seconds or loops >= max_loops:
             break
     cpu = time.process_time() - c0
     cores = max(1, int(round(cpu / el)))
     log(f"cpu baseline: {loops} outer loops in {el:.1f} s")
     return {"value": loops * (eta + 1) / el, "unit": "epochs/s", "cores": cores, "kind": "oracle",
             "sample": f"{loops} SVREM outer loops (anchor + {per} subset updates each) of the same "
-                      f"256x256 / 252x344 / 21-subset workload, FP64 NumPy+SciPy, {el:.1f} s wall"}
+                      f"{label} workload, FP64 NumPy+SciPy, {el:.1f} s wall"}
 
 
 def bench_convergence(args):
@@ -187,10 +187,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--workload", choices=("headline", "multislice", "serve", "serve-compare", "copy",
-                                           "convergence", "algos"),
+                                           "convergence", "algos", "small"),
                     default="headline",
                         help="headline: the JSON line below; multislice / serve / serve-compare / convergence / "
-                         "algos: supplementary measurements")
+                         "algos / small: supplementary measurements")
     ap.add_argument("--epochs", type=float, default=50, help="convergence: epochs per curve")
     ap.add_argument("--curves-out", default="", help="convergence: write every curve as JSON to this file")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
@@ -224,6 +224,8 @@ def main():
         return bench_copy(args)
     if args.workload == "algos":
         return bench_algos(args)
+    if args.workload == "small":
+        return bench_small(args)
     wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
     wb = 4 if args.wtype == "f32" else 2
     cfg = dict(datagen.CONFIG_HEADLINE)
@@ -432,6 +434,63 @@ def bench_algos(args):
                       "config": "SVREM 256x256 (2 mm), 252 views x 344 bins, 21 subsets, counts 1e6, FP32 weights",
                       "calls": calls, "repetitions": reps, "results": out,
                       "objective_ms_per_call": round(objective_ms, 4)}), flush=True)
+
+
+def bench_small(args):
+    """The small configuration (64 x 64 at 4 mm, 60 views x 95 bins, 6 subsets,
+    attenuation, 1e5 counts): OSEM and SVREM (alpha = 0.7, eta = 1, beta = 0.01)
+    epochs/s on the GPU and in the FP64 oracle on one host core, and their
+    ratio.  At this size every kernel is a few wavefronts, so the GPU figure is
+    the dispatch rate of the dependent launches."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    import paper_2106_03172_amd as pkg
+    P = datagen.make_problem(**datagen.CONFIG_SMALL)
+    Ns, N = P.n_subsets, P.geom.n_pixels
+    A = pkg.SystemMatrix(P.geom, Ns, pkg.SVR_W_F32, mu=P.mu)
+    calls = max(1, args.steps)
+    cyc = list(range(Ns))
+    out = {}
+    # GPU: OSEM epochs (Ns iterations each), then SVREM calls (anchor + Ns iterations = 2 epochs)
+    R = pkg.Recon(A, P.g, P.w, np.ones((1, N), np.float32), pkg.params("svrem", alpha=0.7, eta=1, beta=1e-2))
+    for _ in range(5):
+        R.osem_epoch(cyc)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(calls):
+        R.osem_epoch(cyc)
+    torch.cuda.synchronize()
+    out["osem_gpu_epochs_per_s"] = calls / (time.perf_counter() - t0)
+    orders = [datagen.make_order(Ns, Ns, seed=500 + i) for i in range(calls + 5)]
+    for i in range(5):
+        R.svrem_epoch(orders[i])
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(calls):
+        R.svrem_epoch(orders[5 + i])
+    torch.cuda.synchronize()
+    out["svrem_gpu_epochs_per_s"] = 2 * calls / (time.perf_counter() - t0)
+    # oracle (FP64, one core): OSEM epochs, then SVREM outer loops
+    Ao = oracle.system_matrix(P.geom, P.mu)
+    m = oracle.Model(Ao, P.g, P.w, P.geom, Ns)
+    f = np.ones((1, N))
+    n, t0 = 0, time.perf_counter()
+    while time.perf_counter() - t0 < min(args.cpu_seconds, 5.0):
+        f = oracle.osem_epoch(m, f, cyc)
+        n += 1
+    out["osem_oracle_epochs_per_s"] = n / (time.perf_counter() - t0)
+    cpu = cpu_baseline(P, 1e-2, 0.7, 1, min(args.cpu_seconds, 5.0), label="64x64 / 60x95 / 6-subset",
+                       max_loops=100000)
+    out["svrem_oracle_epochs_per_s"] = cpu["value"]
+    out["oracle_cores"] = cpu["cores"]
+    out["svrem_gpu_over_oracle"] = out["svrem_gpu_epochs_per_s"] / out["svrem_oracle_epochs_per_s"]
+    out["osem_gpu_over_oracle"] = out["osem_gpu_epochs_per_s"] / out["osem_oracle_epochs_per_s"]
+    print(json.dumps({"workload": "small", "metric": "OSEM and SVREM epochs/s, GPU and FP64 oracle",
+                      "config": "64x64 (4 mm), 60 views x 95 bins, 6 subsets, attenuation, counts 1e5",
+                      "calls": calls, **{k: round(v, 2) for k, v in out.items()}}), flush=True)
 
 
 def bench_copy(args):
