@@ -299,7 +299,7 @@ __device__ inline double pair_dot(const IT *__restrict__ col, const WT *__restri
 // added): a load per iteration would wait for each one before the next add.
 template <class Mid>
 __device__ inline double subset_sum_mid(const float *__restrict__ x, int Ns, int64_t stride, int64_t i, Mid mid) {
-    constexpr int B = 16;
+    constexpr int B = 32;  // one round trip for up to 32 subsets
     double sum = 0.0;
     for (int t0 = 0; t0 < Ns; t0 += B) {
         float v[B];
