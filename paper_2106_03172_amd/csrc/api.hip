@@ -26,6 +26,7 @@ struct svr_recon {
     int cur = 0;
     float *ratio = nullptr;             // M, subset-ordered
     double *s_hat = nullptr, *s_anc = nullptr, *Q = nullptr, *g_tilde = nullptr;
+    double *grad_anc = nullptr;         // SVRG / SAGA: grad R at the anchor, per pixel (N)
     float *table = nullptr;             // Ns*N
     float *dpre = nullptr;              // frozen preconditioner
     int dpre_per_subset = 0;
@@ -68,7 +69,7 @@ void free_recon(Recon *R) {
     if (!R) return;
     AllocStream as(R->owner);
     for (hipEvent_t e : R->ev) (void)hipEventDestroy(e);
-    void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ft, R->ratio, R->s_hat, R->s_anc, R->Q, R->g_tilde,
+    void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ft, R->ratio, R->s_hat, R->s_anc, R->Q, R->g_tilde, R->grad_anc,
                     R->table, R->dpre, R->part, R->scal, R->bad, R->d_order, R->d_sync, R->d_status};
     for (void *q : ptrs) dfree(q);
     delete R;
@@ -155,6 +156,12 @@ int anchor_iteration(Recon *R, int kind, UpdateArgs &u, hipStream_t s) {
     sa.g_tilde = R->g_tilde;
     sa.Q = R->Q;
     sa.pen = pen_of(R);
+    if ((kind == UPD_SVRG || kind == UPD_SAGA) && sa.pen.beta > 0.0 && R->grad_anc) {
+        // the table's penalty term, once per pixel instead of once per (subset, pixel)
+        rc = launch_penalty_grad(A, sa.f, sa.pen, R->grad_anc, s);
+        if (rc) return rc;
+        sa.grad = R->grad_anc;
+    }
     rc = prof_begin(R, 3, s);
     if (!rc) rc = launch_anchor_table(A, kind, sa, s);
     if (!rc) rc = prof_end(R, s);
@@ -779,6 +786,7 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     if (algo == SVR_ALGO_SVREM || algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA || algo == SVR_ALGO_SAGAEM)
         chk(dalloc(&R->table, NT));
     if (algo == SVR_ALGO_SVRG) chk(dalloc(&R->g_tilde, N));
+    if (algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) chk(dalloc(&R->grad_anc, N));
     if (algo == SVR_ALGO_SAGA || algo == SVR_ALGO_SAGAEM) chk(dalloc(&R->Q, N));
     if ((algo == SVR_ALGO_SVRG || algo == SVR_ALGO_SAGA) && p->precond != SVR_PRECOND_ITERATE) {
         R->dpre_per_subset = (p->precond == SVR_PRECOND_SUBSET_FROZEN);

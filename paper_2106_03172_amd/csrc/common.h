@@ -251,7 +251,13 @@ struct SnapArgs {
     double *g_tilde;
     double *Q;
     PenaltyArgs pen;
+    // SVRG / SAGA: grad R(f)_n per pixel, computed once for the table (every
+    // subset's entry of pixel n carries the same term); nullptr: each entry
+    // computes it from f itself (the same function on the same values)
+    const double *grad;
 };
+// grad R(f)_n of every pixel (the penalty of `p`) into out[N]
+int launch_penalty_grad(const Matrix &A, const float *f, const PenaltyArgs &p, double *out, hipStream_t s);
 int launch_anchor_table(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
 int launch_anchor_sum(const Matrix &A, int kind, const SnapArgs &a, hipStream_t s);
 // anchor sums fused with the update of the iteration that takes the anchor

@@ -138,7 +138,7 @@ template <int KIND>
 __device__ inline void anchor_finish(const SnapArgs &a, int Ns, int64_t q, int n, float f, double b) {
     const PenaltyArgs &p = a.pen;
     double gr = 0.0;
-    if (KIND != UPD_SVREM && KIND != UPD_SAGAEM && p.beta > 0.0) gr = penalty_grad_at(a.f, n, p);
+    if (KIND != UPD_SVREM && KIND != UPD_SAGAEM && p.beta > 0.0) gr = a.grad ? a.grad[n] : penalty_grad_at(a.f, n, p);
     a.table[q] = (KIND == UPD_SVREM || KIND == UPD_SAGAEM) ? tau_of(Ns, f, b) : q_of(b, gr, p.beta, Ns);
 }
 
@@ -150,13 +150,15 @@ __device__ inline void anchor_entry(const int *__restrict__ ptrT, const IT *__re
     const PenaltyArgs &p = a.pen;
     constexpr bool GRAD = (KIND != UPD_SVREM && KIND != UPD_SAGAEM);  // q_t carries -(beta/Ns) grad R
     const float f = a.f[n];
+    // the penalty gradient: the pixel's precomputed value, or (anchor_finish's,
+    // from the same values) computed while the first index/weight batch of the
+    // gather is in flight
+    const bool own = GRAD && p.beta > 0.0 && !a.grad;
+    double gr = (GRAD && p.beta > 0.0 && a.grad) ? a.grad[n] : 0.0;
     Neighbours nb;
-    if (GRAD && p.beta > 0.0) nb = load_neighbours_of(a.f, n, p);
-    // the penalty gradient (anchor_finish's, from the same values) runs while
-    // the first index/weight batch of the gather is in flight
-    double gr = 0.0;
+    if (own) nb = load_neighbours_of(a.f, n, p);
     const double b = bp_range_mid(rowT, valT, ptrT[q], ptrT[q + 1], a.ratio_all + row_start[t], lig, [&] {
-        if (GRAD && p.beta > 0.0) gr = penalty_grad_nb((double)f, nb, p);
+        if (own) gr = penalty_grad_nb((double)f, nb, p);
     });
     if (lig != 0) return;
     a.table[q] = GRAD ? q_of(b, gr, p.beta, Ns) : tau_of(Ns, f, b);

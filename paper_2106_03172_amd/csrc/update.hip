@@ -66,6 +66,18 @@ int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s)
 }
 
 // ---- anchor pass ---------------------------------------------------------------
+__global__ void __launch_bounds__(256) k_penalty_grad(const float *__restrict__ f, int N, PenaltyArgs p,
+                                                      double *__restrict__ out) {
+    const int n = blockIdx.x * 256 + threadIdx.x;
+    if (n >= N) return;
+    out[n] = penalty_grad_at(f, n, p);
+}
+
+int launch_penalty_grad(const Matrix &A, const float *f, const PenaltyArgs &p, double *out, hipStream_t s) {
+    SVR_HIP(launch_k(k_penalty_grad, (A.N + 255) / 256, 256, s, f, A.N, p, out));
+    return SVR_OK;
+}
+
 // table kernel: one BP_G-lane group per (subset, pixel), the same gather and
 // the same tau / q expressions as the iteration kernel
 template <int KIND, typename WT, typename IT>
