@@ -38,10 +38,14 @@ def log(msg):
 
 
 def kernel_source_hash():
+    """Hash of the kernel sources and the device compile flags: a profile taken
+    under another hash describes other machine code."""
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
         with open(os.path.join(ROOT, "paper_2106_03172_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
+    from paper_2106_03172_amd import build as _build
+    h.update(" ".join(_build.FLAGS).encode())
     return h.hexdigest()[:16]
 
 
@@ -186,6 +190,9 @@ def main():
     ap.add_argument("--eta", type=int, default=1)
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the size-based run lengths instead of autotuning them (a profiled run uses this so "
+                         "that its kernels do not depend on timings taken under the profiler)")
     ap.add_argument("--workload", choices=("headline", "multislice", "serve", "serve-compare", "copy",
                                            "convergence", "algos", "small"),
                     default="headline",
@@ -240,9 +247,13 @@ def main():
     build_s = time.perf_counter() - tb
     inf, per_subset = A.info()
     log(f"nnz = {inf.nnz}, build {build_s:.3f} s")
-    tuning = A.tune()
-    log(f"autotuned run lengths: forward {tuning[0]} rows/wavefront ({tuning[2]:.1f} us), "
-        f"anchor table {tuning[1]} rows/group ({tuning[3]:.1f} us)")
+    if args.no_tune:
+        tuning = A.tuning()
+        log(f"size-based run lengths: forward {tuning[0]}, anchor table {tuning[1]}")
+    else:
+        tuning = A.tune()
+        log(f"autotuned run lengths: forward {tuning[0]} rows/wavefront ({tuning[2]:.1f} us), "
+            f"anchor table {tuning[1]} rows/group ({tuning[3]:.1f} us)")
 
     f0 = np.ones((1, N), dtype=np.float32)
     flags = pkg.binding.FLAG_PERSISTENT_EPOCH if args.persistent else 0

@@ -27,6 +27,10 @@ ARCH = os.environ.get("SVR_OFFLOAD_ARCH", "gfx950")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17", "-ffp-contract=off",
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+    # a kernel's leading scalar and pointer arguments arrive in SGPRs at wave
+    # launch, so its first loads need not wait for the argument fetch (the code
+    # object keeps a prologue that loads them where the firmware cannot preload)
+    "-mllvm", "-amdgpu-kernarg-preload-count=16",
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 
