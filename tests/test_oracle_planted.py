@@ -8,11 +8,13 @@ import pytest
 import datagen
 import oracle
 import oracle.em as em
+import oracle.gradient as gradient
 import oracle.geometry as geometry
 import oracle.penalty as penalty
 
 import test_oracle_em as T_em
 import test_oracle_penalty as T_pen
+import test_oracle_schedules as T_sch
 import test_oracle_siddon as T_sid
 import test_oracle_variants as T_var
 
@@ -133,3 +135,67 @@ def test_sagaem_refresh_before_use_is_caught(monkeypatch):
     monkeypatch.setattr(em.SAGAEM, "step", bad_step)
     with pytest.raises(AssertionError):
         T_var.test_sagaem_refresh_stores_the_statistic_before_the_update()
+
+
+def test_sem_schedule_off_by_one_is_caught(monkeypatch):
+    """a_k = 1/(decay (k + 1) + 1): the first weight is no longer 1, so the
+    running mean of the harmonic schedule breaks."""
+    def bad_step(self, t):
+        a = self.a0 / (self.decay * (self.k + 1) + 1.0)
+        self.s_hat = (1.0 - a) * self.s_hat + a * self.m.tau_t(self.f, t)
+        self.f = self.m.mstep(self.s_hat, self.f)
+        self.k += 1
+    monkeypatch.setattr(em.SEM, "step", bad_step)
+    with pytest.raises(AssertionError):
+        T_sch.test_sem_harmonic_schedule_is_the_running_mean()
+
+
+def test_bsrem_without_decay_is_caught(monkeypatch):
+    def bad_step(self, t):
+        d = em._safe_div(self.f, self.m.sens_t[t])
+        self.f = np.maximum(0.0, self.f + self.alpha * d * self.m.grad_Phi_t(self.f, t))
+        self.k += 1
+    monkeypatch.setattr(gradient.BSREM, "step", bad_step)
+    with pytest.raises(AssertionError):
+        T_sch.test_bsrem_step_halves_at_k_1000()
+
+
+def test_svrem_anchor_every_ns_is_caught(monkeypatch):
+    """An anchor every Ns iterations whatever eta."""
+    def bad_step(self, t):
+        if self.k % self.m.Ns == 0:
+            self.anchor()
+        tau = self.m.tau_t(self.f, t)
+        self.s_hat = (1.0 - self.alpha) * self.s_hat + self.alpha * (tau - self.tau_anc[t] + self.s_anc)
+        self.f = self.m.mstep(self.s_hat, self.f)
+        self.k += 1
+    monkeypatch.setattr(em.SVREM, "step", bad_step)
+    with pytest.raises(AssertionError):
+        T_sch.test_svrem_takes_the_full_mstep_exactly_at_anchors(2)
+
+
+def test_svrg_anchor_every_ns_is_caught(monkeypatch):
+    def bad_step(self, t):
+        if self.k == 0:
+            self.f0 = self.f.copy()
+        if self.k % self.m.Ns == 0:
+            self.anchor()
+        d = gradient._precond(self.m, self.f, t, self.precond, self.f0)
+        direction = self.m.grad_Phi_t(self.f, t) - self.grad_anc[t] + self.g_tilde
+        self.f = np.maximum(0.0, self.f + self.alpha * d * direction)
+        self.k += 1
+    monkeypatch.setattr(gradient.SVRG, "step", bad_step)
+    with pytest.raises(AssertionError):
+        T_sch.test_svrg_takes_the_full_gradient_step_exactly_at_anchors(2)
+
+
+def test_contiguous_view_subsets_are_caught(monkeypatch):
+    """Subsets made of contiguous arcs of views are not balanced (Sec. 2.1)."""
+    def contiguous(geom, n_subsets):
+        B, per = geom.n_bins, geom.n_views // n_subsets
+        return [(np.arange(t * per, (t + 1) * per)[:, None] * B + np.arange(B)[None, :]).ravel()
+                for t in range(n_subsets)]
+    monkeypatch.setattr(em, "subset_rows", contiguous)
+    monkeypatch.setattr(oracle, "subset_rows", contiguous)
+    with pytest.raises(AssertionError):
+        T_sch.test_interleaved_subsets_are_balanced()

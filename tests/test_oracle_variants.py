@@ -223,3 +223,64 @@ def test_sagaem_converges_to_the_map_point():
         f = oracle.SAGAEM(m, f_init, 0.7).run(order, rf)
         rel = np.linalg.norm(f - fstar) / np.linalg.norm(fstar)
         assert rel < 1e-6, rel
+
+
+# ---------------------------------------------------------------------------
+# iteration-dependent preconditioner: the fixed-point bias of Sec. 4
+# ---------------------------------------------------------------------------
+
+def _bias_problem():
+    """12 x 12, 10 views in 4 interleaved subsets of 3, 3, 2 and 2 views: the
+    subset sensitivities A_t^T 1 differ by half, so d_t(f) = f / A_t^T 1 differ."""
+    P = datagen.make_problem(12, 12, 3.0, 10, 19, 3.0, 4, 3e4, attenuation=False, seed=5, bg_frac=0.1)
+    A = oracle.system_matrix(P.geom)
+    m = oracle.Model(A, P.g, P.w, P.geom, 4, beta=0.05)
+    f0 = oracle.osem_epoch(m, np.ones((1, 144)), range(4))
+    return m, f0
+
+
+def _kkt_residual(m, f):
+    """|grad Phi| on the support of f, relative to |A^T 1| there."""
+    g = m.grad_Phi(f)[0]
+    sup = f[0] > 1e-8 * f.max()
+    return float(np.linalg.norm(g[sup]) / np.linalg.norm(m.sens[sup]))
+
+
+def _preconditioned_sum(m, f):
+    """|sum_t d_t(f) grad Phi_t(f)| on the support, relative to |f| there."""
+    s = sum(oracle.em._safe_div(f, m.sens_t[t]) * m.grad_Phi_t(f, t) for t in range(m.Ns))[0]
+    sup = f[0] > 1e-8 * f.max()
+    return float(np.linalg.norm(s[sup]) / np.linalg.norm(f[0][sup]))
+
+
+def test_iterate_preconditioner_fixed_point_bias():
+    """Sec. 4, remark on iteration-dependent preconditioners: a preconditioned
+    incremental ascent with d_t(f^k) and a vanishing step converges to a point
+    where sum_t d_t(f*) grad Phi_t(f*) = 0, which is not the MAP point
+    (grad Phi(f*) != 0 on the support) unless all d_t coincide.  BSREM (step
+    1/(0.01 k + 1), cyclic order) shows it: the preconditioned sum goes to 0 like
+    the step while the KKT residual stays put, 3% away from the MAP image.
+    SVRG reaches the MAP point with the frozen preconditioner d = f^0 / A^T 1
+    and also with d_t(f^k): its direction at a fixed point is grad Phi / Ns."""
+    m, f0 = _bias_problem()
+    b = oracle.BSREM(m, f0, alpha=1.0, decay=0.01)
+    b.run(np.tile(np.arange(4), 5000))
+    bias_sum, bias_kkt = _preconditioned_sum(m, b.f), _kkt_residual(m, b.f)
+    assert bias_sum <= 1e-3, bias_sum
+    assert bias_kkt >= 5e-3, bias_kkt
+    assert bias_kkt >= 10 * bias_sum
+    s = oracle.SVRG(m, f0, alpha=1.0, eta=2, precond=oracle.PRECOND_FULL_FROZEN)
+    s.run(np.tile(np.arange(4), 3000))
+    assert _kkt_residual(m, s.f) <= 1e-10
+    assert _preconditioned_sum(m, s.f) >= 1e-2  # the MAP point is not BSREM's fixed point
+    si = oracle.SVRG(m, f0, alpha=0.5, eta=2, precond=oracle.PRECOND_ITERATE)
+    si.run(np.tile(np.arange(4), 3000))
+    assert _kkt_residual(m, si.f) <= 1e-5
+    d_map = np.linalg.norm(b.f - s.f) / np.linalg.norm(s.f)
+    assert d_map >= 1e-2, d_map
+    # the MAP point is the L-BFGS-B maximiser of Phi on f >= 0 (Sec. 5.1's reference method)
+    res = scipy.optimize.minimize(lambda x: -m.objective(x[None]), f0[0],
+                                  jac=lambda x: -m.grad_Phi(x[None])[0], method="L-BFGS-B",
+                                  bounds=[(0, None)] * f0.size,
+                                  options=dict(maxiter=5000, ftol=1e-15, gtol=1e-12))
+    assert np.linalg.norm(res.x - s.f[0]) / np.linalg.norm(s.f) <= 1e-5
