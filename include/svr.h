@@ -183,10 +183,13 @@ enum { SVR_ALGO_OSEM = 0, SVR_ALGO_SVREM = 1, SVR_ALGO_SVRG = 2, SVR_ALGO_SAGA =
        SVR_ALGO_SGA = 4, SVR_ALGO_BSREM = 5, SVR_ALGO_SEM = 6, SVR_ALGO_SAGAEM = 7 };
 /* Potentials of Table 1 (Sec. 3). */
 enum { SVR_PEN_QUADRATIC = 0, SVR_PEN_HUBER = 1, SVR_PEN_LOGCOSH = 2, SVR_PEN_HYPERBOLA = 3 };
-/* Preconditioner of the gradient methods (Sec. 4, eq. preconditioners, frozen
- * at the first iteration as the experiments of Sec. 5 do). */
-enum { SVR_PRECOND_SUBSET_FROZEN = 0,  /* d_t = f0 / A_t^T 1 */
-       SVR_PRECOND_FULL_FROZEN   = 1,  /* d   = f0 / A^T 1   */
+/* Preconditioner of SVRG and SAGA (Sec. 4, eq. preconditioners).  The
+ * experiments of Sec. 5 freeze it at the first iteration, d = d(f0); Theorem 1
+ * and Appendix B take one vector for every subset, f0 / A^T 1, which is the
+ * default (0).  The subset-indexed frozen form is about Ns times larger, so it
+ * needs a step about Ns times smaller than the paper's alpha = 2. */
+enum { SVR_PRECOND_FULL_FROZEN   = 0,  /* d   = f0 / A^T 1   (default) */
+       SVR_PRECOND_SUBSET_FROZEN = 1,  /* d_t = f0 / A_t^T 1 */
        SVR_PRECOND_ITERATE       = 2 };/* d_t = f^k / A_t^T 1 */
 #define SVR_FLAG_RESET_SHAT_AT_ANCHOR 1 /* SVREM: s_hat = s_anc at every anchor */
 #define SVR_FLAG_AXIAL_PENALTY        2 /* slices: add the 2 axial neighbours */

@@ -292,9 +292,11 @@ class SVREM:
         self.k = 0
         self.s_hat = None
         self.n_negative_a = 0
+        self.n_anchors = 0  # full passes taken (bookkeeping only)
 
     def anchor(self):
         m = self.m
+        self.n_anchors += 1
         self.f_anc = self.f.copy()
         self.tau_anc = [m.tau_t(self.f_anc, t) for t in range(m.Ns)]
         self.s_anc = sum(self.tau_anc) / m.Ns

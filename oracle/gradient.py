@@ -7,10 +7,10 @@ Readings:
 
 * ``grad Phi_t(f) = A_t^T(g_t / ybar_t) - A_t^T 1 - (beta/Ns) grad R(f)``;
 * preconditioner: the experiments freeze it at the starting image,
-  ``d = d(f^(0))`` (Sec. 4 remark and Sec. 5).  ``PRECOND_SUBSET_FROZEN``
-  (default) keeps the subset index of eq. preconditioners,
-  ``d_t = f^(0) / A_t^T 1``; ``PRECOND_FULL_FROZEN`` uses one vector
-  ``f^(0) / A^T 1`` (as in Theorem 1 and Appendix B); ``PRECOND_ITERATE``
+  ``d = d(f^(0))`` (Sec. 4 remark and Sec. 5).  ``PRECOND_FULL_FROZEN``
+  (default) uses one vector ``f^(0) / A^T 1`` for every subset, as Theorem 1
+  and Appendix B do; ``PRECOND_SUBSET_FROZEN`` keeps the subset index of
+  eq. preconditioners, ``d_t = f^(0) / A_t^T 1``; ``PRECOND_ITERATE``
   re-evaluates ``d_t(f^k) = f^k / A_t^T 1`` every iteration;
 * SAGA's table starts from one full pass at ``f^(0)`` (the paper does not
   say); the direction uses the table *before* the current update, and the
@@ -47,15 +47,17 @@ class SVRG:
     ``f <- max(0, f + alpha d_t (.) (grad Phi_t(f) - grad Phi_t(f_anc) + g_tilde))``.
     """
 
-    def __init__(self, model: Model, f0, alpha: float, eta: int, precond: int = PRECOND_SUBSET_FROZEN):
+    def __init__(self, model: Model, f0, alpha: float, eta: int, precond: int = PRECOND_FULL_FROZEN):
         self.m = model
         self.f = np.atleast_2d(np.asarray(f0, dtype=np.float64)).copy()
         self.f0 = self.f.copy()
         self.alpha, self.eta, self.precond = float(alpha), int(eta), precond
         self.k = 0
+        self.n_anchors = 0  # full passes taken (bookkeeping only)
 
     def anchor(self):
         m = self.m
+        self.n_anchors += 1
         self.f_anc = self.f.copy()
         self.grad_anc = [m.grad_Phi_t(self.f_anc, t) for t in range(m.Ns)]
         self.g_tilde = sum(self.grad_anc) / m.Ns
@@ -84,7 +86,7 @@ class SAGA:
     then ``q_t <- q_new``.
     """
 
-    def __init__(self, model: Model, f0, alpha: float, precond: int = PRECOND_SUBSET_FROZEN):
+    def __init__(self, model: Model, f0, alpha: float, precond: int = PRECOND_FULL_FROZEN):
         self.m = model
         self.f = np.atleast_2d(np.asarray(f0, dtype=np.float64)).copy()
         self.f0 = self.f.copy()

@@ -26,7 +26,7 @@ SVR_W_F32, SVR_W_F16, SVR_W_BF16 = 0, 1, 2
 SVR_W_INDEX32 = 0x100
 ALGO = dict(osem=0, svrem=1, svrg=2, saga=3, sga=4, bsrem=5, sem=6, sagaem=7)
 PEN = dict(quadratic=0, huber=1, logcosh=2, hyperbola=3)
-PRECOND = dict(subset_frozen=0, full_frozen=1, iterate=2)
+PRECOND = dict(full_frozen=0, subset_frozen=1, iterate=2)
 FLAG_RESET_SHAT_AT_ANCHOR, FLAG_AXIAL_PENALTY, FLAG_PERSISTENT_EPOCH, FLAG_MODIFIED_LL = 1, 2, 4, 8
 
 
@@ -172,8 +172,9 @@ def geometry(geom) -> svr_geometry:
 
 
 def params(algo="svrem", alpha=1.0, eta=1, beta=0.0, penalty="quadratic", delta=1.0,
-           precond="subset_frozen", flags=0, decay=0.001, ll_eps=0.0) -> svr_params:
-    """svr_params; ``ll_eps > 0`` also sets FLAG_MODIFIED_LL (the modified likelihood)."""
+           precond="full_frozen", flags=0, decay=0.001, ll_eps=0.0) -> svr_params:
+    """svr_params; ``ll_eps > 0`` also sets FLAG_MODIFIED_LL (the modified likelihood).  ``precond``
+    (SVRG, SAGA) defaults to the one frozen vector f0 / A^T 1 of Theorem 1."""
     if ll_eps > 0:
         flags |= FLAG_MODIFIED_LL
     return svr_params(ALGO[algo] if isinstance(algo, str) else int(algo), float(alpha), int(eta),
@@ -243,6 +244,15 @@ def svr_objective(R, stream=None) -> float:
 # ---------------------------------------------------------------------------
 # handle wrappers
 # ---------------------------------------------------------------------------
+def _slices(t, per_slice: int, name: str) -> int:
+    """Number of slices in t, which must hold a positive whole number of
+    per_slice values (the library reads and writes S * per_slice values)."""
+    n = int(t.numel() if hasattr(t, "numel") else np.size(t))
+    if n == 0 or n % per_slice:
+        raise ValueError(f"{name} holds {n} values, not a positive multiple of {per_slice}")
+    return n // per_slice
+
+
 class SystemMatrix:
     """A system matrix built on the device (``svr_build_system_matrix``)."""
 
@@ -304,18 +314,26 @@ class SystemMatrix:
         return int(t.fwd_pairs_per_wave), int(t.bp_rows_per_group), float(t.fwd_us), float(t.bp_us)
 
     def project(self, x, subset: int = -1, y=None, stream=None):
+        """y = A_t x for every slice of x ([S][N]); y ([S][M], natural order) is
+        allocated when not given, else must hold exactly S*M floats."""
         import torch
-        S = x.numel() // self.N
+        S = _slices(x, self.N, "x")
         if y is None:
             y = torch.zeros(S, self.M, dtype=torch.float32, device=x.device)
+        elif y.numel() != S * self.M:
+            raise ValueError(f"y holds {y.numel()} values, the projection of {S} slice(s) needs {S * self.M}")
         svr_project(self.h, subset, x, S, y, stream)
         return y
 
     def backproject(self, y, subset: int = -1, x=None, stream=None):
+        """x = A_t^T y for every slice of y ([S][M]); x ([S][N]) is allocated when
+        not given, else must hold exactly S*N floats."""
         import torch
-        S = y.numel() // self.M
+        S = _slices(y, self.M, "y")
         if x is None:
             x = torch.empty(S, self.N, dtype=torch.float32, device=y.device)
+        elif x.numel() != S * self.N:
+            raise ValueError(f"x holds {x.numel()} values, the back-projection of {S} slice(s) needs {S * self.N}")
         svr_backproject(self.h, subset, y, S, x, stream)
         return x
 
@@ -342,8 +360,11 @@ class Recon:
                 return x.to(device="cuda", dtype=torch.float32).contiguous()
             return torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32), device="cuda")
         self.A = A
+        S = _slices(g, A.M, "g")
+        if _slices(w, A.M, "w") != S or _slices(f0, A.N, "f0") != S:
+            raise ValueError(f"g, w and f0 must describe the same number of slices ({S})")
         self.g, self.w, f0 = dev(g), dev(w), dev(f0)
-        self.S = self.g.numel() // A.M
+        self.S = S
         self.prm = prm
         self.h = svr_recon_create(A.h, self.g, self.w, f0, self.S, prm, stream)
 
@@ -422,6 +443,9 @@ class Server:
                f0_value: float = 1.0, wtype: int = SVR_W_F32) -> int:
         g = np.ascontiguousarray(g, dtype=np.float32).ravel()
         w = np.ascontiguousarray(w, dtype=np.float32).ravel()
+        M = int(geom.n_views) * int(geom.n_bins)
+        if g.size != M or w.size != M:
+            raise ValueError(f"g and w must hold n_views * n_bins = {M} values (got {g.size}, {w.size})")
         req = svr_serve_request(geometry(geom), int(n_subsets), int(wtype), prm, int(epochs),
                                 int(order_seed), g.ctypes.data_as(C.POINTER(C.c_float)),
                                 w.ctypes.data_as(C.POINTER(C.c_float)), float(f0_value))

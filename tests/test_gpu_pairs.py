@@ -89,7 +89,7 @@ def test_pair_epochs_match_oracle(odd, algo):
     R.osem_epoch(list(range(Ns)))
     f_or = oracle.osem_epoch(m, f0, list(range(Ns)))
     alg = (oracle.SVREM(m, f_or, 0.5, 1) if algo == "svrem"
-           else oracle.SVRG(m, f_or, 0.5, 1, precond=binding.PRECOND["subset_frozen"]))
+           else oracle.SVRG(m, f_or, 0.5, 1, precond=oracle.PRECOND_SUBSET_FROZEN))
     for e in range(3):
         order = datagen.make_order(Ns, Ns, seed=50 + e)
         R.epoch(algo, order)

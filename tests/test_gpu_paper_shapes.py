@@ -45,7 +45,7 @@ def test_brain_like_svrem_saga_svrg(Ns):
         R = pkg.Recon(A, P.g, P.w, f0, pkg.params(algo, alpha=alpha, eta=eta, beta=beta, penalty="logcosh",
                                                    delta=delta, precond=pre))
         R.osem_epoch(cyc)
-        pc = binding.PRECOND[pre]
+        pc = getattr(oracle, "PRECOND_" + pre.upper())
         alg = {"svrem": lambda: oracle.SVREM(m, fo, alpha, eta),
                "svrg": lambda: oracle.SVRG(m, fo, alpha, eta, precond=pc),
                "saga": lambda: oracle.SAGA(m, fo, alpha, precond=pc)}[algo]()

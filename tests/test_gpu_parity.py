@@ -117,8 +117,8 @@ def _run_pair(P, Ao, A, algo, epochs, beta=0.0, alpha=1.0, eta=1, precond="subse
     mk = {
         "osem": None,
         "svrem": lambda f: oracle.SVREM(m, f, alpha, eta),
-        "svrg": lambda f: oracle.SVRG(m, f, alpha, eta, precond=binding.PRECOND[precond]),
-        "saga": lambda f: oracle.SAGA(m, f, alpha, precond=binding.PRECOND[precond]),
+        "svrg": lambda f: oracle.SVRG(m, f, alpha, eta, precond=getattr(oracle, "PRECOND_" + precond.upper())),
+        "saga": lambda f: oracle.SAGA(m, f, alpha, precond=getattr(oracle, "PRECOND_" + precond.upper())),
         "sga": lambda f: oracle.SGA(m, f, alpha),
         "bsrem": lambda f: oracle.BSREM(m, f, alpha),
         "sem": lambda f: oracle.SEM(m, f, alpha),

@@ -106,7 +106,7 @@ def test_modified_likelihood_matches_oracle(prob, algo, alpha, precond):
     eps = float(np.median(yb[P.g[0] > 0]))
     assert np.count_nonzero((yb <= eps) & (P.g[0] > 0)) > 1000
     m, R, fo = _init(P, Ao, A, beta, w=w0, eps=eps, algo=algo, alpha=alpha, eta=1, precond=precond)
-    pc = binding.PRECOND[precond]
+    pc = getattr(oracle, "PRECOND_" + precond.upper())
     alg = {"svrg": lambda: oracle.SVRG(m, fo, alpha, 1, precond=pc),
            "saga": lambda: oracle.SAGA(m, fo, alpha, precond=pc),
            "sga": lambda: oracle.SGA(m, fo, alpha),

@@ -190,7 +190,7 @@ def test_svrg_first_direction_is_full_gradient():
     """P13 (SVRG): at f = f_anc the direction is g_tilde = grad Phi(f_anc)/Ns."""
     P, A, m = _tiny_problem(Ns=3, beta=0.2)
     f0 = np.random.default_rng(8).uniform(0.5, 2.0, (1, A.shape[1]))
-    alg = oracle.SVRG(m, f0, 1.5, 2)
+    alg = oracle.SVRG(m, f0, 1.5, 2, precond=oracle.PRECOND_SUBSET_FROZEN)
     alg.step(1)
     d = oracle.em._safe_div(f0, m.sens_t[1])
     expect = np.maximum(0, f0 + 1.5 * d * m.grad_Phi(f0) / 3)
@@ -252,8 +252,8 @@ def test_vr_methods_converge_to_lbfgsb_maximiser():
     order = datagen.make_order(3, 3000, seed=1)
     runs = {
         "SVREM": oracle.SVREM(m, f_init, alpha=0.7, eta=1),
-        "SVRG": oracle.SVRG(m, f_init, 1.0, 2),
-        "SAGA": oracle.SAGA(m, f_init, 0.5),
+        "SVRG": oracle.SVRG(m, f_init, 1.0, 2, precond=oracle.PRECOND_SUBSET_FROZEN),
+        "SAGA": oracle.SAGA(m, f_init, 0.5, precond=oracle.PRECOND_SUBSET_FROZEN),
     }
     for name, alg in runs.items():
         alg.run(order)
