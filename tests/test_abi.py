@@ -71,3 +71,36 @@ def test_serve_config_is_validated(L):
     assert L.svr_serve_create(C.byref(cfg), C.byref(h)) == binding.SVR_EINVAL
     cfg = binding.svr_serve_config(1 << 30, 0, 1)
     assert L.svr_serve_create(C.byref(cfg), C.byref(h)) == binding.SVR_EINVAL
+
+
+def test_binding_rejects_mismatched_sizes_before_any_call():
+    """The wrappers check that the tensors they pass hold the sizes the
+    library will read and write (S*N, S*M), so a short buffer raises in Python
+    instead of reaching the device; no library call is made here."""
+    import numpy as np
+    import torch
+    from types import SimpleNamespace
+
+    A = object.__new__(pkg.SystemMatrix)
+    A.M, A.N, A.h = 12, 9, None
+    with pytest.raises(ValueError):
+        A.project(torch.zeros(10))                      # not a multiple of N
+    with pytest.raises(ValueError):
+        A.project(torch.zeros(18), y=torch.zeros(12))   # 2 slices need 24 outputs
+    with pytest.raises(ValueError):
+        A.backproject(torch.zeros(0))
+    with pytest.raises(ValueError):
+        A.backproject(torch.zeros(12), x=torch.zeros(8))
+    with pytest.raises(ValueError):
+        pkg.Recon(A, np.zeros(24), np.zeros(12), np.ones(18), pkg.params("svrem"))
+    with pytest.raises(ValueError):
+        pkg.Recon(A, np.zeros(12), np.zeros(12), np.ones(18), pkg.params("svrem"))
+    S = object.__new__(pkg.Server)
+    S.h, S._keep = None, {}
+    geom = SimpleNamespace(nx=3, ny=3, pixel_mm=1.0, n_views=3, n_bins=4, bin_mm=1.0)
+    with pytest.raises(ValueError):
+        S.submit(geom, 1, np.zeros(11), np.zeros(12), pkg.params("svrem"), 1, 0)
+    with pytest.raises(ValueError):
+        S.submit(geom, 1, np.zeros(12), np.zeros(13), pkg.params("svrem"), 1, 0)
+    S.h = None
+    A.h = None
