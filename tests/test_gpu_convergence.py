@@ -43,7 +43,7 @@ def setup():
 
 def test_reference_matches_lbfgsb(setup):
     P, A, m, fstar = setup
-    ref = cv.Method("SAGA", "saga", dict(alpha=0.5, beta=BETA, penalty=PEN, delta=DELTA))
+    ref = cv.Method("SAGA", "saga", dict(alpha=0.5, precond="subset_frozen", beta=BETA, penalty=PEN, delta=DELTA))
     f_ref, ep, change = cv.reference_image(A, P.g, P.w, ref, max_epochs=3000, tol=1e-7)
     d = np.linalg.norm(f_ref - fstar) / np.linalg.norm(fstar)
     print(f"reference: {ep} epochs, last change {change:.1e}, Delta vs L-BFGS-B {d:.2e}", flush=True)
@@ -54,8 +54,8 @@ def test_reference_matches_lbfgsb(setup):
 def test_epoch_accounting(setup):
     P, A, m, fstar = setup
     methods = [cv.Method("SVREM", "svrem", dict(alpha=0.7, eta=1, beta=BETA, penalty=PEN, delta=DELTA)),
-               cv.Method("SVRG", "svrg", dict(alpha=0.5, eta=2, beta=BETA, penalty=PEN, delta=DELTA)),
-               cv.Method("SAGA", "saga", dict(alpha=0.5, beta=BETA, penalty=PEN, delta=DELTA)),
+               cv.Method("SVRG", "svrg", dict(alpha=0.5, eta=2, precond="subset_frozen", beta=BETA, penalty=PEN, delta=DELTA)),
+               cv.Method("SAGA", "saga", dict(alpha=0.5, precond="subset_frozen", beta=BETA, penalty=PEN, delta=DELTA)),
                cv.Method("OSEM", "osem", {})]
     curves = cv.compare(A, P.g, P.w, methods, 6)
     ep = {c.name: c.epochs for c in curves}
@@ -74,8 +74,8 @@ def test_variance_reduction_reaches_the_map_point(setup):
     pen = dict(beta=BETA, penalty=PEN, delta=DELTA)
     methods = [cv.Method("SVREM", "svrem", dict(alpha=0.7, eta=1, **pen)),
                cv.Method("SAGA-EM", "sagaem", dict(alpha=0.7, **pen)),
-               cv.Method("SVRG", "svrg", dict(alpha=0.5, eta=2, **pen)),
-               cv.Method("SAGA", "saga", dict(alpha=0.5, **pen)),
+               cv.Method("SVRG", "svrg", dict(alpha=0.5, eta=2, precond="subset_frozen", **pen)),
+               cv.Method("SAGA", "saga", dict(alpha=0.5, precond="subset_frozen", **pen)),
                cv.Method("OSEM", "osem", {}),
                cv.Method("SGA", "sga", dict(alpha=1.0, **pen)),
                cv.Method("BSREM", "bsrem", dict(alpha=1.0, decay=0.001, **pen)),

@@ -42,11 +42,13 @@ def test_stored_weights_rounding(prob, wtype, bound):
         assert np.all(err[~normal] <= 2.0 ** -25)
 
 
-@pytest.mark.parametrize("wtype,tol", [(pkg.SVR_W_F32, 1e-5), (pkg.SVR_W_F16, 1e-3), (pkg.SVR_W_BF16, 1e-2)])
-def test_svrem_error_vs_fp64_oracle(prob, wtype, tol):
-    """Final-iterate and objective error of 5 SVREM epochs per weight type.
-    The bound for 16-bit weights is the weight rounding itself: a relative
-    perturbation eps of A moves the iterate by O(eps)."""
+@pytest.mark.parametrize("wtype,tol,phi_tol", [(pkg.SVR_W_F32, 1e-5, 1e-9), (pkg.SVR_W_F16, 2e-4, 1e-8),
+                                              (pkg.SVR_W_BF16, 1.2e-3, 5e-7)])
+def test_svrem_error_vs_fp64_oracle(prob, wtype, tol, phi_tol):
+    """Final-iterate and objective error of 5 SVREM epochs per weight type,
+    bounded at 1.5x what they measure (FP16 1.1e-4, BF16 8.2e-4; objectives
+    2.1e-9 and 1.9e-7).  A relative perturbation eps of A moves the iterate by
+    O(eps): 2^-11 for FP16, 2^-8 for BF16."""
     P, Ao = prob
     beta = 1e-2
     A = pkg.SystemMatrix(P.geom, P.n_subsets, wtype)
@@ -65,4 +67,43 @@ def test_svrem_error_vs_fp64_oracle(prob, wtype, tol):
     phi_err = abs(R.objective() - m.objective(alg.f)) / abs(m.objective(alg.f))
     print(f"wtype {wtype}: iterate rel L2 {err:.3e}, objective rel {phi_err:.3e}")
     assert err <= tol
-    assert phi_err <= tol * 1e-2
+    assert phi_err <= phi_tol
+
+
+@pytest.fixture(scope="module")
+def headline_oracle():
+    """The headline problem (256^2, 252 x 344, 21 subsets, counts 1e6, beta 1e-2)
+    and the FP64 oracle's SVREM run (alpha 0.7, eta 1) over 50 epochs."""
+    P = datagen.make_problem(**datagen.CONFIG_HEADLINE)
+    Ao = oracle.system_matrix(P.geom)
+    m = oracle.Model(Ao, P.g, P.w, P.geom, P.n_subsets, beta=1e-2)
+    alg = oracle.SVREM(m, oracle.osem_epoch(m, np.ones((1, P.geom.n_pixels)), range(P.n_subsets)), 0.7, 1)
+    orders = [datagen.make_order(P.n_subsets, P.n_subsets, seed=3000 + 100 * c) for c in range(25)]
+    for o in orders:
+        alg.run(o)
+    return P, m, orders, alg.f, m.objective(alg.f)
+
+
+@pytest.mark.parametrize("wtype,tol,phi_tol", [(pkg.SVR_W_F32, 1e-5, 1e-9), (pkg.SVR_W_F16, 2.75e-4, 1.2e-7),
+                                              (pkg.SVR_W_BF16, 2.2e-3, 1.8e-7)])
+def test_headline_precision_sweep(headline_oracle, wtype, tol, phi_tol):
+    """The precision sweep at the headline size: weights stored FP32, FP16 or
+    BF16, FP64 accumulation and FP64 running statistics, 50 SVREM epochs
+    (Sec. 5.1 accounting).  The FP64 oracle with FP16- or BF16-rounded weights
+    ends 2.2e-4 / 1.8e-3 from the exact-weight run: that is what 16-bit weights
+    cost here, so BF16 stays above a 1e-3 bar and FP16 below it; the GPU
+    measures the same (2.20e-4, 1.77e-3).  The objective the library reports is
+    evaluated with its own stored weights: 7.6e-8 (FP16) and 1.1e-7 (BF16) from
+    the oracle's.  Bounds: 1.25x the iterate errors, 1.5x the objective ones."""
+    P, m, orders, f_or, phi_or = headline_oracle
+    A = pkg.SystemMatrix(P.geom, P.n_subsets, wtype)
+    R = pkg.Recon(A, P.g, P.w, np.ones((1, P.geom.n_pixels)), pkg.params("svrem", alpha=0.7, eta=1, beta=1e-2))
+    R.osem_epoch(list(range(P.n_subsets)))
+    for o in orders:
+        R.svrem_epoch(o)
+    fg = R.image().cpu().numpy()
+    err = rel(fg, f_or)
+    phi_err = abs(R.objective() - phi_or) / abs(phi_or)
+    print(f"wtype {wtype}: 50 epochs, iterate rel L2 {err:.3e}, objective rel {phi_err:.3e}", flush=True)
+    assert err <= tol
+    assert phi_err <= phi_tol

@@ -74,27 +74,86 @@ def test_stack_rejects_gradient_algorithms():
         pkg.Recon(A, P.g, P.w, np.ones((3, 256)), pkg.params("saga"))
 
 
-def test_full_size_stack_sampled_slices():
-    """127 slices of 285 x 285 (2.5 mm), 344 views x 435 bins, 21 subsets,
-    in-plane penalty only, so slices are independent: sampled slices of the
-    GPU stack are compared with single-slice oracle runs of the same data."""
+def _bf16_weights(A):
+    """The FP64 lengths rounded as the library stores BF16 weights: to FP32,
+    then to BF16 with round-to-nearest-even (test-side rounding of the
+    oracle's own matrix)."""
+    u = np.asarray(A.data, np.float32).view(np.uint32).astype(np.uint64)
+    r = (((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16).astype(np.uint32)
+    B = A.copy()
+    B.data = r.view(np.float32).astype(np.float64)
+    return B
+
+
+@pytest.fixture(scope="module")
+def full_stack():
     cfg = datagen.CONFIG_MULTISLICE
     P = datagen.make_multislice_problem(cfg["nx"], cfg["ny"], cfg["pixel_mm"], cfg["n_views"], cfg["n_bins"],
                                         cfg["bin_mm"], cfg["n_subsets"], cfg["counts"], n_slices=cfg["n_slices"],
                                         seed=cfg["seed"])
+    Ao = oracle.system_matrix(P.geom)
+    return cfg, P, Ao
+
+
+@pytest.mark.parametrize("wtype", [pkg.SVR_W_F32, pkg.SVR_W_BF16])
+def test_full_size_stack_sampled_slices(full_stack, wtype):
+    """127 slices of 285 x 285 (2.5 mm), 344 views x 435 bins, 21 subsets,
+    in-plane penalty only, so slices are independent: sampled slices of the
+    GPU stack after OSEM and 3 SVREM calls (6 epochs) are compared with
+    single-slice oracle runs of the same data.  BF16 weights are compared with
+    the oracle run on the same BF16-rounded lengths (parity bar), and with the
+    exact lengths (the precision cost, about 1e-3)."""
+    cfg, P, Ao = full_stack
     Ns, S = cfg["n_subsets"], cfg["n_slices"]
-    A = pkg.SystemMatrix(P.geom, Ns)
+    A = pkg.SystemMatrix(P.geom, Ns, wtype)
     beta = 1e-3
     f0 = np.ones((S, P.geom.n_pixels))
     R = pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem", alpha=0.7, eta=1, beta=beta))
     R.osem_epoch(list(range(Ns)))
-    o = datagen.make_order(Ns, Ns, seed=90)
-    R.svrem_epoch(o)
+    orders = [datagen.make_order(Ns, Ns, seed=90 + c) for c in range(3)]
+    for o in orders:
+        R.svrem_epoch(o)
     fg = R.image().cpu().numpy()
-    Ao = oracle.system_matrix(P.geom)
-    for sl in (0, 63, 126):
-        m = oracle.Model(Ao, P.g[sl:sl + 1], P.w[sl:sl + 1], P.geom, Ns, beta=beta)
-        f = oracle.osem_epoch(m, np.ones((1, P.geom.n_pixels)), range(Ns))
-        alg = oracle.SVREM(m, f, 0.7, 1)
+    Aw = Ao if wtype == pkg.SVR_W_F32 else _bf16_weights(Ao)
+    sample = [0, 63, 126]
+    errs = []
+    for Am in ((Aw,) if wtype == pkg.SVR_W_F32 else (Aw, Ao)):
+        # the sampled slices as a 3-slice stack without axial coupling: each
+        # slice runs exactly as alone
+        m = oracle.Model(Am, P.g[sample], P.w[sample], P.geom, Ns, beta=beta)
+        alg = oracle.SVREM(m, oracle.osem_epoch(m, np.ones((3, P.geom.n_pixels)), range(Ns)), 0.7, 1)
+        for o in orders:
+            alg.run(o)
+        errs.append([rel(fg[sl], alg.f[i]) for i, sl in enumerate(sample)])
+    print(f"wtype {wtype} slices {sample}: rel L2 {errs}", flush=True)
+    assert max(errs[0]) <= 1e-5
+    if len(errs) > 1:
+        assert max(errs[1]) <= 2.5e-3
+
+
+@pytest.mark.parametrize("wtype", [pkg.SVR_W_F32, pkg.SVR_W_BF16])
+def test_axial_stack_at_full_in_plane_size(full_stack, wtype):
+    """The stack's in-plane size (285 x 285, 344 x 435, 21 subsets) with the
+    8 + 2 axial penalty, on the first 6 slices (the axial coupling makes every
+    slice depend on all others, so the oracle runs the whole stack): OSEM and
+    3 SVREM calls (6 epochs) against the oracle, every call."""
+    cfg, P, Ao = full_stack
+    Ns, S = cfg["n_subsets"], 6
+    g, w = P.g[:S], P.w[:S]
+    A = pkg.SystemMatrix(P.geom, Ns, wtype)
+    beta = 1e-3
+    f0 = np.ones((S, P.geom.n_pixels))
+    R = pkg.Recon(A, g, w, f0, pkg.params("svrem", alpha=0.7, eta=1, beta=beta, flags=binding.FLAG_AXIAL_PENALTY))
+    Aw = Ao if wtype == pkg.SVR_W_F32 else _bf16_weights(Ao)
+    m = oracle.Model(Aw, g, w, P.geom, Ns, beta=beta, axial=True)
+    R.osem_epoch(list(range(Ns)))
+    alg = oracle.SVREM(m, oracle.osem_epoch(m, f0, range(Ns)), 0.7, 1)
+    for c in range(3):
+        o = datagen.make_order(Ns, Ns, seed=120 + c)
+        R.svrem_epoch(o)
         alg.run(o)
-        assert rel(fg[sl], alg.f) <= 1e-5, sl
+        e = rel(R.image().cpu().numpy(), alg.f)
+        print(f"wtype {wtype} axial call {c}: rel L2 {e:.2e}", flush=True)
+        assert e <= 1e-5, (c, e)
+    phi = R.objective()
+    assert abs(phi - m.objective(R.image().cpu().numpy().astype(np.float64))) <= 1e-6 * abs(phi)

@@ -161,3 +161,49 @@ def test_variant_arguments_are_validated(prob):
     with pytest.raises(pkg.SvrError):
         R.svrem_epoch([0])  # wrong algo for this recon
     R.sagaem_epoch([0, 1], [2, 3])
+
+
+def test_iterate_preconditioner_fixed_point_bias_on_gpu():
+    """Sec. 4, remark on iteration-dependent preconditioners, on the device:
+    BSREM (d_t(f^k) = f^k / A_t^T 1, step 1/(0.01 k + 1), 20,000 cyclic
+    updates) settles where sum_t d_t grad Phi_t = 0, off the MAP point; SVRG
+    with d_t(f^k) reaches the MAP point.  Both agree with the oracle, and the
+    FP64 residuals of the GPU images show the bias."""
+    P = datagen.make_problem(12, 12, 3.0, 10, 19, 3.0, 4, 3e4, attenuation=False, seed=5, bg_frac=0.1)
+    Ao = oracle.system_matrix(P.geom)
+    A = pkg.SystemMatrix(P.geom, 4, pkg.SVR_W_F32)
+    beta = 0.05
+    m = oracle.Model(Ao, P.g, P.w, P.geom, 4, beta=beta)
+    f0 = np.ones((1, 144))
+    fo = oracle.osem_epoch(m, f0, range(4))
+    cyc = np.tile(np.arange(4, dtype=np.int32), 5000)
+
+    def residuals(f):
+        f = np.asarray(f, np.float64).reshape(1, -1)
+        sup = f[0] > 1e-8 * f.max()
+        kkt = np.linalg.norm(m.grad_Phi(f)[0][sup]) / np.linalg.norm(m.sens[sup])
+        s = sum(oracle.em._safe_div(f, m.sens_t[t]) * m.grad_Phi_t(f, t) for t in range(4))[0]
+        return kkt, np.linalg.norm(s[sup]) / np.linalg.norm(f[0][sup])
+
+    R = pkg.Recon(A, P.g, P.w, f0.astype(np.float32), pkg.params("bsrem", alpha=1.0, beta=beta, decay=0.01))
+    R.osem_epoch(list(range(4)))
+    R.bsrem_epoch(cyc)
+    fb = R.image().cpu().numpy()
+    ob = oracle.BSREM(m, fo, alpha=1.0, decay=0.01)
+    ob.run(cyc)
+    assert rel(fb, ob.f) <= 1e-5
+    kkt_b, sum_b = residuals(fb)
+    R2 = pkg.Recon(A, P.g, P.w, f0.astype(np.float32), pkg.params("svrg", alpha=0.5, eta=2, beta=beta,
+                                                                  precond="iterate"))
+    R2.osem_epoch(list(range(4)))
+    R2.svrg_epoch(cyc[:12000])
+    fs = R2.image().cpu().numpy()
+    os_ = oracle.SVRG(m, fo, alpha=0.5, eta=2, precond=oracle.PRECOND_ITERATE)
+    os_.run(cyc[:12000])
+    assert rel(fs, os_.f) <= 1e-5
+    kkt_s, sum_s = residuals(fs)
+    print(f"BSREM: KKT {kkt_b:.2e}, preconditioned sum {sum_b:.2e}; SVRG(d_t(f^k)): KKT {kkt_s:.2e}, "
+          f"sum {sum_s:.2e}; distance {rel(fb, fs):.2e}", flush=True)
+    assert sum_b <= 1e-3 and kkt_b >= 5e-3
+    assert kkt_s <= 1e-5 and sum_s >= 1e-2
+    assert rel(fb, fs) >= 1e-2
