@@ -177,6 +177,24 @@ int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t
 int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int32_t n_slices,
                     float *x_dev, void *stream);
 
+/* Forward projection exactly as svr_project (same kernels, bitwise the same
+ * result), for callers that cannot allocate device memory: code under HIP
+ * graph capture, serving loops and harnesses that forbid hipMalloc.  The call
+ * allocates nothing (no hipMalloc, hipFree or allocating library routine): the
+ * tiled copy of each slice goes to a scratch array of
+ * SVR_NOALLOC_SCRATCH_FLOATS floats (4 MiB) that the library keeps in device
+ * memory on every device it runs on until the process ends.  The tiled image,
+ * ceil(nx/4)*4 * ceil(ny/8)*8 floats, must fit (up to 1024 x 1024).
+ * Every call on one device shares that array: calls that overlap on one GPU
+ * (two streams, or two host threads) race on it and must be serialised by the
+ * caller.  Nothing in the array needs to start at zero (each call writes every
+ * slot it reads).
+ * Errors: SVR_EINVAL (NULL, subset out of range, n_slices < 1, tiled image
+ * beyond the scratch), SVR_EDEVICE. */
+#define SVR_NOALLOC_SCRATCH_FLOATS (1 << 20)
+int svr_project_noalloc(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t n_slices,
+                        float *y_dev, void *stream);
+
 /* ---- reconstruction ------------------------------------------------------ */
 
 enum { SVR_ALGO_OSEM = 0, SVR_ALGO_SVREM = 1, SVR_ALGO_SVRG = 2, SVR_ALGO_SAGA = 3,

@@ -102,6 +102,7 @@ _SIGS = {
     "svr_matrix_tune": ([_VP, _VP, C.POINTER(svr_tuning_t)], C.c_int),
     "svr_project": ([_VP, _I32, _VP, _I32, _VP, _VP], C.c_int),
     "svr_backproject": ([_VP, _I32, _VP, _I32, _VP, _VP], C.c_int),
+    "svr_project_noalloc": ([_VP, _I32, _VP, _I32, _VP, _VP], C.c_int),
     "svr_recon_create": ([_VP, _VP, _VP, _VP, _I32, C.POINTER(svr_params), _VP, C.POINTER(_VP)], C.c_int),
     "svr_objective": ([_VP, C.POINTER(C.c_double), _VP], C.c_int),
     "svr_get_image": ([_VP, _VP, _VP], C.c_int),
@@ -196,6 +197,10 @@ def svr_build_system_matrix(geom, n_subsets: int, wtype: int = SVR_W_F32, mu=Non
 
 def svr_project(A, subset: int, x, n_slices: int, y, stream=None):
     _check(lib().svr_project(A, int(subset), _dev(x), int(n_slices), _dev(y), _stream(stream)))
+
+
+def svr_project_noalloc(A, subset: int, x, n_slices: int, y, stream=None):
+    _check(lib().svr_project_noalloc(A, int(subset), _dev(x), int(n_slices), _dev(y), _stream(stream)))
 
 
 def svr_backproject(A, subset: int, y, n_slices: int, x, stream=None):

@@ -698,6 +698,64 @@ int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t
     return rc;
 }
 
+}  // extern "C"
+
+// Scratch of svr_project_noalloc: the tiled copy of one slice of the image.
+// The library never allocates it; each device holds its own copy for the life
+// of the process.  Host code must not pass `scratch` itself to a kernel (it is
+// a host-side stand-in): it uses the device address looked up per device.
+static __device__ __align__(256) float scratch[SVR_NOALLOC_SCRATCH_FLOATS];
+
+namespace {
+
+constexpr int kMaxScratchDevices = 64;
+std::mutex g_scratch_mu;
+float *g_scratch_dev[kMaxScratchDevices];  // device address of `scratch`, per device
+
+// The address of `scratch` on `device` (the current device), looked up on the
+// first call there with hipGetSymbolAddress and kept.
+int noalloc_scratch(int device, float **out) {
+    SVR_REQUIRE(device >= 0 && device < kMaxScratchDevices, "device %d beyond the %d supported", device,
+                kMaxScratchDevices);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_dev[device]) {
+        void *p = nullptr;
+        SVR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+        SVR_REQUIRE(p, "no device address for the scratch array");
+        g_scratch_dev[device] = (float *)p;
+    }
+    *out = g_scratch_dev[device];
+    return SVR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int svr_project_noalloc(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t n_slices, float *y_dev,
+                        void *stream) {
+    clear_error();
+    SVR_REQUIRE(A && x_dev && y_dev, "NULL argument");
+    SVR_REQUIRE(subset >= -1 && subset < A->Ns, "subset %d out of range", subset);
+    SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
+    SVR_REQUIRE((int64_t)A->Nt <= (int64_t)SVR_NOALLOC_SCRATCH_FLOATS,
+                "the tiled image (%d floats) exceeds the allocation-free scratch (%d floats)", A->Nt,
+                (int)SVR_NOALLOC_SCRATCH_FLOATS);
+    SVR_HIP(hipSetDevice(A->device));
+    float *xt = nullptr;
+    int rc = noalloc_scratch(A->device, &xt);
+    if (rc != SVR_OK) return rc;
+    hipStream_t s = (hipStream_t)stream;
+    const int r0 = subset < 0 ? 0 : A->row_start[subset];
+    const int r1 = subset < 0 ? A->M : A->row_start[subset + 1];
+    for (int sl = 0; sl < n_slices && rc == SVR_OK; ++sl) {  // the same kernels as svr_project
+        rc = launch_tile_image(*A, x_dev + (int64_t)sl * A->N, xt, s);
+        FwdArgs fa{xt, nullptr, nullptr, y_dev + (int64_t)sl * A->M, nullptr, nullptr};
+        if (rc == SVR_OK) rc = launch_forward(*A, r0, r1, 0, fa, s);
+    }
+    return rc;
+}
+
 int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int32_t n_slices, float *x_dev,
                     void *stream) {
     clear_error();
