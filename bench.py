@@ -194,13 +194,18 @@ def main():
                     help="keep the size-based run lengths instead of autotuning them (a profiled run uses this so "
                          "that its kernels do not depend on timings taken under the profiler)")
     ap.add_argument("--workload", choices=("headline", "multislice", "serve", "serve-compare", "copy",
-                                           "convergence", "algos", "small"),
+                                           "convergence", "algos", "small", "projectors"),
                     default="headline",
                         help="headline: the JSON line below; multislice / serve / serve-compare / convergence / "
                          "algos / small: supplementary measurements")
     ap.add_argument("--epochs", type=float, default=50, help="convergence: epochs per curve")
     ap.add_argument("--curves-out", default="", help="convergence: write every curve as JSON to this file")
     ap.add_argument("--requests", type=int, default=200, help="serve: number of requests")
+    ap.add_argument("--serve-requests", type=int, default=48,
+                    help="headline: requests of the serving stream for the p50/p99 latency and the batched "
+                         "FP32/BF16/FP16 comparison in the JSON line (0: skip)")
+    ap.add_argument("--fwd-natural-order", action="store_true",
+                    help="per-subset forward passes take their rows in order instead of one bin band per XCD")
     ap.add_argument("--persistent", action="store_true",
                     help="one persistent cooperative kernel per epoch call instead of one kernel per phase")
     args = ap.parse_args()
@@ -233,6 +238,8 @@ def main():
         return bench_algos(args)
     if args.workload == "small":
         return bench_small(args)
+    if args.workload == "projectors":
+        return bench_projectors(args)
     wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
     wb = 4 if args.wtype == "f32" else 2
     cfg = dict(datagen.CONFIG_HEADLINE)
@@ -255,6 +262,8 @@ def main():
         log(f"autotuned run lengths: forward {tuning[0]} rows/wavefront ({tuning[2]:.1f} us), "
             f"anchor table {tuning[1]} rows/group ({tuning[3]:.1f} us)")
 
+    if args.fwd_natural_order:
+        A.set_tuning(tuning[0], tuning[1], fwd_natural_order=1)
     f0 = np.ones((1, N), dtype=np.float32)
     flags = pkg.binding.FLAG_PERSISTENT_EPOCH if args.persistent else 0
     R = pkg.Recon(A, P.g, P.w, f0, pkg.params("svrem", alpha=args.alpha, eta=args.eta, beta=args.beta,
@@ -310,7 +319,9 @@ def main():
     traffic = traffic_from_profile(dom, args.wtype)
     roofline = {"bound": "hbm", "achieved": round(d["gbs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(d["gbs"] / HBM_PEAK_GBS, 4), "traffic": traffic, "kernel": dom,
-                "avg_us": round(d["avg_us"], 3), "bytes_per_launch": int(d["algorithmic_bytes"])}
+                "avg_us": round(d["avg_us"], 3), "bytes_per_launch": int(d["algorithmic_bytes"]),
+                "duration": "mean of HIP events attached to each dispatch of the kernel on the library's stream, "
+                            "over a second pass of the timed steps"}
 
     # standalone projectors over the whole matrix
     x = torch.rand(1, N, device="cuda")
@@ -359,6 +370,13 @@ def main():
                             "forward_gbs": round(f0_b / f0_s / 1e9, 1), "back_gbs": round(b0_b / b0_s / 1e9, 1),
                             "rows": M0, "nnz": nnz0}
 
+    serving = compare = None
+    if args.serve_requests > 0:
+        specs, sdata = _serving_data(args.serve_requests)
+        serving = serve_latency(specs, sdata, args.alpha)
+        log(f"serving: p50 {serving['p50_ms']} ms, p99 {serving['p99_ms']} ms, {serving['achieved_rps']} requests/s")
+        compare = serve_compare(specs, sdata, args.alpha)
+
     cpu = None
     if not args.no_cpu_baseline:
         cpu = cpu_baseline(P, args.beta, args.alpha, args.eta, args.cpu_seconds)
@@ -366,18 +384,22 @@ def main():
     out = {
         "metric": METRIC, "value": round(value, 2), "unit": "epochs/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(1e3 * el / args.steps, 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": f"SVREM 256x256 (2 mm), 252 views x 344 bins, 21 interleaved subsets, "
                                f"counts {args.counts:.0e}, 10% background, quadratic 8-neighbour beta={args.beta}, "
                                f"alpha={args.alpha}, eta={args.eta}; {args.wtype} weights and FP32 iterate, "
                                f"FP64 products, sums and statistics",
+                   "arithmetic": {"weights": args.wtype, "iterate": "f32", "tables": "f32",
+                                  "products_and_sums": "f64", "statistics_and_objective": "f64"},
                    "epochs_per_step": epochs_per_step, "nnz": int(inf.nnz), "build_s": round(build_s, 4),
-                   "tuning": {"fwd_pairs_per_wave": tuning[0], "bp_rows_per_group": tuning[1]},
+                   "tuning": {"fwd_pairs_per_wave": tuning[0], "bp_rows_per_group": tuning[1],
+                              "fwd_row_order": "natural" if args.fwd_natural_order else "xcd_bin_bands"},
                    "objective_after": phi, "parallelism": "single GPU",
                    "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                                for k, v in kernels.items()},
-                   "projector": projector, "kernel_source_hash": kernel_source_hash()},
+                   "projector": projector, "kernel_source_hash": kernel_source_hash(),
+                   "serving": serving, "serve_compare": compare},
         "roofline": roofline,
         "cpu_baseline": cpu,
     }
@@ -390,8 +412,8 @@ def bench_algos(args):
     on one matrix: subset iterations per second and epochs per second in the
     paper's accounting (Sec. 5.1: a pass over the data, i.e. Ns subset updates
     or one anchor / table fill, counts one epoch).  SVREM alpha = 0.7, eta = 1;
-    SVRG alpha = 2, eta = 2 and SAGA alpha = 2 with the frozen subset
-    preconditioner (Sec. 5.1); SGA, BSREM (a_k = 1/(0.001 k + 1)) and SEM with
+    SVRG alpha = 2, eta = 2 and SAGA alpha = 2 with the frozen preconditioner
+    f0 / A^T 1 (Sec. 5.1, Theorem 1); SGA, BSREM (a_k = 1/(0.001 k + 1)) and SEM with
     the decaying step; OSEM unpenalised.  Each figure is the median of five
     timed blocks of --steps epoch calls.  Also the wall time of one objective
     evaluation (svr_objective, which synchronises) on the SVREM recon."""
@@ -504,6 +526,60 @@ def bench_small(args):
                       "calls": calls, **{k: round(v, 2) for k, v in out.items()}}), flush=True)
 
 
+def bench_projectors(args):
+    """The whole-matrix projector calls (svr_project / svr_backproject over every
+    subset) and the subset-0 calls on the largest single-image serving size,
+    384 x 384 (2 mm), 400 views x 518 bins, 21 subsets: 75 M non-zeros with
+    32-bit indices, 602 MB per layout, so neither layout fits the 256 MB
+    Infinity Cache and the streams come from HBM.  Algorithmic bytes: index and
+    weight of every non-zero, row pointers, the input read once and the output
+    written once (plus the input permutation or tiling the call performs)."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import paper_2106_03172_amd as pkg
+    geom = datagen.Geometry(384, 384, 2.0, 400, 518, 2.0)
+    Ns, N, M = 21, geom.n_pixels, geom.n_rays
+    wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
+    wb = 4 if args.wtype == "f32" else 2
+    A = pkg.SystemMatrix(geom, Ns, wt)
+    inf, per_subset = A.info()
+    ib = inf.index_bytes
+    x = torch.rand(1, N, device="cuda")
+    y = torch.rand(1, M, device="cuda")
+    yo = torch.empty(1, M, device="cuda")
+    xo = torch.empty(1, N, device="cuda")
+    reps = max(1, args.steps)
+    out = {"workload": "projectors", "config": "384x384 (2 mm), 400 views x 518 bins, 21 subsets",
+           "nnz": int(inf.nnz), "index_bytes": ib, "wtype": args.wtype,
+           "layout_mb": round(inf.nnz * (ib + wb) / 1e6, 1)}
+    for label, subset in (("all", -1), ("subset0", 0)):
+        for _ in range(3):
+            A.project(x, subset, yo)
+            A.backproject(y, subset, xo)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        for _ in range(reps):
+            A.project(x, subset, yo)
+        ev[1].record()
+        for _ in range(reps):
+            A.backproject(y, subset, xo)
+        ev[2].record()
+        torch.cuda.synchronize()
+        f_s = ev[0].elapsed_time(ev[1]) / reps / 1e3
+        b_s = ev[1].elapsed_time(ev[2]) / reps / 1e3
+        nnz = inf.nnz if subset < 0 else int(np.asarray(per_subset)[0])
+        rows = M if subset < 0 else ((geom.n_views + Ns - 1) // Ns) * geom.n_bins
+        f_b = nnz * (ib + wb) + 4 * (rows + 1) + 4 * N + 4 * rows
+        b_b = nnz * (ib + wb) + 4 * ((Ns if subset < 0 else 1) * N + 1) + 4 * N + 8 * M + 4 * rows
+        out[label] = {"forward_us": round(f_s * 1e6, 2), "back_us": round(b_s * 1e6, 2),
+                      "forward_gbs": round(f_b / f_s / 1e9, 1), "back_gbs": round(b_b / b_s / 1e9, 1),
+                      "forward_bytes": int(f_b), "back_bytes": int(b_b)}
+        log(f"{label}: {out[label]}")
+    print(json.dumps(out), flush=True)
+
+
 def bench_copy(args):
     """A plain device copy of a known size (256 MiB read + 256 MiB written per
     launch): the calibration run for the HBM byte counters of rocprofv3."""
@@ -583,26 +659,27 @@ def bench_multislice(args):
                       "nnz": int(inf.nnz), "kernels": kernels, "objective_after": R.objective()}), flush=True)
 
 
-def bench_serve(args):
-    """Continuous batching of independent SVREM requests with Poisson arrivals
-    (sizes from {128, 192, 256, 384}^2, views in [120, 400], bins 1.35 N,
-    subsets in {8, 14, 21}, counts log-uniform in [1e5, 1e7], 30 epochs).
-    First all requests arrive at once to measure capacity (the second of two such runs); then they arrive
-    as a Poisson stream at 0.8 of that capacity; p50/p99 latency is taken
-    from arrival to completion."""
-    import numpy as np
-
+def _serving_data(n):
+    """The first ``n`` requests of the seeded serving stream (sizes from
+    {128, 192, 256, 384}^2, views in [120, 400], bins 1.35 N, subsets in
+    {8, 14, 21}, counts log-uniform in [1e5, 1e7], SVREM 30 epochs)."""
     import datagen
-    import paper_2106_03172_amd as pkg
-    n = args.requests
     specs = datagen.serving_requests(n, 1.0, seed=0)
     log(f"generating {n} requests")
-    data = []
-    for r in specs:
-        P = datagen.make_problem(r["nx"], r["ny"], r["pixel_mm"], r["n_views"], r["n_bins"], r["bin_mm"],
-                                 r["n_subsets"], r["counts"], seed=r["seed"])
-        data.append(P)
-    prm = pkg.params("svrem", alpha=args.alpha, eta=1, beta=1e-3)
+    data = [datagen.make_problem(r["nx"], r["ny"], r["pixel_mm"], r["n_views"], r["n_bins"], r["bin_mm"],
+                                 r["n_subsets"], r["counts"], seed=r["seed"]) for r in specs]
+    return specs, data
+
+
+def serve_latency(specs, data, alpha):
+    """Continuous batching with Poisson arrivals: capacity from all requests at
+    once (the second of two such runs), then a Poisson stream at 0.8 of it;
+    latency from arrival to completion."""
+    import numpy as np
+
+    import paper_2106_03172_amd as pkg
+    n = len(data)
+    prm = pkg.params("svrem", alpha=alpha, eta=1, beta=1e-3)
 
     def run(arrivals):
         S = pkg.Server(64 << 30, max_slots=16, n_streams=8)
@@ -640,33 +717,28 @@ def bench_serve(args):
     done, total = run(arrivals)
     lat = np.array([done[i][0] for i in range(n)]) * 1e3
     ok = all(done[i][1]["status"] == 0 for i in range(n))
-    print(json.dumps({"workload": "serve", "metric": "p50/p99 recon latency and requests/s (Poisson arrivals)",
-                      "requests": n, "capacity_rps": round(capacity, 3), "offered_rps": round(rate, 3),
-                      "achieved_rps": round(n / total, 3), "p50_ms": round(float(np.percentile(lat, 50)), 2),
-                      "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2),
-                      "all_ok": ok, "epochs_per_request": specs[0]["epochs"]}), flush=True)
+    return {"requests": n, "capacity_rps": round(capacity, 3), "offered_rps": round(rate, 3),
+            "achieved_rps": round(n / total, 3), "p50_ms": round(float(np.percentile(lat, 50)), 2),
+            "p99_ms": round(float(np.percentile(lat, 99)), 2), "mean_ms": round(float(lat.mean()), 2),
+            "all_ok": ok, "epochs_per_request": specs[0]["epochs"]}
 
 
-def bench_serve_compare(args):
-    """The same set of serving requests (sizes and counts as bench_serve, SVREM, 30 epochs each, the
-    subset sequence of each request from its seed) three ways: the plain per-request path (FP32
-    weights; build the matrix, one OSEM epoch, the SVREM epochs, one request after the other,
-    through SystemMatrix / Recon), and the continuous-batching server with every request submitted
-    at once: with each request's epochs on one of 8 streams (FP32), and with the subset iterations
-    batched into one launch per phase (FP32, BF16 and FP16 weights).  Reports SVREM epochs/s of each and, over the
-    requests, the relative L2 difference of the batched half-precision results from the per-request
-    FP32 ones (the GPU tests pin each weight type against the FP64 oracle)."""
+def serve_compare(specs, data, alpha):
+    """The same requests (SVREM, 30 epochs each, the subset sequence of each
+    request from its seed) four ways: the plain per-request path (FP32
+    weights; build the matrix, one OSEM epoch, the SVREM epochs, one request
+    after the other, through SystemMatrix / Recon), and the continuous-batching
+    server with every request submitted at once: each request's epochs on one
+    of 8 streams (FP32), and the subset iterations batched into one launch per
+    phase (FP32, BF16 and FP16 weights).  SVREM epochs/s of each and, over the
+    requests, the relative L2 difference of each result from the per-request
+    FP32 one (the GPU tests pin every weight type against the FP64 oracle)."""
     import numpy as np
     import torch
 
-    import datagen
     import paper_2106_03172_amd as pkg
-    n = min(args.requests, 64)
-    specs = datagen.serving_requests(n, 1.0, seed=0)
-    log(f"generating {n} requests")
-    data = [datagen.make_problem(r["nx"], r["ny"], r["pixel_mm"], r["n_views"], r["n_bins"], r["bin_mm"],
-                                 r["n_subsets"], r["counts"], seed=r["seed"]) for r in specs]
-    prm = pkg.params("svrem", alpha=args.alpha, eta=1, beta=1e-3)
+    n = len(data)
+    prm = pkg.params("svrem", alpha=alpha, eta=1, beta=1e-3)
     epochs = [int(r["epochs"]) for r in specs]
     total_epochs = sum(epochs)
 
@@ -707,32 +779,41 @@ def bench_serve_compare(args):
     f_req, t_req = per_request()
     log(f"per-request FP32: {t_req:.3f} s")
     f32_str, t_str = served(pkg.SVR_W_F32, batch=False)
-    log(f"per-request epochs on 8 streams, FP32: {t_str:.3f} s")
     f32_srv, t_f32 = served(pkg.SVR_W_F32)
-    log(f"batched FP32: {t_f32:.3f} s")
     f_bf, t_bf = served(pkg.SVR_W_BF16)
-    log(f"batched BF16: {t_bf:.3f} s")
     f_h, t_h = served(pkg.SVR_W_F16)
-    log(f"batched FP16: {t_h:.3f} s")
+    log(f"8 streams FP32 {t_str:.3f} s, batched FP32 {t_f32:.3f} s, BF16 {t_bf:.3f} s, FP16 {t_h:.3f} s")
 
     def rel(a, b):
         return float(np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300))
-    d_bf = [rel(f_bf[i], f_req[i]) for i in range(n)]
-    d_h = [rel(f_h[i], f_req[i]) for i in range(n)]
-    d_32 = [max(rel(f32_srv[i], f_req[i]), rel(f32_str[i], f_req[i])) for i in range(n)]
+
+    def entry(t, f=None):
+        e = {"seconds": round(t, 4), "epochs_per_s": round(total_epochs / t, 1)}
+        if f is not None:
+            d = [rel(f[i], f_req[i]) for i in range(n)]
+            e.update(max_rel_diff_vs_f32=float(max(d)), median_rel_diff_vs_f32=float(np.median(d)))
+        return e
+    return {"requests": n, "epochs": total_epochs, "per_request_f32": entry(t_req),
+            "streams_f32": entry(t_str, f32_str), "batched_f32": entry(t_f32, f32_srv),
+            "batched_bf16": entry(t_bf, f_bf), "batched_f16": entry(t_h, f_h),
+            "speedup_bf16_batched_vs_f32_per_request": round(t_req / t_bf, 3),
+            "speedup_f16_batched_vs_f32_per_request": round(t_req / t_h, 3)}
+
+
+def bench_serve(args):
+    """p50/p99 latency of --requests serving requests with Poisson arrivals."""
+    specs, data = _serving_data(args.requests)
+    out = serve_latency(specs, data, args.alpha)
+    print(json.dumps({"workload": "serve", "metric": "p50/p99 recon latency and requests/s (Poisson arrivals)",
+                      **out}), flush=True)
+
+
+def bench_serve_compare(args):
+    """Batched FP32 / BF16 / FP16 serving against the plain FP32 per-request path."""
+    specs, data = _serving_data(min(args.requests, 64))
+    out = serve_compare(specs, data, args.alpha)
     print(json.dumps({"workload": "serve-compare", "metric": "SVREM epochs/s over a set of serving requests",
-                      "requests": n, "epochs": total_epochs,
-                      "per_request_f32": {"seconds": round(t_req, 4), "epochs_per_s": round(total_epochs / t_req, 1)},
-                      "streams_f32": {"seconds": round(t_str, 4), "epochs_per_s": round(total_epochs / t_str, 1)},
-                      "batched_f32": {"seconds": round(t_f32, 4), "epochs_per_s": round(total_epochs / t_f32, 1)},
-                      "batched_bf16": {"seconds": round(t_bf, 4), "epochs_per_s": round(total_epochs / t_bf, 1)},
-                      "batched_f16": {"seconds": round(t_h, 4), "epochs_per_s": round(total_epochs / t_h, 1)},
-                      "speedup_bf16_batched_vs_f32_per_request": round(t_req / t_bf, 3),
-                      "speedup_f16_batched_vs_f32_per_request": round(t_req / t_h, 3),
-                      "max_rel_diff_bf16_vs_f32": float(max(d_bf)),
-                      "median_rel_diff_bf16_vs_f32": float(np.median(d_bf)),
-                      "max_rel_diff_f16_vs_f32": float(max(d_h)),
-                      "max_rel_diff_batched_f32_vs_per_request": float(max(d_32))}), flush=True)
+                      **out}), flush=True)
 
 
 if __name__ == "__main__":

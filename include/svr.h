@@ -146,6 +146,10 @@ typedef struct {
                                     wavefront, others one row (0: twice the wavefronts the device
                                     holds at once, 2 * 32 * compute units); >= 0 */
     double  fwd_us, bp_us;       /* svr_matrix_tune: measured duration of the chosen runs */
+    int32_t fwd_natural_order;   /* forward passes with one row per wavefront (the per-subset passes):
+                                    0 (default) gives each of the device's 8 XCDs a band of bins of every
+                                    view, so its L2 holds the part of the image those rays cross; 1 takes
+                                    the rows in order.  Results are bitwise the same either way. */
 } svr_tuning_t;
 
 /* Run lengths in use for the whole-matrix passes (0 resolved to the

@@ -67,7 +67,8 @@ class svr_kernel_times_t(C.Structure):
 
 class svr_tuning_t(C.Structure):
     _fields_ = [("fwd_pairs_per_wave", C.c_int32), ("bp_rows_per_group", C.c_int32),
-                ("fwd_pair_rows", C.c_int32), ("fwd_us", C.c_double), ("bp_us", C.c_double)]
+                ("fwd_pair_rows", C.c_int32), ("fwd_us", C.c_double), ("bp_us", C.c_double),
+                ("fwd_natural_order", C.c_int32)]
 
 
 class svr_serve_config(C.Structure):
@@ -299,11 +300,16 @@ class SystemMatrix:
         _check(lib().svr_matrix_get_tuning(self.h, C.byref(t)))
         return int(t.fwd_pairs_per_wave), int(t.bp_rows_per_group)
 
-    def set_tuning(self, fwd_pairs_per_wave: int = 0, bp_rows_per_group: int = 0, fwd_pair_rows=None):
+    def set_tuning(self, fwd_pairs_per_wave: int = 0, bp_rows_per_group: int = 0, fwd_pair_rows=None,
+                   fwd_natural_order=None):
         """Sets the run lengths (0: size-based); fwd_pair_rows (None: unchanged) is the row count above
-        which a forward pass runs a pair of rows per wavefront (0: from the device)."""
-        pr = self.pair_rows() if fwd_pair_rows is None else int(fwd_pair_rows)
-        t = svr_tuning_t(int(fwd_pairs_per_wave), int(bp_rows_per_group), pr, 0.0, 0.0)
+        which a forward pass runs a pair of rows per wavefront (0: from the device); fwd_natural_order
+        (None: unchanged) 1 takes the rows of one-row-per-wavefront passes in order, 0 in XCD bin bands."""
+        cur = svr_tuning_t()
+        _check(lib().svr_matrix_get_tuning(self.h, C.byref(cur)))
+        pr = cur.fwd_pair_rows if fwd_pair_rows is None else int(fwd_pair_rows)
+        no = cur.fwd_natural_order if fwd_natural_order is None else int(fwd_natural_order)
+        t = svr_tuning_t(int(fwd_pairs_per_wave), int(bp_rows_per_group), pr, 0.0, 0.0, no)
         _check(lib().svr_matrix_set_tuning(self.h, C.byref(t)))
 
     def pair_rows(self) -> int:

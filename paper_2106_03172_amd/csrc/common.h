@@ -81,6 +81,8 @@ constexpr int64_t NNZ_PAD = 1024;
 // tile in several consecutive entries, so a wavefront's gathers touch far
 // fewer cache lines than in row-major order (about 2.6x fewer at 256^2).
 constexpr int TILE_W = 4, TILE_H = 8;
+// XCDs of the device: workgroups are dispatched to them round-robin by index
+constexpr int XCDS = 8;
 __host__ __device__ inline int tiles_x(int nx) { return (nx + TILE_W - 1) / TILE_W; }
 __host__ __device__ inline int tiled_count(int nx, int ny) {
     return tiles_x(nx) * TILE_W * ((ny + TILE_H - 1) / TILE_H) * TILE_H;
@@ -126,6 +128,7 @@ struct Matrix {
     int pair_rows_eff() const { return pair_rows > 0 ? pair_rows : 2 * 32 * (cus > 1 ? cus : 1); }
     int run_fwd = 0;                // row pairs per wavefront in whole-matrix forward passes (0: by size)
     int run_bp = 0;                 // transposed rows per lane group in whole-matrix back-projections (0: by size)
+    int xcd_bands = 1;              // one-row-per-wavefront forward passes: each XCD a band of bins (band_row)
     // scratch of the projector calls (svr_project / svr_backproject), max(Nt, M) floats kept
     // between calls: a call takes it when it is idle and its last use was on the call's stream
     // or has completed (proj_done), else allocates its own

@@ -39,17 +39,38 @@ __device__ inline double loglik_term(float g, float w, double yb, double eps, in
     return -yb;
 }
 
+// Row of wavefront wv of block b in a one-row-per-wavefront pass over the
+// rows r0 + j*B + bin (views j < Vt, bins bin < B) when B > 0: workgroups are
+// dispatched to the XCDs round-robin (b mod XCDS), and XCD x takes the bin
+// band [x B / XCDS, (x + 1) B / XCDS) of every view, bin-minor.  A band's
+// rays cross a ring of the image rather than all of it, so each XCD's L2
+// fetches a part of the image instead of the whole.  B = 0: row r0 + b W + wv.
+// Returns -1 for a wavefront with no row.
+__device__ inline int band_row(int b, int wv, int r0, int r1, int B, int Vt) {
+    if (B == 0) {
+        const int r = r0 + b * FWD_WAVES_PER_BLOCK + wv;
+        return r < r1 ? r : -1;
+    }
+    const int x = b % XCDS, L = b / XCDS;
+    const int lo = x * B / XCDS, w = (x + 1) * B / XCDS - lo;
+    const int p = L * FWD_WAVES_PER_BLOCK + wv;
+    const int j = p / w;
+    return j < Vt ? r0 + j * B + lo + (p - j * w) : -1;
+}
+
 // one wavefront per row r (PAIR: per pair of rows r, r + 1); mode 0 writes
 // y[row_sino[r]], mode 1 the ratio, mode 2 the row's log-likelihood term to
-// part[r - r0] (summed afterwards in a fixed order)
+// part[r - r0] (summed afterwards in a fixed order).  Without PAIR the row
+// comes from band_row (B, Vt); a row's arithmetic does not depend on which
+// wavefront takes it.
 template <int MODE, bool PAIR, typename WT, typename IT>
 __global__ void __launch_bounds__(FWD_THREADS)
 k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
-          const int *__restrict__ row_sino, int r0, int r1, FwdArgs a) {
+          const int *__restrict__ row_sino, int r0, int r1, int B, int Vt, FwdArgs a) {
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
-    const int r = r0 + (PAIR ? 2 : 1) * (blockIdx.x * FWD_WAVES_PER_BLOCK + wv);
-    if (r >= r1) return;  // wave-uniform
+    const int r = PAIR ? r0 + 2 * (blockIdx.x * FWD_WAVES_PER_BLOCK + wv) : band_row(blockIdx.x, wv, r0, r1, B, Vt);
+    if (r < 0 || r >= r1) return;  // wave-uniform
     if constexpr (!PAIR) {
         if (MODE == 1) {
             fwd_ratio_row(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane, a.eps);
@@ -130,15 +151,24 @@ int forward_run_length(const Matrix &A, int rows) {
 template <int MODE>
 static int launch_forward_t(const Matrix &A, int r0, int r1, bool pair, int R, const FwdArgs &a, hipStream_t s,
                             int nb) {
+    // one row per wavefront: XCD bin bands when the range is whole views of at
+    // least XCDS bins (every subset range and the whole matrix)
+    const int B = A.geom.n_bins, rows = r1 - r0;
+    const bool bands = !pair && A.xcd_bands && B >= XCDS && rows % B == 0;
+    const int Bb = bands ? B : 0, Vt = bands ? rows / B : 0;
+    if (bands) {
+        const int64_t per_xcd = ((int64_t)Vt * ((B + XCDS - 1) / XCDS) + FWD_WAVES_PER_BLOCK - 1) / FWD_WAVES_PER_BLOCK;
+        nb = (int)(per_xcd * XCDS);
+    }
     return with_types(A, [&](auto w, auto i) {
         using WT = decltype(w);
         using IT = decltype(i);
         if (!pair)
             SVR_HIP(launch_k(k_forward<MODE, false, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
-                             (const WT *)A.d_val, A.d_row_sino, r0, r1, a));
+                             (const WT *)A.d_val, A.d_row_sino, r0, r1, Bb, Vt, a));
         else if (R == 1)
             SVR_HIP(launch_k(k_forward<MODE, true, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
-                             (const WT *)A.d_val, A.d_row_sino, r0, r1, a));
+                             (const WT *)A.d_val, A.d_row_sino, r0, r1, 0, 0, a));
         else
             SVR_HIP(launch_k(k_forward_run<MODE, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
                              (const WT *)A.d_val, A.d_row_sino, r0, r1, R, a));

@@ -123,6 +123,7 @@ int tune(Matrix &A, hipStream_t s, svr_tuning_t *out) {
             out->fwd_pair_rows = A.pair_rows_eff();
             out->fwd_us = us_f;
             out->bp_us = us_b;
+            out->fwd_natural_order = A.xcd_bands ? 0 : 1;
         }
     }
     SVR_HIP(hipStreamSynchronize(s));
@@ -143,6 +144,7 @@ int svr_matrix_get_tuning(const svr_matrix *A, svr_tuning_t *t) {
     t->fwd_pair_rows = A->pair_rows_eff();
     t->fwd_us = 0.0;
     t->bp_us = 0.0;
+    t->fwd_natural_order = A->xcd_bands ? 0 : 1;
     return SVR_OK;
 }
 
@@ -152,6 +154,8 @@ int svr_matrix_set_tuning(svr_matrix *A, const svr_tuning_t *t) {
     SVR_REQUIRE(t->fwd_pairs_per_wave >= 0 && t->fwd_pairs_per_wave <= 31, "fwd_pairs_per_wave must be in [0, 31]");
     SVR_REQUIRE(t->bp_rows_per_group >= 0 && t->bp_rows_per_group <= 1024, "bp_rows_per_group must be in [0, 1024]");
     SVR_REQUIRE(t->fwd_pair_rows >= 0, "fwd_pair_rows must be >= 0");
+    SVR_REQUIRE(t->fwd_natural_order == 0 || t->fwd_natural_order == 1, "fwd_natural_order must be 0 or 1");
+    A->xcd_bands = t->fwd_natural_order ? 0 : 1;
     A->run_fwd = t->fwd_pairs_per_wave;
     A->pair_rows = t->fwd_pair_rows;
     A->run_bp = t->bp_rows_per_group;
