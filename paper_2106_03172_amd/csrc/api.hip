@@ -46,6 +46,7 @@ struct svr_recon {
     std::vector<hipEvent_t> ev;
     std::vector<int> ev_kind;
     size_t ev_used = 0;
+    StackPlan plan;                     // slice stacks: image regions, row segments, schedules
 };
 
 namespace {
@@ -72,6 +73,7 @@ void free_recon(Recon *R) {
     void *ptrs[] = {R->g, R->w, R->f[0], R->f[1], R->ft, R->ratio, R->s_hat, R->s_anc, R->Q, R->g_tilde, R->grad_anc,
                     R->table, R->dpre, R->part, R->scal, R->bad, R->d_order, R->d_sync, R->d_status};
     for (void *q : ptrs) dfree(q);
+    ms_plan_free(R->plan);
     delete R;
 }
 
@@ -310,10 +312,10 @@ int run_epoch_slices(Recon *R, int algo, int kind, const int32_t *order, int32_t
         float *f = R->f[R->cur];
         if (kind == UPD_SVREM && R->k % ((int64_t)R->p.eta * R->Ns) == 0) {
             rc = prof_begin(R, 2, s);
-            if (!rc) rc = ms_forward(A, 0, A.M, 1, S, f, R->g, R->w, R->ratio, nullptr, nullptr, s, nullptr);
+            if (!rc) rc = ms_forward(A, R->plan, -1, 1, S, f, R->g, R->w, R->ratio, nullptr, nullptr, s, nullptr);
             if (!rc) rc = prof_end(R, s);
             if (!rc) rc = prof_begin(R, 3, s);
-            if (!rc) rc = ms_anchor_table(A, S, R->ratio, f, R->table, s);
+            if (!rc) rc = ms_anchor_table(A, R->plan, S, R->ratio, f, R->table, s);
             if (!rc) rc = prof_end(R, s);
             if (!rc) rc = prof_begin(R, 4, s);
             if (!rc)
@@ -323,9 +325,9 @@ int run_epoch_slices(Recon *R, int algo, int kind, const int32_t *order, int32_t
             if (rc) return rc;
             R->n_snap++;
         }
-        const int r0 = A.row_start[t], r1 = A.row_start[t + 1];
+        const int r0 = A.row_start[t];
         rc = prof_begin(R, 0, s);
-        if (!rc) rc = ms_forward(A, r0, r1, 1, S, f, R->g, R->w, R->ratio, nullptr, nullptr, s, nullptr);
+        if (!rc) rc = ms_forward(A, R->plan, t, 1, S, f, R->g, R->w, R->ratio, nullptr, nullptr, s, nullptr);
         if (!rc) rc = prof_end(R, s);
         if (rc) return rc;
         UpdateArgs u{};
@@ -341,7 +343,7 @@ int run_epoch_slices(Recon *R, int algo, int kind, const int32_t *order, int32_t
         u.pen = pen_of(R);
         if (kind == UPD_OSEM) u.pen.beta = 0.0;
         rc = prof_begin(R, 1, s);
-        if (!rc) rc = ms_update(A, kind, S, axial, u, s);
+        if (!rc) rc = ms_update(A, R->plan, kind, S, axial, u, s);
         if (!rc) rc = prof_end(R, s);
         if (rc) return rc;
         R->cur = 1 - R->cur;
@@ -888,6 +890,7 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
         rc = ms_pack_sino(*A, (int)S, g_dev, R->g, s);
         if (!rc) rc = ms_pack_sino(*A, (int)S, w_dev, R->w, s);
         if (!rc) rc = ms_pack_img(N, (int)S, f0_dev, R->f[0], s);
+        if (!rc) rc = ms_plan_build(*A, (int)S, R->plan, s);
     }
     if (rc) { free_recon(R); return rc; }
     SVR_HIP(hipMemsetAsync(R->ratio, 0, sizeof(float) * MS_, s));
@@ -922,7 +925,7 @@ int svr_objective(svr_recon *R, double *phi_host, void *stream) {
         fa.eps = ll_eps_of(R);
         rc = launch_forward(A, 0, A.M, 2, fa, s, &nb);
     } else {
-        rc = ms_forward(A, 0, A.M, 2, R->S, R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad, s, &nb);
+        rc = ms_forward(A, R->plan, -1, 2, R->S, R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad, s, &nb);
     }
     if (!rc) rc = launch_reduce_sum(R->part, nb, R->scal, s);
     if (!rc) {

@@ -304,10 +304,44 @@ int launch_epoch(const Matrix &A, int kind, const EpochArgs &e, hipStream_t s, i
 int persistent_sync_words();
 
 // slice stacks (slices.hip): images [N][S], data and ratios [row][S]
-int ms_forward(const Matrix &A, int r0, int r1, int mode, int S, const float *X, const float *g, const float *w,
-               float *ratio, double *part, int *bad, hipStream_t s, int *nb_out);
-int ms_update(const Matrix &A, int kind, int S, int axial, const UpdateArgs &u, hipStream_t s);
-int ms_anchor_table(const Matrix &A, int S, const float *ratio_all, const float *X, float *table, hipStream_t s);
+//
+// The image is cut into a grid of rectangular regions (ry x rx, each ly x lx
+// pixels, the last ones smaller) small enough that one region of the stack,
+// ly * lx * S floats, fits in an XCD's L2 with room to spare.  Region q belongs
+// to XCD q mod XCDS (workgroups are dispatched to the XCDs round-robin by
+// index).  A ray crosses a convex region in one run of consecutive entries of
+// its row, so each row splits into segments, one per region it crosses, in ray
+// order.
+struct Regions {
+    int ry = 1, rx = 1, ly = 1, lx = 1;
+};
+struct XcdSched {  // per XCD: first entry in a schedule and number of entries
+    int off[XCDS];
+    int cnt[XCDS];
+};
+struct StackPlan {
+    Regions reg;
+    int S = 0, nch = 0;
+    int64_t nseg = 0;
+    int *seg_ptr = nullptr;      // M+1: segments of subset-ordered row r are [seg_ptr[r], seg_ptr[r+1])
+    int *seg_beg = nullptr;      // nseg+1: first entry of each segment (seg_beg[nseg] = nnz)
+    int *sched_sub = nullptr;    // nseg: each subset's segments grouped by XCD, region-major
+    int *sched_all = nullptr;    // nseg: every segment grouped by XCD, region-major
+    std::vector<XcdSched> sub;   // per subset, offsets into sched_sub
+    XcdSched all{};              // offsets into sched_all
+    int area[XCDS] = {};         // pixels of each XCD's regions
+    double *P = nullptr;         // nseg x (64 nch) FP64 segment sums
+};
+Regions choose_regions(int nx, int ny, int S);
+int ms_plan_build(const Matrix &A, int S, StackPlan &plan, hipStream_t s);
+void ms_plan_free(StackPlan &plan);
+// mode 1: ratio of every row of subset t (t = -1: all rows); mode 2: the
+// log-likelihood partials of all rows (t = -1), *nb_out of them in part
+int ms_forward(const Matrix &A, const StackPlan &plan, int t, int mode, int S, const float *X, const float *g,
+               const float *w, float *ratio, double *part, int *bad, hipStream_t s, int *nb_out);
+int ms_update(const Matrix &A, const StackPlan &plan, int kind, int S, int axial, const UpdateArgs &u, hipStream_t s);
+int ms_anchor_table(const Matrix &A, const StackPlan &plan, int S, const float *ratio_all, const float *X,
+                    float *table, hipStream_t s);
 int ms_anchor_sum(const Matrix &A, int S, const float *table, double *s_anc, double *s_hat, int init_shat,
                   hipStream_t s);
 int ms_penalty_value(const Matrix &A, int S, const float *X, int potential, double delta, int axial, double *part,
