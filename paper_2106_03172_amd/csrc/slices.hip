@@ -63,15 +63,36 @@ __device__ inline void ms_dot(const IT *__restrict__ idx, const WT *__restrict__
     }
     const int row_bytes = S * 4;
     int i = beg;
-    for (; i + MS_U <= end; i += MS_U) {
+    // software-pipelined: the next batch's indices and weights are loaded
+    // while the current batch's gathers are in flight
+    int cn[MS_U];
+    float an[MS_U];
+    bool more = i + MS_U <= end;
+    if (more) {
+#pragma unroll
+        for (int u = 0; u < MS_U; ++u) {
+            cn[u] = (int)idx[i + u];
+            an[u] = load_w(val[i + u]);
+        }
+    }
+    while (more) {
         float x[MS_U][NC], a[MS_U];
 #pragma unroll
         for (int u = 0; u < MS_U; ++u) {
-            const int off = (int)idx[i + u] * row_bytes;
-            a[u] = load_w(val[i + u]);
+            const int off = cn[u] * row_bytes;
+            a[u] = an[u];
 #pragma unroll
             for (int c = 0; c < NC; ++c)
                 x[u][c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ry, vo[c], off, 0));
+        }
+        i += MS_U;
+        more = i + MS_U <= end;
+        if (more) {
+#pragma unroll
+            for (int u = 0; u < MS_U; ++u) {
+                cn[u] = (int)idx[i + u];
+                an[u] = load_w(val[i + u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < MS_U; ++u) {
@@ -333,25 +354,38 @@ k_ms_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT 
 }
 
 // ---- SVREM anchor: tau table and FP64 sums -----------------------------------
-// task p of XCD x: subset t = p / (area_x ng), then the pixels of the XCD's
-// regions as in k_ms_update (subset-major, so the XCD's L2 holds the part of
-// one subset's ratio block its regions' rays touch)
+// Task p of XCD x, region-major: the XCD's regions q = x, x + XCDS, ... in
+// turn, and within a region every subset t, then the region's pixels
+// (row-major), then the slice group.  A region's slab of the stack stays in
+// the L2 while all subsets visit it (tau_t reads f for every t), and each
+// subset's ratios of the rays crossing the region are streamed once.
 template <int NC, typename WT, typename IT>
 __global__ void __launch_bounds__(MS_THREADS)
 k_ms_anchor_table(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
                   const int *__restrict__ row_start, int Ns, int N, int S, int ng, int nx, int ny, Regions rg,
-                  XcdSched area, const float *__restrict__ ratio, const float *__restrict__ X,
-                  float *__restrict__ table) {
+                  const float *__restrict__ ratio, const float *__restrict__ X, float *__restrict__ table) {
     const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const int x = blockIdx.x % XCDS;
-    const int task = (int)(blockIdx.x / XCDS) * MS_WAVES + wv;
-    const int per_t = area.cnt[x] * ng;
-    if (per_t == 0 || task >= per_t * Ns) return;  // wave-uniform
-    const int t = task / per_t;
-    const int rem = task - t * per_t;
-    const int item = rem / ng, grp = rem - item * ng;
-    const int n = region_pixel(rg, x, item, nx, ny);
-    if (n < 0) return;
+    int p = (int)(blockIdx.x / XCDS) * MS_WAVES + wv;
+    int n = -1, t = 0, grp = 0;
+    for (int q = x; q < rg.ry * rg.rx; q += XCDS) {  // wave-uniform walk over the XCD's regions
+        const int qy = q / rg.rx;
+        const int y0 = qy * rg.ly, x0 = (q - qy * rg.rx) * rg.lx;
+        const int h = min(rg.ly, ny - y0), w = min(rg.lx, nx - x0);
+        if (h <= 0 || w <= 0) continue;
+        const int per_t = h * w * ng;
+        if (p < per_t * Ns) {
+            t = p / per_t;
+            const int rem = p - t * per_t;
+            const int item = rem / ng;
+            grp = rem - item * ng;
+            const int py = item / w;
+            n = (y0 + py) * nx + x0 + (item - py * w);
+            break;
+        }
+        p -= per_t * Ns;
+    }
+    if (n < 0) return;  // wave-uniform
     const int64_t q = (int64_t)t * N + n;
     const int s0 = grp * NC * 64 + lane;
     float f[NC];
@@ -602,12 +636,8 @@ int ms_anchor_table(const Matrix &A, const StackPlan &plan, int S, const float *
                     float *table, hipStream_t s) {
     const int nch = nchunks(S);
     const int nc = nch > 1 ? 2 : 1, ng = (nch + nc - 1) / nc;
-    XcdSched area{};
     int most = 0;
-    for (int x = 0; x < XCDS; ++x) {
-        area.cnt[x] = plan.area[x];
-        most = std::max(most, plan.area[x]);
-    }
+    for (int x = 0; x < XCDS; ++x) most = std::max(most, plan.area[x]);
     const unsigned nb = xcd_blocks((int64_t)A.Ns * most * ng);
     return with_types(A, [&](auto wv, auto iv) {
         using WT = decltype(wv);
@@ -615,11 +645,11 @@ int ms_anchor_table(const Matrix &A, const StackPlan &plan, int S, const float *
         if (nc == 2)
             SVR_HIP(launch_k(k_ms_anchor_table<2, WT, IT>, nb, MS_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
                              (const WT *)A.d_valT, A.d_row_start, A.Ns, A.N, S, ng, A.geom.nx, A.geom.ny, plan.reg,
-                             area, ratio_all, X, table));
+                             ratio_all, X, table));
         else
             SVR_HIP(launch_k(k_ms_anchor_table<1, WT, IT>, nb, MS_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
                              (const WT *)A.d_valT, A.d_row_start, A.Ns, A.N, S, ng, A.geom.nx, A.geom.ny, plan.reg,
-                             area, ratio_all, X, table));
+                             ratio_all, X, table));
         return SVR_OK;
     });
 }
