@@ -190,7 +190,7 @@ __global__ void __launch_bounds__(MS_THREADS)
 k_ms_seg_dot(const IT *__restrict__ col, const WT *__restrict__ val, const int *__restrict__ seg_beg,
              const int *__restrict__ sched, XcdSched xs, int S, int nch, int ng, const float *__restrict__ X,
              double *__restrict__ P) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int x = blockIdx.x % XCDS;
     const int p = (int)(blockIdx.x / XCDS) * MS_WAVES + wv;
     if (p >= xs.cnt[x] * ng) return;  // wave-uniform
@@ -215,7 +215,7 @@ __global__ void __launch_bounds__(MS_THREADS)
 k_ms_seg_rows(const int *__restrict__ seg_ptr, int r0, int r1, int S, int nch, const double *__restrict__ P,
               const float *__restrict__ g, const float *__restrict__ w, float *__restrict__ ratio,
               double *__restrict__ part, int *bad) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int task = (int)blockIdx.x * MS_WAVES + wv;
     const int rr = task / nch, c = task - rr * nch;
     const int r = r0 + rr;
@@ -304,7 +304,7 @@ __global__ void __launch_bounds__(MS_THREADS)
 k_ms_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
             const float *__restrict__ sens_t, const double *__restrict__ sens, int N, int S, int ng, int axial,
             Regions rg, UpdateArgs u) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int x = blockIdx.x % XCDS;
     const int task = (int)(blockIdx.x / XCDS) * MS_WAVES + wv;
     const int item = task / ng, grp = task - item * ng;
@@ -364,7 +364,7 @@ __global__ void __launch_bounds__(MS_THREADS)
 k_ms_anchor_table(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
                   const int *__restrict__ row_start, int Ns, int N, int S, int ng, int nx, int ny, Regions rg,
                   const float *__restrict__ ratio, const float *__restrict__ X, float *__restrict__ table) {
-    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const int lane = threadIdx.x & 63, wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int x = blockIdx.x % XCDS;
     int p = (int)(blockIdx.x / XCDS) * MS_WAVES + wv;
     int n = -1, t = 0, grp = 0;
