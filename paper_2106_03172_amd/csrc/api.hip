@@ -95,12 +95,18 @@ int prof_begin(Recon *R, int kind, hipStream_t) {
     t.stop = R->ev[R->ev_used + 1];
     return SVR_OK;
 }
-int prof_end(Recon *R, hipStream_t) {
+int prof_end(Recon *R, hipStream_t s) {
     if (!R->prof) return SVR_OK;
     LaunchEvents &t = pending_timing();
     if (t.start) {  // the armed launch did not happen (nothing to time)
         t.start = t.stop = nullptr;
+        t.span = 1;
         return SVR_OK;
+    }
+    if (t.stop) {  // a span ended early: close it on the stream
+        SVR_HIP(hipEventRecord(t.stop, s));
+        t.stop = nullptr;
+        t.span = 1;
     }
     R->ev_used += 2;
     return SVR_OK;

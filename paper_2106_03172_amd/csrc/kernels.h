@@ -54,15 +54,23 @@ constexpr int BP_RUN_U = SVR_BP_RUN_U;         // 4*5 = 20, as BP_U (46.5 -> 39 
 // ---- launches, optionally timed by events attached to the dispatch itself ----
 struct LaunchEvents {
     hipEvent_t start = nullptr, stop = nullptr;
+    int span = 1;  // launches the armed pair covers: start on the first, stop on the last
 };
 LaunchEvents &pending_timing();  // per host thread (util.hip)
 
 template <typename... KArgs, typename... Args>
 inline hipError_t launch_k(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipStream_t s, Args... args) {
     LaunchEvents &t = pending_timing();
-    if (t.start) {
-        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t.start, t.stop, 0, static_cast<KArgs>(args)...);
-        t.start = t.stop = nullptr;
+    if (t.start || t.stop) {
+        hipEvent_t stop = t.span <= 1 ? t.stop : nullptr;
+        hipExtLaunchKernelGGL(kernel, grid, block, 0, s, t.start, stop, 0, static_cast<KArgs>(args)...);
+        t.start = nullptr;
+        if (t.span <= 1) {
+            t.stop = nullptr;
+            t.span = 1;
+        } else {
+            --t.span;
+        }
     } else {
         kernel<<<grid, block, 0, s>>>(static_cast<KArgs>(args)...);
     }

@@ -580,6 +580,8 @@ int ms_forward(const Matrix &A, const StackPlan &plan, int t, int mode, int S, c
     if (nb_out) *nb_out = (int)nb;
     if (nb == 0) return SVR_OK;
     int rc = SVR_OK;
+    LaunchEvents &tm = pending_timing();
+    if (tm.start && nbd > 0) tm.span = 2;  // a timed forward covers both kernels
     if (nbd > 0) {
         rc = with_types(A, [&](auto wv, auto iv) {
             using WT = decltype(wv);
