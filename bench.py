@@ -194,7 +194,7 @@ def main():
                     help="keep the size-based run lengths instead of autotuning them (a profiled run uses this so "
                          "that its kernels do not depend on timings taken under the profiler)")
     ap.add_argument("--workload", choices=("headline", "multislice", "serve", "serve-compare", "copy",
-                                           "convergence", "algos", "small", "projectors"),
+                                           "convergence", "algos", "small", "projectors", "precision"),
                     default="headline",
                         help="headline: the JSON line below; multislice / serve / serve-compare / convergence / "
                          "algos / small: supplementary measurements")
@@ -240,6 +240,8 @@ def main():
         return bench_small(args)
     if args.workload == "projectors":
         return bench_projectors(args)
+    if args.workload == "precision":
+        return bench_precision(args)
     wt = {"f32": pkg.SVR_W_F32, "f16": pkg.SVR_W_F16, "bf16": pkg.SVR_W_BF16}[args.wtype]
     wb = 4 if args.wtype == "f32" else 2
     cfg = dict(datagen.CONFIG_HEADLINE)
@@ -577,6 +579,85 @@ def bench_projectors(args):
                       "forward_gbs": round(f_b / f_s / 1e9, 1), "back_gbs": round(b_b / b_s / 1e9, 1),
                       "forward_bytes": int(f_b), "back_bytes": int(b_b)}
         log(f"{label}: {out[label]}")
+    print(json.dumps(out), flush=True)
+
+
+def bench_precision(args):
+    """The precision sweep of the headline problem (256 x 256, 252 x 344, 21
+    subsets, counts 1e6, beta 1e-2): for FP32, FP16 and BF16 weights, SVREM
+    epochs/s (alpha 0.7, eta 1), the whole-matrix projector kernels' GB/s
+    (forward and back-projection calls over all subsets, algorithmic bytes of
+    the stored weight type) and, after 50 epochs, the relative L2 error of the
+    iterate and the relative error of the objective against the FP64 oracle
+    run with the exact lengths on the same subset sequence."""
+    import numpy as np
+    import torch
+
+    import datagen
+    import oracle
+    import paper_2106_03172_amd as pkg
+    P = datagen.make_problem(**datagen.CONFIG_HEADLINE)
+    Ns, N, M = P.n_subsets, P.geom.n_pixels, P.geom.n_rays
+    beta, calls = 1e-2, 25
+    orders = [datagen.make_order(Ns, Ns, seed=3000 + 100 * c) for c in range(calls)]
+    log("oracle: 50 epochs of SVREM in FP64")
+    Ao = oracle.system_matrix(P.geom)
+    m = oracle.Model(Ao, P.g, P.w, P.geom, Ns, beta=beta)
+    alg = oracle.SVREM(m, oracle.osem_epoch(m, np.ones((1, N)), range(Ns)), 0.7, 1)
+    for o in orders:
+        alg.run(o)
+    f_or, phi_or = alg.f, m.objective(alg.f)
+    out = {"workload": "precision", "config": "SVREM 256x256 (2 mm), 252 views x 344 bins, 21 subsets, counts 1e6, "
+                                              "beta 1e-2, alpha 0.7, eta 1; 50 epochs against the FP64 oracle",
+           "results": {}}
+    for name, wt, wb in (("f32", pkg.SVR_W_F32, 4), ("f16", pkg.SVR_W_F16, 2), ("bf16", pkg.SVR_W_BF16, 2)):
+        A = pkg.SystemMatrix(P.geom, Ns, wt)
+        A.tune()
+        inf, _ = A.info()
+        R = pkg.Recon(A, P.g, P.w, np.ones((1, N), np.float32), pkg.params("svrem", alpha=0.7, eta=1, beta=beta))
+        R.osem_epoch(list(range(Ns)))
+        for o in orders:
+            R.svrem_epoch(o)
+        fg = R.image().cpu().numpy()
+        err = float(np.linalg.norm(fg - f_or) / np.linalg.norm(f_or))
+        phi_err = abs(R.objective() - phi_or) / abs(phi_or)
+        steps = max(1, args.steps)
+        extra = [datagen.make_order(Ns, Ns, seed=8000 + i) for i in range(steps + 5)]
+        for o in extra[:5]:
+            R.svrem_epoch(o)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for o in extra[5:]:
+            R.svrem_epoch(o)
+        torch.cuda.synchronize()
+        eps = 2 * steps / (time.perf_counter() - t0)
+        x = torch.rand(1, N, device="cuda")
+        y = torch.rand(1, M, device="cuda")
+        yo, xo = torch.empty(1, M, device="cuda"), torch.empty(1, N, device="cuda")
+        for _ in range(3):
+            A.project(x, -1, yo)
+            A.backproject(y, -1, xo)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(3)]
+        ev[0].record()
+        for _ in range(20):
+            A.project(x, -1, yo)
+        ev[1].record()
+        for _ in range(20):
+            A.backproject(y, -1, xo)
+        ev[2].record()
+        torch.cuda.synchronize()
+        ib = inf.index_bytes
+        f_s, b_s = ev[0].elapsed_time(ev[1]) / 20e3, ev[1].elapsed_time(ev[2]) / 20e3
+        f_b = inf.nnz * (ib + wb) + 4 * (M + 1) + 4 * N + 4 * M
+        b_b = inf.nnz * (ib + wb) + 4 * (Ns * N + 1) + 4 * N + 12 * M
+        out["results"][name] = {"iterate_rel_l2": err, "objective_rel": phi_err, "svrem_epochs_per_s": round(eps, 1),
+                                "projector_forward_gbs": round(f_b / f_s / 1e9, 1),
+                                "projector_back_gbs": round(b_b / b_s / 1e9, 1),
+                                "projector_forward_us": round(f_s * 1e6, 2), "projector_back_us": round(b_s * 1e6, 2),
+                                "matrix_mb": round(inf.nnz * (ib + wb) / 1e6, 1)}
+        log(f"{name}: {out['results'][name]}")
+        R.close()
+        A.close()
     print(json.dumps(out), flush=True)
 
 

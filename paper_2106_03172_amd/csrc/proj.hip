@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(FWD_THREADS)
 k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
           const int *__restrict__ row_sino, int r0, int r1, int B, int Vt, FwdArgs a) {
     const int lane = threadIdx.x & 63;
-    const int wv = threadIdx.x >> 6;
+    const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);  // wave-uniform
     const int r = PAIR ? r0 + 2 * (blockIdx.x * FWD_WAVES_PER_BLOCK + wv) : band_row(blockIdx.x, wv, r0, r1, B, Vt);
     if (r < 0 || r >= r1) return;  // wave-uniform
     if constexpr (!PAIR) {

@@ -157,3 +157,34 @@ def test_axial_stack_at_full_in_plane_size(full_stack, wtype):
         assert e <= 1e-5, (c, e)
     phi = R.objective()
     assert abs(phi - m.objective(R.image().cpu().numpy().astype(np.float64))) <= 1e-6 * abs(phi)
+
+
+@pytest.mark.parametrize("wtype", [pkg.SVR_W_F32, pkg.SVR_W_BF16])
+def test_axial_stack_twenty_epochs(full_stack, wtype):
+    """The stack's configuration over its stated horizon: SVREM for 20 epochs
+    (10 calls of an anchor and 21 subset updates) with the 8 + 2 axial penalty,
+    on the first 10 slices of the 285 x 285 / 344 x 435 / 21-subset stack,
+    against the oracle after every call (BF16 weights against the oracle on the
+    same BF16-rounded lengths)."""
+    cfg, P, Ao = full_stack
+    Ns, S = cfg["n_subsets"], 10
+    g, w = P.g[:S], P.w[:S]
+    A = pkg.SystemMatrix(P.geom, Ns, wtype)
+    beta = 1e-3
+    f0 = np.ones((S, P.geom.n_pixels))
+    R = pkg.Recon(A, g, w, f0, pkg.params("svrem", alpha=0.7, eta=1, beta=beta, flags=binding.FLAG_AXIAL_PENALTY))
+    Aw = Ao if wtype == pkg.SVR_W_F32 else _bf16_weights(Ao)
+    m = oracle.Model(Aw, g, w, P.geom, Ns, beta=beta, axial=True)
+    R.osem_epoch(list(range(Ns)))
+    alg = oracle.SVREM(m, oracle.osem_epoch(m, f0, range(Ns)), 0.7, 1)
+    worst = 0.0
+    for c in range(10):
+        o = datagen.make_order(Ns, Ns, seed=200 + c)
+        R.svrem_epoch(o)
+        alg.run(o)
+        e = rel(R.image().cpu().numpy(), alg.f)
+        worst = max(worst, e)
+        assert e <= 1e-5, (c, e)
+    print(f"wtype {wtype}: 20 epochs, worst rel L2 {worst:.2e}", flush=True)
+    phi = R.objective()
+    assert abs(phi - m.objective(R.image().cpu().numpy().astype(np.float64))) <= 1e-6 * abs(phi)
