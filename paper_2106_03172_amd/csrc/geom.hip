@@ -231,21 +231,34 @@ __global__ void k_narrow(const int *src, int64_t n, uint16_t *dst) {
 
 // stats[0] = longest row, stats[1] = longest transposed row, stats[2 + t] =
 // row_ptr at the first row of subset t (t = 0..Ns)
-// maxima by a wavefront reduction and one integer atomic per wavefront (an
-// atomic per element serialised on one address: 247 us for the 1.4 M transposed
-// row counts of the 256^2 matrix)
-__device__ inline void wave_max_to(int v, int *dst) {
+// Maxima: a grid-stride loop, a block reduction and one integer atomic per
+// block.  Atomics on one address serialise (an atomic per element or per
+// wavefront took 245 us for the 1.4 M transposed row counts at 256^2), so
+// these kernels run at most MAX_BLOCKS blocks.
+constexpr int MAX_BLOCKS = 256;
+__device__ inline void block_max_to(int v, int *dst) {
+    __shared__ int red[256 / 64];
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o));
-    if ((threadIdx.x & 63) == 0) atomicMax(dst, v);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = v;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        int m = red[0];
+        for (int k = 1; k < (int)(blockDim.x >> 6); ++k) m = max(m, red[k]);
+        atomicMax(dst, m);
+    }
 }
-__global__ void k_row_stats(int M, const int *row_ptr, int *stats) {
-    const int r = blockIdx.x * blockDim.x + threadIdx.x;
-    wave_max_to(r < M ? row_ptr[r + 1] - row_ptr[r] : 0, &stats[0]);
+__global__ void __launch_bounds__(256) k_row_stats(int M, const int *row_ptr, int *stats) {
+    int v = 0;
+    for (int r = blockIdx.x * blockDim.x + threadIdx.x; r < M; r += gridDim.x * blockDim.x)
+        v = max(v, row_ptr[r + 1] - row_ptr[r]);
+    block_max_to(v, &stats[0]);
 }
-__global__ void k_max_count(int64_t n, const int *cnt, int *stats) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    wave_max_to(i < n ? cnt[i] : 0, &stats[1]);
+__global__ void __launch_bounds__(256) k_max_count(int64_t n, const int *cnt, int *stats) {
+    int v = 0;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        v = max(v, cnt[i]);
+    block_max_to(v, &stats[1]);
 }
 __global__ void k_subset_offsets(int Ns, const int *row_start, const int *row_ptr, int *stats) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -322,13 +335,13 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     A.d_val = val;
     A.d_valT = valT;
     k_siddon_fill<WT><<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, A.d_row_ptr, mu, col, val);
-    k_row_stats<<<gM, T, 0, s>>>(M, A.d_row_ptr, stats);
+    k_row_stats<<<std::min<unsigned>(gM, MAX_BLOCKS), T, 0, s>>>(M, A.d_row_ptr, stats);
     k_subset_offsets<<<(Ns + 1 + T - 1) / T, T, 0, s>>>(Ns, A.d_row_start, A.d_row_ptr, stats);
     // transposed rows per subset
     SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
     const unsigned gW = (unsigned)(((int64_t)M * 64 + T - 1) / T);  // a wavefront per row
     k_col_count<<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt);
-    k_max_count<<<(unsigned)((NT + T - 1) / T), T, 0, s>>>(NT, cnt, stats);
+    k_max_count<<<(unsigned)std::min<int64_t>((NT + T - 1) / T, MAX_BLOCKS), T, 0, s>>>(NT, cnt, stats);
     SVR_HIP(hipGetLastError());
     int64_t nnzT = 0;
     rc = exclusive_scan(cnt, NT, A.d_ptrT, &nnzT, s);

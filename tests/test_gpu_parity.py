@@ -58,6 +58,7 @@ def test_matrix_matches_oracle(small):
     assert inf.nnz == Ao.nnz and inf.max_row_nnz == np.diff(Ao.indptr).max()
     rows = oracle.subset_rows(P.geom, P.n_subsets)
     assert [int(x) for x in per] == [Ao[r].nnz for r in rows]
+    assert inf.max_col_nnz == max(int(np.diff(Ao[r].tocsc().indptr).max()) for r in rows)
 
 
 def test_transpose_matches_oracle(small):
