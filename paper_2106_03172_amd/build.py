@@ -34,6 +34,9 @@ FLAGS = [
     "-Wall", "-Wno-unused-function", "-Wno-unused-command-line-argument",
 ]
 
+# roctx ranges around the host phases (csrc/trace.h)
+LINK = ["-L/opt/rocm/lib", "-lrocprofiler-sdk-roctx"]
+
 
 def _hipcc() -> str:
     for c in ("/opt/rocm/bin/hipcc", "hipcc"):
@@ -42,9 +45,27 @@ def _hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str, defines=(), builddir=BUILDDIR) -> str:
+# AddressSanitizer and UndefinedBehaviorSanitizer for the host code only (the
+# device code is built as always).  The library then expects the ASan runtime
+# to be preloaded into the process (``sanitizer_runtime()``).
+SANITIZE = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+            "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+SANITIZED_LIB = os.path.join(BUILDDIR, "sanitize", "libsvr.so")
+
+
+def sanitizer_runtime() -> str:
+    """Path of the compiler's shared ASan runtime (it also carries the UBSan
+    handlers) that a process preloads to run the sanitized library."""
+    r = subprocess.run([_hipcc(), "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("ASan runtime not found")
+    return path
+
+
+def _compile(src: str, defines=(), builddir=BUILDDIR, extra=()) -> str:
     obj = os.path.join(builddir, os.path.splitext(src)[0] + ".o")
-    cmd = [_hipcc(), *FLAGS, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
+    cmd = [_hipcc(), *FLAGS, *extra, *[f"-D{d}" for d in defines], "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed on {src}:\n{r.stdout}\n{r.stderr}")
@@ -54,17 +75,25 @@ def _compile(src: str, defines=(), builddir=BUILDDIR) -> str:
     return obj
 
 
-def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
+def build(verbose: bool = False, defines=(), out: str = LIB, sanitize: bool = False) -> str:
     """Compiles every source and links the shared library; returns its path.
-    ``defines`` (e.g. ``["SVR_BP_G=8"]``) override the kernels' tuning constants."""
+    ``defines`` (e.g. ``["SVR_BP_G=8"]``) override the kernels' tuning constants;
+    ``sanitize`` builds the host code under ASan and UBSan into its own folder
+    (``SANITIZED_LIB`` unless ``out`` says otherwise)."""
     builddir = BUILDDIR if not defines else os.path.join(BUILDDIR, "_".join(defines).replace("=", ""))
+    extra = ()
+    if sanitize:
+        builddir = os.path.join(builddir, "sanitize")
+        extra = SANITIZE
+        if out == LIB:
+            out = SANITIZED_LIB
     os.makedirs(builddir, exist_ok=True)
     os.makedirs(os.path.dirname(out), exist_ok=True)
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     with cf.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
-        objs = list(ex.map(lambda s: _compile(s, defines, builddir), srcs))
+        objs = list(ex.map(lambda s: _compile(s, defines, builddir, extra), srcs))
     tmp = out + ".tmp"
-    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [_hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs, *LINK]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stdout}\n{r.stderr}")
@@ -75,4 +104,4 @@ def build(verbose: bool = False, defines=(), out: str = LIB) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose=True)
+    build(verbose=True, sanitize="--sanitize" in sys.argv[1:])

@@ -10,6 +10,7 @@
 #include "kernels.h"
 #include "util.h"
 #include "batch.h"
+#include "trace.h"
 
 using namespace svr;
 
@@ -147,6 +148,7 @@ int check_order(const Recon *R, const int32_t *order, int32_t n) {
 // with the update of the iteration that takes it (subset t): see
 // anchor_sum_update_pixel.
 int anchor_iteration(Recon *R, int kind, UpdateArgs &u, hipStream_t s) {
+    TraceRange tr("svr.anchor");
     Matrix &A = *R->A;
     FwdArgs fa{R->ft, R->g, R->w, R->ratio, nullptr, nullptr};
     fa.eps = ll_eps_of(R, kind);
@@ -317,6 +319,7 @@ int run_epoch_slices(Recon *R, int algo, int kind, const int32_t *order, int32_t
         const int t = order[i];
         float *f = R->f[R->cur];
         if (kind == UPD_SVREM && R->k % ((int64_t)R->p.eta * R->Ns) == 0) {
+            TraceRange tr("svr.anchor");
             rc = prof_begin(R, 2, s);
             if (!rc) rc = ms_forward(A, R->plan, -1, 1, S, f, R->g, R->w, R->ratio, nullptr, nullptr, s, nullptr);
             if (!rc) rc = prof_end(R, s);
@@ -373,6 +376,7 @@ int check_status(Recon *R, hipStream_t s) {
 
 int run_epoch(Recon *R, int algo, const int32_t *order, int32_t n, void *stream,
               const int32_t *refresh = nullptr) {
+    TraceRange tr(epoch_range_name(algo));
     clear_error();
     SVR_REQUIRE(R, "recon is NULL");
     if (algo != SVR_ALGO_OSEM)
@@ -461,6 +465,7 @@ int svr_version(void) { return 10000; }
 int svr_build_system_matrix(const svr_geometry *geom, int32_t n_subsets, int32_t wtype, const float *mu_dev,
                             void *stream, svr_matrix **out) {
     clear_error();
+    TraceRange tr("svr.build_matrix");
     SVR_REQUIRE(out, "out is NULL");
     *out = nullptr;
     int rc = check_geom(geom);
@@ -686,6 +691,7 @@ extern "C" {
 int svr_project(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t n_slices, float *y_dev,
                 void *stream) {
     clear_error();
+    TraceRange tr("svr.project");
     SVR_REQUIRE(A && x_dev && y_dev, "NULL argument");
     SVR_REQUIRE(subset >= -1 && subset < A->Ns, "subset %d out of range", subset);
     SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
@@ -743,6 +749,7 @@ extern "C" {
 int svr_project_noalloc(const svr_matrix *A, int32_t subset, const float *x_dev, int32_t n_slices, float *y_dev,
                         void *stream) {
     clear_error();
+    TraceRange tr("svr.project_noalloc");
     SVR_REQUIRE(A && x_dev && y_dev, "NULL argument");
     SVR_REQUIRE(subset >= -1 && subset < A->Ns, "subset %d out of range", subset);
     SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
@@ -767,6 +774,7 @@ int svr_project_noalloc(const svr_matrix *A, int32_t subset, const float *x_dev,
 int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int32_t n_slices, float *x_dev,
                     void *stream) {
     clear_error();
+    TraceRange tr("svr.backproject");
     SVR_REQUIRE(A && x_dev && y_dev, "NULL argument");
     SVR_REQUIRE(subset >= -1 && subset < A->Ns, "subset %d out of range", subset);
     SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
@@ -787,6 +795,7 @@ int svr_backproject(const svr_matrix *A, int32_t subset, const float *y_dev, int
 int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, const float *f0_dev, int32_t n_slices,
                      const svr_params *p, void *stream, svr_recon **out) {
     clear_error();
+    TraceRange tr("svr.recon_create");
     SVR_REQUIRE(out, "out is NULL");
     *out = nullptr;
     SVR_REQUIRE(A && g_dev && w_dev && f0_dev && p, "NULL argument");
@@ -920,6 +929,7 @@ int svr_sagaem_epoch(svr_recon *R, const int32_t *o, const int32_t *refresh, int
 
 int svr_objective(svr_recon *R, double *phi_host, void *stream) {
     clear_error();
+    TraceRange tr("svr.objective");
     SVR_REQUIRE(R && phi_host, "NULL argument");
     SVR_HIP(hipSetDevice(R->device));
     hipStream_t s = (hipStream_t)stream;
@@ -1019,6 +1029,7 @@ int svr_recon_info(const svr_recon *R, svr_recon_info_t *info) {
 
 int svr_recon_get_state(const svr_recon *R, void *buf, size_t *len, void *stream) {
     clear_error();
+    TraceRange tr("svr.get_state");
     SVR_REQUIRE(R && len, "NULL argument");
     auto fields = state_fields(R);
     size_t tot = sizeof(StateHeader);
@@ -1043,6 +1054,7 @@ int svr_recon_get_state(const svr_recon *R, void *buf, size_t *len, void *stream
 
 int svr_recon_set_state(svr_recon *R, const void *buf, size_t len, void *stream) {
     clear_error();
+    TraceRange tr("svr.set_state");
     SVR_REQUIRE(R && buf, "NULL argument");
     SVR_REQUIRE(len >= sizeof(StateHeader), "buffer too small");
     StateHeader h;

@@ -21,6 +21,7 @@
 
 #include "batch.h"
 #include "common.h"
+#include "trace.h"
 #include "util.h"
 
 namespace {
@@ -309,6 +310,7 @@ int svr_serve_submit(svr_server *S, const svr_serve_request *r, uint64_t *ticket
 
 int svr_serve_step(svr_server *S, int32_t max_ticks) {
     clear_error();
+    TraceRange tr("svr.serve_step");
     SVR_REQUIRE(S, "NULL server");
     SVR_HIP(hipSetDevice(S->device));
     for (int tick = 0; max_ticks <= 0 || tick < max_ticks; ++tick) {

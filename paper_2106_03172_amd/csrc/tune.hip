@@ -11,6 +11,7 @@
 
 #include "common.h"
 #include "kernels.h"
+#include "trace.h"
 
 namespace svr {
 int forward_run_length(const Matrix &A, int rows);
@@ -164,6 +165,7 @@ int svr_matrix_set_tuning(svr_matrix *A, const svr_tuning_t *t) {
 
 int svr_matrix_tune(svr_matrix *A, void *stream, svr_tuning_t *out) {
     svr::clear_error();
+    svr::TraceRange tr("svr.tune");
     SVR_REQUIRE(A, "NULL argument");
     SVR_HIP(hipSetDevice(A->device));
     return svr::tune(*A, (hipStream_t)stream, out);

@@ -104,3 +104,16 @@ def test_binding_rejects_mismatched_sizes_before_any_call():
         S.submit(geom, 1, np.zeros(12), np.zeros(13), pkg.params("svrem"), 1, 0)
     S.h = None
     A.h = None
+
+
+def test_host_phases_carry_roctx_ranges():
+    """Matrix build, epoch calls, anchors, projector calls and serving ticks
+    push named roctx ranges, so the library imports the roctx entry points."""
+    import shutil
+    import subprocess
+    nm = shutil.which("nm")
+    if nm is None or not os.path.exists(binding.LIB_PATH):
+        pytest.skip("nm or library not available")
+    syms = subprocess.run([nm, "-D", "--undefined-only", binding.LIB_PATH], capture_output=True, text=True,
+                          check=True).stdout
+    assert "roctxRangePushA" in syms and "roctxRangePop" in syms
