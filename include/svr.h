@@ -243,7 +243,9 @@ typedef struct {
  * per subset (slices as columns) and the recon runs OSEM and SVREM epochs
  * (other algos are rejected with SVR_EINVAL).  SVR_FLAG_MODIFIED_LL needs a
  * gradient algo (SVRG, SAGA, SGA, BSREM) and a finite ll_eps > 0; the
- * persistent flag is not available with SAGAEM or the modified likelihood.
+ * persistent flag is not available with SAGAEM.  A stack's image and
+ * sinogram blocks (n_slices x N and n_slices x M floats) must each stay below
+ * 2^31 bytes (SVR_EINVAL otherwise).
  *   g_dev  : [S][M] counts (finite, >= 0);  w_dev: [S][M] background (finite, >= 0)
  *   f0_dev : [S][N] starting image (finite, > 0)
  * The matrix must outlive the recon.  Synchronises (validates the data). */

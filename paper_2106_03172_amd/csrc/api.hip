@@ -802,6 +802,11 @@ int svr_recon_create(svr_matrix *A, const float *g_dev, const float *w_dev, cons
     SVR_REQUIRE(n_slices >= 1, "n_slices must be >= 1");
     SVR_REQUIRE(n_slices == 1 || p->algo == SVR_ALGO_SVREM || p->algo == SVR_ALGO_OSEM,
                 "slice stacks (n_slices > 1) run OSEM and SVREM");
+    // the stack kernels address an image or sinogram block with 32-bit byte
+    // offsets (buffer loads)
+    SVR_REQUIRE(n_slices == 1 || ((int64_t)A->N * n_slices * 4 <= INT32_MAX && (int64_t)A->M * n_slices * 4 <= INT32_MAX),
+                "slice stack too large: %d slices x %d pixels / %d rows exceeds 2^31 bytes per block", n_slices, A->N,
+                A->M);
     SVR_REQUIRE(kind_of_algo(p->algo) >= 0, "unknown algo %d", p->algo);
     SVR_REQUIRE(p->alpha > 0 && std::isfinite(p->alpha), "alpha must be finite and > 0");
     SVR_REQUIRE(p->beta >= 0 && std::isfinite(p->beta), "beta must be finite and >= 0");

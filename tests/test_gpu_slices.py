@@ -74,6 +74,17 @@ def test_stack_rejects_gradient_algorithms():
         pkg.Recon(A, P.g, P.w, np.ones((3, 256)), pkg.params("saga"))
 
 
+def test_stack_beyond_32bit_offsets_is_rejected():
+    """A stack whose image block passes 2^31 bytes is refused at creation,
+    before the (small, valid) data pointers are read."""
+    P = datagen.make_multislice_problem(16, 16, 2.5, 12, 23, 2.5, 3, 1e4, n_slices=2, seed=1)
+    A = pkg.SystemMatrix(P.geom, 3)
+    t = torch.ones(1024, device="cuda")
+    S = (2 ** 31) // (4 * A.N) + 1
+    with pytest.raises(pkg.SvrError, match="too large"):
+        binding.svr_recon_create(A.h, t, t, t, S, pkg.params("svrem"))
+
+
 def _bf16_weights(A):
     """The FP64 lengths rounded as the library stores BF16 weights: to FP32,
     then to BF16 with round-to-nearest-even (test-side rounding of the
