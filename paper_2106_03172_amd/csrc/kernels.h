@@ -77,6 +77,20 @@ inline hipError_t launch_k(void (*kernel)(KArgs...), dim3 grid, dim3 block, hipS
     return hipGetLastError();
 }
 
+// ---- XCD-contiguous work chunks ----------------------------------------------------
+// Workgroups are dispatched to the XCDs round-robin by index.  A pass over
+// `chunks` consecutive chunks of work launched as xcd_grid(chunks, per) blocks
+// gives block b the chunk xcd_chunk(b, per): XCD b mod XCDS takes the
+// contiguous chunks [x per, (x + 1) per), so the cache lines two neighbouring
+// chunks share, and the image rows a pixel's stencil reads, stay in one L2.
+// Past the last chunk: >= chunks (the block returns).  Which block takes a
+// chunk changes nothing in its arithmetic.
+__device__ inline int xcd_chunk(int b, int per) { return (b % XCDS) * per + b / XCDS; }
+inline int xcd_grid(int64_t chunks, int &per) {
+    per = (int)((chunks + XCDS - 1) / XCDS);
+    return per * XCDS;
+}
+
 // ---- cross-lane sums ------------------------------------------------------------
 // FP64 value of another lane through a DPP move of both halves (CTRL: the
 // GFX9 DPP control; every source lane used here lies in the same 16-lane row

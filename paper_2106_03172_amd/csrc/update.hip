@@ -29,11 +29,16 @@
 
 namespace svr {
 
+// One BP_G-lane group per pixel, 64 consecutive pixels per workgroup; XCD x
+// takes a contiguous eighth of the image (xcd_chunk), so the transposed-row
+// lines two neighbouring workgroups share, the stencil's neighbour rows and
+// the 4 x 8 tiles of the tiled write stay in one L2 (HBM counters: 1.17x ->
+// 1.03x of the algorithmic bytes)
 template <int KIND, typename WT, typename IT>
 __global__ void __launch_bounds__(BP_THREADS)
 k_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
-         const float *__restrict__ sens_t, const double *__restrict__ sens, int N, UpdateArgs u) {
-    const int gid = blockIdx.x * BP_THREADS + threadIdx.x;
+         const float *__restrict__ sens_t, const double *__restrict__ sens, int N, int per, UpdateArgs u) {
+    const int gid = xcd_chunk(blockIdx.x, per) * BP_THREADS + threadIdx.x;
     const int n = gid / BP_G, lig = gid % BP_G;
     if (n >= N) return;
     update_pixel<KIND, WT, IT>(ptrT, rowT, valT, sens_t, sens, N, u, n, lig);
@@ -41,12 +46,13 @@ k_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__
 
 template <int KIND>
 static int launch_update_k(const Matrix &A, const UpdateArgs &u, hipStream_t s) {
-    const int nb = (int)(((int64_t)A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
+    int per = 0;
+    const int nb = xcd_grid(((int64_t)A.N * BP_G + BP_THREADS - 1) / BP_THREADS, per);
     return with_types(A, [&](auto w, auto i) {
         using WT = decltype(w);
         using IT = decltype(i);
         SVR_HIP(launch_k(k_update<KIND, WT, IT>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
-                         (const WT *)A.d_valT, A.d_sens_t, A.d_sens, A.N, u));
+                         (const WT *)A.d_valT, A.d_sens_t, A.d_sens, A.N, per, u));
         return SVR_OK;
     });
 }
