@@ -392,6 +392,24 @@ int  svr_serve_poll(svr_server *S, uint64_t ticket, svr_serve_result *res);
 int  svr_serve_cancel(svr_server *S, uint64_t ticket);
 void svr_serve_destroy(svr_server *S);
 
+/* Server state for monitoring (host-only, enqueues nothing): queue depth,
+ * slots in use, device memory held, and running totals. */
+typedef struct {
+    int32_t queued;            /* submitted, waiting for admission */
+    int32_t resident;          /* admitted and iterating (<= max_slots) */
+    int32_t max_slots;
+    int32_t done_unpolled;     /* finished (any status), result not yet polled */
+    int64_t used_bytes;        /* device bytes held by resident requests (the admission estimate,
+                                  then the matrix's actual size plus the recon's estimate) */
+    int64_t mem_budget_bytes;
+    int64_t ticks;             /* scheduler ticks run */
+    int64_t admitted;          /* requests admitted so far */
+    int64_t completed;         /* requests finished so far: done, failed or cancelled */
+    int64_t epochs;            /* SVREM epochs run so far, over all requests */
+} svr_serve_stats_t;
+/* Errors: SVR_EINVAL (NULL argument). */
+int  svr_serve_stats(const svr_server *S, svr_serve_stats_t *out);
+
 #ifdef __cplusplus
 }
 #endif

@@ -83,6 +83,12 @@ class svr_serve_request(C.Structure):
                 ("f0_value", C.c_float)]
 
 
+class svr_serve_stats_t(C.Structure):
+    _fields_ = [("queued", C.c_int32), ("resident", C.c_int32), ("max_slots", C.c_int32),
+                ("done_unpolled", C.c_int32), ("used_bytes", C.c_int64), ("mem_budget_bytes", C.c_int64),
+                ("ticks", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("epochs", C.c_int64)]
+
+
 class svr_serve_result(C.Structure):
     _fields_ = [("f_host", C.POINTER(C.c_float)), ("phi", C.c_double), ("queue_ms", C.c_double),
                 ("run_ms", C.c_double), ("status", C.c_int32)]
@@ -119,6 +125,7 @@ _SIGS = {
     "svr_serve_poll": ([_VP, C.c_uint64, C.POINTER(svr_serve_result)], C.c_int),
     "svr_serve_cancel": ([_VP, C.c_uint64], C.c_int),
     "svr_serve_destroy": ([_VP], None),
+    "svr_serve_stats": ([_VP, C.POINTER(svr_serve_stats_t)], C.c_int),
 }
 for _e in ("osem", "svrem", "svrg", "saga", "sga", "bsrem", "sem"):
     _SIGS[f"svr_{_e}_epoch"] = ([_VP, _VP, _I32, _VP], C.c_int)
@@ -482,6 +489,12 @@ class Server:
 
     def cancel(self, ticket: int):
         _check(lib().svr_serve_cancel(self.h, C.c_uint64(ticket)))
+
+    def stats(self) -> dict:
+        """Queue depth, slots in use, device memory held and running totals (svr_serve_stats)."""
+        st = svr_serve_stats_t()
+        _check(lib().svr_serve_stats(self.h, C.byref(st)))
+        return {k: int(getattr(st, k)) for k, _ in svr_serve_stats_t._fields_}
 
     def close(self):
         if getattr(self, "h", None):

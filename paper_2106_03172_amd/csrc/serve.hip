@@ -95,6 +95,7 @@ struct svr_server {
     uint64_t next_ticket = 1;
     int64_t used_bytes = 0;
     int device = 0;
+    int64_t ticks = 0, admitted = 0, completed = 0, epochs = 0;  // running totals (svr_serve_stats)
 };
 
 using namespace svr;
@@ -217,6 +218,7 @@ void batched_epoch(svr_server *S) {
         }
     }
     for (Res &r : rs) r.q->epochs_done++;
+    S->epochs += (int64_t)rs.size();
 }
 
 int finish(svr_server *S, Request *q, hipStream_t s) {
@@ -329,7 +331,9 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
                 if (rc) q->status = rc;
                 q->epochs_done++;
             }
+            S->epochs += (int64_t)running;
         }
+        ++S->ticks;
         // admission, FIFO while a slot is free and the estimate fits the budget, after the epochs
         // are enqueued: a new request's matrix build (which waits on the host for its sizes) and
         // OSEM epoch then overlap the resident requests' epochs on the other streams
@@ -339,11 +343,13 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
             S->queue.pop_front();
             q->stream = (int)(q->ticket % S->streams.size());
             int rc = admit(S, q, S->streams[q->stream]);
+            ++S->admitted;
             if (rc) {
                 q->status = rc;
                 q->state = DONE;
                 q->t_admit = q->t_done = clk::now();
                 release(S, q);
+                ++S->completed;
                 continue;
             }
             S->resident.push_back(q->ticket);
@@ -358,6 +364,7 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
                 int st = q->status;
                 finish(S, q, S->streams[q->stream]);
                 if (st != SVR_OK) q->status = st;
+                ++S->completed;
             } else {
                 still.push_back(tk);
             }
@@ -410,6 +417,25 @@ int svr_serve_cancel(svr_server *S, uint64_t ticket) {
     q->state = DONE;
     q->status = SVR_ECANCELLED;
     q->t_done = clk::now();
+    ++S->completed;
+    return SVR_OK;
+}
+
+int svr_serve_stats(const svr_server *S, svr_serve_stats_t *out) {
+    clear_error();
+    SVR_REQUIRE(S && out, "NULL argument");
+    int32_t done = 0;
+    for (const auto &kv : S->reqs) done += kv.second->state == DONE ? 1 : 0;
+    out->queued = (int32_t)S->queue.size();
+    out->resident = (int32_t)S->resident.size();
+    out->max_slots = S->cfg.max_slots;
+    out->done_unpolled = done;
+    out->used_bytes = S->used_bytes;
+    out->mem_budget_bytes = S->cfg.mem_budget_bytes;
+    out->ticks = S->ticks;
+    out->admitted = S->admitted;
+    out->completed = S->completed;
+    out->epochs = S->epochs;
     return SVR_OK;
 }
 

@@ -159,3 +159,38 @@ def test_cancel_and_unknown_ticket():
     with pytest.raises(pkg.SvrError):
         S.poll(12345)
     S.close()
+
+
+@pytest.mark.parametrize("batch", [True, False])
+def test_server_stats_track_queue_slots_memory_and_totals(batch):
+    """svr_serve_stats: after submits everything is queued; a tick admits up
+    to max_slots requests, whose held bytes stay within the budget; a cancelled
+    request counts as completed; when all are done nothing is held, every
+    admitted request is completed, the epochs are the requests' epochs and the
+    results wait unpolled until polled."""
+    probs = [_req(s) for s in SPECS]
+    budget = 1 << 31
+    S = pkg.Server(budget, max_slots=2, n_streams=2, batch=batch)
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+    tickets = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS, 50 + i) for i, P in enumerate(probs)]
+    st = S.stats()
+    assert (st["queued"], st["resident"], st["max_slots"], st["done_unpolled"]) == (4, 0, 2, 0)
+    assert (st["used_bytes"], st["mem_budget_bytes"], st["ticks"], st["admitted"], st["completed"]) == \
+        (0, budget, 0, 0, 0)
+    S.cancel(tickets[3])
+    st = S.stats()
+    assert (st["queued"], st["completed"], st["done_unpolled"]) == (3, 1, 1)
+    S.step(1)  # no request resident yet: the tick admits two
+    st = S.stats()
+    assert (st["queued"], st["resident"], st["admitted"], st["ticks"]) == (1, 2, 2, 1)
+    assert 0 < st["used_bytes"] <= budget
+    S.step(0)
+    st = S.stats()
+    assert (st["queued"], st["resident"], st["used_bytes"]) == (0, 0, 0)
+    assert (st["admitted"], st["completed"], st["done_unpolled"]) == (3, 4, 4)
+    assert st["epochs"] == 3 * EPOCHS
+    for t in tickets[:3]:
+        assert S.poll(t)["status"] == 0
+    assert S.poll(tickets[3])["status"] == pkg.binding.SVR_ECANCELLED
+    assert S.stats()["done_unpolled"] == 0
+    S.close()
