@@ -164,8 +164,15 @@ int svr_matrix_set_tuning(svr_matrix *A, const svr_tuning_t *t);
 /* Autotuner: times the candidate run lengths of the whole-matrix forward
  * pass and of the anchor table on A itself, the two kernels alternating as in
  * an anchor pass (HIP events on `stream`, median of 9 pairs, synthetic
- * operands), keeps the fastest in A and reports it in out (nullable).  Allocates about 4(2M + N + Ns*N) bytes for the duration of
- * the call and synchronises.  Errors: SVR_ENOMEM, SVR_EDEVICE (A unchanged). */
+ * operands), keeps the fastest in A and reports it in out (nullable).
+ * Allocates about 4(2M + N + Ns*N) bytes for the duration of the call and
+ * synchronises.  With the environment variable SVR_TUNE_CACHE naming a file,
+ * a matrix whose geometry, subsets, weight and index types and device (name,
+ * compute units) are recorded there takes the recorded run lengths without
+ * timing (out reports the recorded durations); otherwise the result is
+ * appended to the file (one text line per tuning; unreadable lines are
+ * ignored, an unwritable file only costs the next call its timing).
+ * Errors: SVR_ENOMEM, SVR_EDEVICE (A unchanged). */
 int svr_matrix_tune(svr_matrix *A, void *stream, svr_tuning_t *out);
 
 /* ---- projectors ---------------------------------------------------------- */

@@ -7,6 +7,10 @@
 // wavefront computes a row, never the row's arithmetic, so every result is
 // bitwise the same under any tuning.
 #include <algorithm>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <string>
 #include <vector>
 
 #include "common.h"
@@ -132,6 +136,82 @@ int tune(Matrix &A, hipStream_t s, svr_tuning_t *out) {
     return rc;
 }
 
+// ---- tuning cache (environment SVR_TUNE_CACHE = a file path) --------------------
+// One line per tuned matrix: "svr-tune 1 <key> fwd <R> bp <T> fwd_us <x> bp_us <y>",
+// the key naming everything the timings depend on (geometry, subsets, weight
+// and index types, device name and compute units).  A tune call whose key is
+// in the file applies the stored run lengths without timing; otherwise it
+// tunes and appends a line.  Lines that do not parse are ignored.
+std::string cache_key(const Matrix &A) {
+    hipDeviceProp_t prop{};
+    std::string dev = "unknown";
+    if (hipGetDeviceProperties(&prop, A.device) == hipSuccess) {
+        dev = prop.gcnArchName;
+        for (char &c : dev)
+            if (c == ' ') c = '_';
+    }
+    const svr_geometry &g = A.geom;
+    char buf[512];
+    snprintf(buf, sizeof buf, "%dx%d/%.9g/%dx%d/%.9g/%.9g/ns%d/w%d/i%d/%s/cu%d", g.nx, g.ny, g.pixel_mm, g.n_views,
+             g.n_bins, g.bin_mm, g.arc_rad, A.Ns, A.wtype, A.idx16 ? 16 : 32, dev.c_str(), A.cus);
+    return buf;
+}
+
+bool cache_lookup(const char *path, const std::string &key, int *fwd, int *bp, double *fwd_us, double *bp_us) {
+    FILE *fp = fopen(path, "r");
+    if (!fp) return false;
+    char line[1024], k[600];
+    bool found = false;
+    while (fgets(line, sizeof line, fp)) {
+        int ver = 0, R = 0, T = 0;
+        double uf = 0.0, ub = 0.0;
+        if (sscanf(line, "svr-tune %d %599s fwd %d bp %d fwd_us %lf bp_us %lf", &ver, k, &R, &T, &uf, &ub) == 6 &&
+            ver == 1 && key == k && R >= 1 && R <= 31 && T >= 1 && T <= 1024) {
+            *fwd = R;  // the last matching line wins
+            *bp = T;
+            *fwd_us = uf;
+            *bp_us = ub;
+            found = true;
+        }
+    }
+    fclose(fp);
+    return found;
+}
+
+void cache_store(const char *path, const std::string &key, int fwd, int bp, double fwd_us, double bp_us) {
+    FILE *fp = fopen(path, "a");
+    if (!fp) return;  // a cache that cannot be written only costs the next call its timing
+    fprintf(fp, "svr-tune 1 %s fwd %d bp %d fwd_us %.3f bp_us %.3f\n", key.c_str(), fwd, bp, fwd_us, bp_us);
+    fclose(fp);
+}
+
+int tune_cached(Matrix &A, hipStream_t s, svr_tuning_t *out) {
+    const char *path = getenv("SVR_TUNE_CACHE");
+    if (!path || !*path) return tune(A, s, out);
+    const std::string key = cache_key(A);
+    int R = 0, T = 0;
+    double uf = 0.0, ub = 0.0;
+    if (cache_lookup(path, key, &R, &T, &uf, &ub)) {
+        A.run_fwd = R;
+        A.run_bp = T;
+        if (out) {
+            out->fwd_pairs_per_wave = R;
+            out->bp_rows_per_group = T;
+            out->fwd_pair_rows = A.pair_rows_eff();
+            out->fwd_us = uf;
+            out->bp_us = ub;
+            out->fwd_natural_order = A.xcd_bands ? 0 : 1;
+        }
+        return SVR_OK;
+    }
+    svr_tuning_t t{};
+    const int rc = tune(A, s, &t);
+    if (rc) return rc;
+    cache_store(path, key, t.fwd_pairs_per_wave, t.bp_rows_per_group, t.fwd_us, t.bp_us);
+    if (out) *out = t;
+    return SVR_OK;
+}
+
 }  // namespace
 }  // namespace svr
 
@@ -168,7 +248,7 @@ int svr_matrix_tune(svr_matrix *A, void *stream, svr_tuning_t *out) {
     svr::TraceRange tr("svr.tune");
     SVR_REQUIRE(A, "NULL argument");
     SVR_HIP(hipSetDevice(A->device));
-    return svr::tune(*A, (hipStream_t)stream, out);
+    return svr::tune_cached(*A, (hipStream_t)stream, out);
 }
 
 }  // extern "C"

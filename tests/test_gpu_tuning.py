@@ -128,3 +128,33 @@ def test_forward_row_order_is_bitwise_neutral(shape):
         out.append(got)
     for k in out[0]:
         np.testing.assert_array_equal(np.asarray(out[0][k]), np.asarray(out[1][k]), err_msg=k)
+
+
+def test_tuning_cache(tmp_path, monkeypatch):
+    """SVR_TUNE_CACHE: the first tune of a geometry times the candidates and
+    appends one line; a second matrix of the same geometry takes the recorded
+    run lengths without timing (its own setting overridden, no new line); a
+    different geometry appends its own line; lines that do not parse are
+    ignored."""
+    path = tmp_path / "tune.txt"
+    monkeypatch.setenv("SVR_TUNE_CACHE", str(path))
+    P = datagen.make_problem(96, 96, 2.0, 70, 131, 2.0, 7, 3e5, attenuation=False, seed=21)
+    A = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32)
+    t1 = A.tune()
+    lines = path.read_text().splitlines()
+    assert len(lines) == 1 and lines[0].startswith("svr-tune 1 96x96/"), lines
+    B = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32)
+    fw = 3 if t1[0] != 3 else 4
+    B.set_tuning(fw, 7)
+    t2 = B.tune()
+    assert t2[:2] == t1[:2] and B.tuning() == t1[:2]
+    assert abs(t2[2] - t1[2]) < 1e-3 and abs(t2[3] - t1[3]) < 1e-3
+    assert len(path.read_text().splitlines()) == 1
+    Q = datagen.make_problem(64, 64, 2.0, 40, 91, 2.0, 5, 1e5, attenuation=False, seed=22)
+    C = pkg.SystemMatrix(Q.geom, Q.n_subsets, pkg.SVR_W_F32)
+    C.tune()
+    assert len(path.read_text().splitlines()) == 2
+    path.write_text("not a tuning line\nsvr-tune 1 " + lines[0].split()[2] + " fwd 99 bp 1 fwd_us 1 bp_us 1\n"
+                    + "\n".join(path.read_text().splitlines()) + "\n")
+    D = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32)
+    assert D.tune()[:2] == t1[:2]   # the out-of-range line is skipped, the valid one used
