@@ -262,7 +262,8 @@ def main():
     else:
         tuning = A.tune()
         log(f"autotuned run lengths: forward {tuning[0]} rows/wavefront ({tuning[2]:.1f} us), "
-            f"anchor table {tuning[1]} rows/group ({tuning[3]:.1f} us)")
+            f"anchor table {tuning[1]} rows/group ({tuning[3]:.1f} us); per-subset batch widths "
+            f"{A.batch_widths()}")
 
     if args.fwd_natural_order:
         A.set_tuning(tuning[0], tuning[1], fwd_natural_order=1)
@@ -396,7 +397,8 @@ def main():
                                   "products_and_sums": "f64", "statistics_and_objective": "f64"},
                    "epochs_per_step": epochs_per_step, "nnz": int(inf.nnz), "build_s": round(build_s, 4),
                    "tuning": {"fwd_pairs_per_wave": tuning[0], "bp_rows_per_group": tuning[1],
-                              "fwd_row_order": "natural" if args.fwd_natural_order else "xcd_bin_bands"},
+                              "fwd_row_order": "natural" if args.fwd_natural_order else "xcd_bin_bands",
+                              "subset_batch_widths": dict(zip(("forward", "update"), A.batch_widths()))},
                    "objective_after": phi, "parallelism": "single GPU",
                    "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                                for k, v in kernels.items()},

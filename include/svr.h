@@ -150,13 +150,19 @@ typedef struct {
                                     0 (default) gives each of the device's 8 XCDs a band of bins of every
                                     view, so its L2 holds the part of the image those rays cross; 1 takes
                                     the rows in order.  Results are bitwise the same either way. */
+    int32_t subset_fwd_batch;    /* per-subset forward passes with one row per wavefront: index/weight
+                                    loads per lane issued together, 4, 6 or 8 (0: 8) */
+    int32_t subset_bp_batch;     /* per-subset update: loads per lane of each pixel's 4-lane group issued
+                                    together, 3, 4, 5, 6 or 8 (0: 5).  Neither width changes the entries
+                                    a lane adds or their order, so results are bitwise the same. */
 } svr_tuning_t;
 
-/* Run lengths in use for the whole-matrix passes (0 resolved to the
- * size-based choice); fwd_us and bp_us are 0.  Host-only. */
+/* Run lengths and batch widths in use (0 resolved to the size-based or
+ * default choice); fwd_us and bp_us are 0.  Host-only. */
 int svr_matrix_get_tuning(const svr_matrix *A, svr_tuning_t *t);
 
-/* Sets the run lengths (0 = size-based).  Errors: SVR_EINVAL out of range.
+/* Sets the run lengths (0 = size-based) and batch widths (0 = default).
+ * Errors: SVR_EINVAL out of range.
  * Not to be called while work that uses A is being enqueued from another
  * thread. */
 int svr_matrix_set_tuning(svr_matrix *A, const svr_tuning_t *t);
@@ -164,11 +170,14 @@ int svr_matrix_set_tuning(svr_matrix *A, const svr_tuning_t *t);
 /* Autotuner: times the candidate run lengths of the whole-matrix forward
  * pass and of the anchor table on A itself, the two kernels alternating as in
  * an anchor pass (HIP events on `stream`, median of 9 pairs, synthetic
- * operands), keeps the fastest in A and reports it in out (nullable).
+ * operands), then the batch widths of the per-subset forward and SVREM update
+ * passes, timed together over all subsets as an epoch runs them (median of 9;
+ * the default widths are kept unless a pair is at least 2% faster), keeps the
+ * fastest in A and reports them in out (nullable).
  * Allocates about 4(2M + N + Ns*N) bytes for the duration of the call and
  * synchronises.  With the environment variable SVR_TUNE_CACHE naming a file,
  * a matrix whose geometry, subsets, weight and index types and device (name,
- * compute units) are recorded there takes the recorded run lengths without
+ * compute units) are recorded there takes the recorded choices without
  * timing (out reports the recorded durations); otherwise the result is
  * appended to the file (one text line per tuning; unreadable lines are
  * ignored, an unwritable file only costs the next call its timing).

@@ -68,7 +68,7 @@ class svr_kernel_times_t(C.Structure):
 class svr_tuning_t(C.Structure):
     _fields_ = [("fwd_pairs_per_wave", C.c_int32), ("bp_rows_per_group", C.c_int32),
                 ("fwd_pair_rows", C.c_int32), ("fwd_us", C.c_double), ("bp_us", C.c_double),
-                ("fwd_natural_order", C.c_int32)]
+                ("fwd_natural_order", C.c_int32), ("subset_fwd_batch", C.c_int32), ("subset_bp_batch", C.c_int32)]
 
 
 class svr_serve_config(C.Structure):
@@ -308,16 +308,25 @@ class SystemMatrix:
         return int(t.fwd_pairs_per_wave), int(t.bp_rows_per_group)
 
     def set_tuning(self, fwd_pairs_per_wave: int = 0, bp_rows_per_group: int = 0, fwd_pair_rows=None,
-                   fwd_natural_order=None):
+                   fwd_natural_order=None, subset_fwd_batch=None, subset_bp_batch=None):
         """Sets the run lengths (0: size-based); fwd_pair_rows (None: unchanged) is the row count above
         which a forward pass runs a pair of rows per wavefront (0: from the device); fwd_natural_order
-        (None: unchanged) 1 takes the rows of one-row-per-wavefront passes in order, 0 in XCD bin bands."""
+        (None: unchanged) 1 takes the rows of one-row-per-wavefront passes in order, 0 in XCD bin bands;
+        subset_fwd_batch / subset_bp_batch (None: unchanged, 0: default) the per-subset batch widths."""
         cur = svr_tuning_t()
         _check(lib().svr_matrix_get_tuning(self.h, C.byref(cur)))
         pr = cur.fwd_pair_rows if fwd_pair_rows is None else int(fwd_pair_rows)
         no = cur.fwd_natural_order if fwd_natural_order is None else int(fwd_natural_order)
-        t = svr_tuning_t(int(fwd_pairs_per_wave), int(bp_rows_per_group), pr, 0.0, 0.0, no)
+        fu = cur.subset_fwd_batch if subset_fwd_batch is None else int(subset_fwd_batch)
+        bu = cur.subset_bp_batch if subset_bp_batch is None else int(subset_bp_batch)
+        t = svr_tuning_t(int(fwd_pairs_per_wave), int(bp_rows_per_group), pr, 0.0, 0.0, no, fu, bu)
         _check(lib().svr_matrix_set_tuning(self.h, C.byref(t)))
+
+    def batch_widths(self):
+        """Batch widths of the per-subset passes in use: (forward loads per lane, update loads per lane)."""
+        t = svr_tuning_t()
+        _check(lib().svr_matrix_get_tuning(self.h, C.byref(t)))
+        return int(t.subset_fwd_batch), int(t.subset_bp_batch)
 
     def pair_rows(self) -> int:
         """Effective row count above which a forward pass runs a pair of rows per wavefront."""
@@ -326,7 +335,8 @@ class SystemMatrix:
         return int(t.fwd_pair_rows)
 
     def tune(self, stream=None):
-        """Autotunes the run lengths on the device; returns (fwd, bp, fwd_us, bp_us)."""
+        """Autotunes the run lengths and the per-subset batch widths on the device; returns
+        (fwd, bp, fwd_us, bp_us); batch_widths() then gives the chosen widths."""
         t = svr_tuning_t()
         _check(lib().svr_matrix_tune(self.h, _stream(stream), C.byref(t)))
         return int(t.fwd_pairs_per_wave), int(t.bp_rows_per_group), float(t.fwd_us), float(t.bp_us)

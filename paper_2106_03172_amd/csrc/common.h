@@ -129,6 +129,9 @@ struct Matrix {
     int run_fwd = 0;                // row pairs per wavefront in whole-matrix forward passes (0: by size)
     int run_bp = 0;                 // transposed rows per lane group in whole-matrix back-projections (0: by size)
     int xcd_bands = 1;              // one-row-per-wavefront forward passes: each XCD a band of bins (band_row)
+    int sub_fwd_u = 0;              // one-row-per-wavefront forward passes: index/weight loads per lane and batch
+                                    // (0: FWD_U; tuned among 4, 6, 8)
+    int sub_bp_u = 0;               // per-subset update: loads per lane and batch (0: BP_U; tuned among 3, 4, 5, 6, 8)
     // scratch of the projector calls (svr_project / svr_backproject), max(Nt, M) floats kept
     // between calls: a call takes it when it is idle and its last use was on the call's stream
     // or has completed (proj_done), else allocates its own

@@ -270,19 +270,20 @@ __device__ inline double row_rest(const IT *__restrict__ idx, const WT *__restri
 
 // ---- forward rows ----------------------------------------------------------------
 // (A f)_r: the lanes of a wavefront stride over row r's non-zeros in batches
-// of 64 * FWD_U, FP64 products; lane j adds entries beg + j, beg + j + 64, ...
-// in that order.  The per-subset passes, whose rows fit in the wavefronts the
-// device holds at once, run one row per wavefront: their time is one
-// wavefront's latency chain, which a pair per wavefront lengthens.
-template <typename WT, typename IT>
+// of 64 * U (U = FWD_U unless tuned), FP64 products; lane j adds entries
+// beg + j, beg + j + 64, ... in that order whatever U.  The per-subset passes,
+// whose rows fit in the wavefronts the device holds at once, run one row per
+// wavefront: their time is one wavefront's latency chain, which a pair per
+// wavefront lengthens.
+template <int U = FWD_U, typename WT, typename IT>
 __device__ inline double row_dot(const int *__restrict__ row_ptr, const IT *__restrict__ col,
                                  const WT *__restrict__ val, const float *__restrict__ f, int r, int lane) {
     r = __builtin_amdgcn_readfirstlane(r);  // one row per wavefront: scalar row bounds
     const int beg = row_ptr[r], end = row_ptr[r + 1];
     double acc = 0.0;
-    for (int bb = beg; bb < end; bb += 64 * FWD_U) {
-        RowBatch<64, FWD_U, WT, IT> b;
-        float xv[FWD_U];
+    for (int bb = beg; bb < end; bb += 64 * U) {
+        RowBatch<64, U, WT, IT> b;
+        float xv[U];
         b.load_wave(col, val, bb, end, lane);
         b.gather(f, xv);
         acc = b.fma(xv, acc);
@@ -356,13 +357,13 @@ __device__ inline float lik_ratio(float g, float w, double yb, double eps) {
 
 // Forward row r with the ratio written to ratio[r]; every lane of the
 // wavefront calls it with the same r.
-template <typename WT, typename IT>
+template <int U = FWD_U, typename WT, typename IT>
 __device__ inline void fwd_ratio_row(const int *__restrict__ row_ptr, const IT *__restrict__ col,
                                      const WT *__restrict__ val, const float *__restrict__ f,
                                      const float *__restrict__ g, const float *__restrict__ w,
                                      float *__restrict__ ratio, int r, int lane, double eps) {
     const float gv = g[r], wv = w[r];
-    double acc = row_dot(row_ptr, col, val, f, r, lane);
+    double acc = row_dot<U>(row_ptr, col, val, f, r, lane);
     acc = wave_sum(acc);
     if (lane == 0) ratio[r] = lik_ratio(gv, wv, acc + (double)wv, eps);
 }
@@ -415,15 +416,17 @@ __device__ inline double bp_range(const IT *__restrict__ rowT, const WT *__restr
 // The same sum with `mid()` run once per lane while the lane's first
 // index/weight batch is in flight (after the loop for a lane with no entries):
 // work that does not depend on the sum, such as the penalty's stencil sums,
-// then takes none of the gather's latency.
-template <typename WT, typename IT, class Mid>
+// then takes none of the gather's latency.  U entries per lane and batch
+// (BP_U unless tuned); lane lig adds entries beg + lig, beg + lig + BP_G, ...
+// in that order whatever U.
+template <int U = BP_U, typename WT, typename IT, class Mid>
 __device__ inline double bp_range_mid(const IT *__restrict__ rowT, const WT *__restrict__ valT, int beg, int end,
                                       const float *__restrict__ y, int lig, Mid mid) {
     double acc = 0.0;
     bool done = false;
-    for (int base = beg + lig; base < end; base += BP_G * BP_U) {
-        RowBatch<BP_G, BP_U, WT, IT> b;
-        float xv[BP_U];
+    for (int base = beg + lig; base < end; base += BP_G * U) {
+        RowBatch<BP_G, U, WT, IT> b;
+        float xv[U];
         b.load(rowT, valT, base, end);
         if (!done) {
             mid();

@@ -43,8 +43,8 @@ __device__ inline double precond_of(const UpdateArgs &u, int64_t q, int n, float
 }
 
 // One pixel's fused back-projection and update; the BP_G lanes of the
-// pixel's group call it together.
-template <int KIND, typename WT, typename IT>
+// pixel's group call it together; U index/weight loads per lane and batch.
+template <int KIND, typename WT, typename IT, int U = BP_U>
 __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__restrict__ rowT,
                                     const WT *__restrict__ valT, const float *__restrict__ sens_t,
                                     const double *__restrict__ sens, int N, const UpdateArgs &u, int n, int lig) {
@@ -75,7 +75,7 @@ __device__ inline void update_pixel(const int *__restrict__ ptrT, const IT *__re
     // the stencil sums need only f and its neighbours: they run while the
     // first index/weight batch of the gather is in flight
     double D = 0.0, E = 0.0, gr = 0.0;
-    const double b = bp_range_mid(rowT, valT, beg, end, u.ratio, lig, [&] {
+    const double b = bp_range_mid<U>(rowT, valT, beg, end, u.ratio, lig, [&] {
         if (p.beta > 0.0) {
             if (EM) surrogate_nb((double)f, nb, p, D, E);
             else if (KIND != UPD_OSEM) gr = penalty_grad_nb((double)f, nb, p);

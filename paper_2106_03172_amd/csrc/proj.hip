@@ -63,7 +63,7 @@ __device__ inline int band_row(int b, int wv, int r0, int r1, int B, int Vt) {
 // part[r - r0] (summed afterwards in a fixed order).  Without PAIR the row
 // comes from band_row (B, Vt); a row's arithmetic does not depend on which
 // wavefront takes it.
-template <int MODE, bool PAIR, typename WT, typename IT>
+template <int MODE, bool PAIR, typename WT, typename IT, int U = FWD_U>
 __global__ void __launch_bounds__(FWD_THREADS)
 k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT *__restrict__ val,
           const int *__restrict__ row_sino, int r0, int r1, int B, int Vt, FwdArgs a) {
@@ -73,10 +73,10 @@ k_forward(const int *__restrict__ row_ptr, const IT *__restrict__ col, const WT 
     if (r < 0 || r >= r1) return;  // wave-uniform
     if constexpr (!PAIR) {
         if (MODE == 1) {
-            fwd_ratio_row(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane, a.eps);
+            fwd_ratio_row<U>(row_ptr, col, val, a.f, a.g, a.w, a.out, r, lane, a.eps);
             return;
         }
-        const double acc = wave_sum(row_dot(row_ptr, col, val, a.f, r, lane));
+        const double acc = wave_sum(row_dot<U>(row_ptr, col, val, a.f, r, lane));
         if (lane != 0) return;
         if (MODE == 0) a.out[row_sino[r]] = (float)acc;
         else a.part[r - r0] = loglik_term(a.g[r], a.w[r], acc + (double)a.w[r], a.eps, a.bad);
@@ -163,10 +163,19 @@ static int launch_forward_t(const Matrix &A, int r0, int r1, bool pair, int R, c
     return with_types(A, [&](auto w, auto i) {
         using WT = decltype(w);
         using IT = decltype(i);
-        if (!pair)
-            SVR_HIP(launch_k(k_forward<MODE, false, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
-                             (const WT *)A.d_val, A.d_row_sino, r0, r1, Bb, Vt, a));
-        else if (R == 1)
+        if (!pair) {  // the tuned loads per lane and batch (the width never changes a row's sum)
+            const IT *col = (const IT *)A.d_colt;
+            const WT *val = (const WT *)A.d_val;
+            if (A.sub_fwd_u == 4)
+                SVR_HIP(launch_k(k_forward<MODE, false, WT, IT, 4>, nb, FWD_THREADS, s, A.d_row_ptr, col, val,
+                                 A.d_row_sino, r0, r1, Bb, Vt, a));
+            else if (A.sub_fwd_u == 6)
+                SVR_HIP(launch_k(k_forward<MODE, false, WT, IT, 6>, nb, FWD_THREADS, s, A.d_row_ptr, col, val,
+                                 A.d_row_sino, r0, r1, Bb, Vt, a));
+            else
+                SVR_HIP(launch_k(k_forward<MODE, false, WT, IT, FWD_U>, nb, FWD_THREADS, s, A.d_row_ptr, col, val,
+                                 A.d_row_sino, r0, r1, Bb, Vt, a));
+        } else if (R == 1)
             SVR_HIP(launch_k(k_forward<MODE, true, WT, IT>, nb, FWD_THREADS, s, A.d_row_ptr, (const IT *)A.d_colt,
                              (const WT *)A.d_val, A.d_row_sino, r0, r1, 0, 0, a));
         else

@@ -34,27 +34,41 @@ namespace svr {
 // lines two neighbouring workgroups share, the stencil's neighbour rows and
 // the 4 x 8 tiles of the tiled write stay in one L2 (HBM counters: 1.17x ->
 // 1.03x of the algorithmic bytes)
-template <int KIND, typename WT, typename IT>
+template <int KIND, typename WT, typename IT, int U>
 __global__ void __launch_bounds__(BP_THREADS)
 k_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
          const float *__restrict__ sens_t, const double *__restrict__ sens, int N, int per, UpdateArgs u) {
     const int gid = xcd_chunk(blockIdx.x, per) * BP_THREADS + threadIdx.x;
     const int n = gid / BP_G, lig = gid % BP_G;
     if (n >= N) return;
-    update_pixel<KIND, WT, IT>(ptrT, rowT, valT, sens_t, sens, N, u, n, lig);
+    update_pixel<KIND, WT, IT, U>(ptrT, rowT, valT, sens_t, sens, N, u, n, lig);
 }
 
-template <int KIND>
-static int launch_update_k(const Matrix &A, const UpdateArgs &u, hipStream_t s) {
+// the update with U index/weight loads per lane and batch (the tuned width,
+// else BP_U); the width changes neither the entries a lane adds nor their
+// order, so the result is bitwise the same for every U
+template <int KIND, int U>
+static int launch_update_u(const Matrix &A, const UpdateArgs &u, hipStream_t s) {
     int per = 0;
     const int nb = xcd_grid(((int64_t)A.N * BP_G + BP_THREADS - 1) / BP_THREADS, per);
     return with_types(A, [&](auto w, auto i) {
         using WT = decltype(w);
         using IT = decltype(i);
-        SVR_HIP(launch_k(k_update<KIND, WT, IT>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+        SVR_HIP(launch_k(k_update<KIND, WT, IT, U>, nb, BP_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
                          (const WT *)A.d_valT, A.d_sens_t, A.d_sens, A.N, per, u));
         return SVR_OK;
     });
+}
+
+template <int KIND>
+static int launch_update_k(const Matrix &A, const UpdateArgs &u, hipStream_t s) {
+    switch (A.sub_bp_u) {
+        case 3: return launch_update_u<KIND, 3>(A, u, s);
+        case 4: return launch_update_u<KIND, 4>(A, u, s);
+        case 6: return launch_update_u<KIND, 6>(A, u, s);
+        case 8: return launch_update_u<KIND, 8>(A, u, s);
+        default: return launch_update_u<KIND, BP_U>(A, u, s);
+    }
 }
 
 int launch_update(const Matrix &A, int kind, const UpdateArgs &u, hipStream_t s) {

@@ -22,7 +22,9 @@ pytestmark = pytest.mark.gpu
 
 import paper_2106_03172_amd as pkg  # noqa: E402
 
-TUNINGS = [(1, 1), (2, 3), (7, 5), (13, 16), (31, 1024), (0, 0)]
+# (row pairs per wavefront, rows per lane group, per-subset forward batch,
+# per-subset update batch)
+TUNINGS = [(1, 1, 4, 3), (2, 3, 6, 4), (7, 5, 8, 6), (13, 16, 0, 8), (31, 1024, 4, 5), (0, 0, 0, 0)]
 
 
 def rel(a, b):
@@ -62,11 +64,12 @@ def test_results_are_bitwise_independent_of_tuning(shape):
     f0 = np.ones(A.N, np.float32)
     order = datagen.make_order(P.n_subsets, 2 * P.n_subsets, seed=9)
     ref = None
-    for fw, bp in TUNINGS:
-        A.set_tuning(fw, bp)
+    for fw, bp, fu, bu in TUNINGS:
+        A.set_tuning(fw, bp, subset_fwd_batch=fu, subset_bp_batch=bu)
         eff = A.tuning()
         assert eff[0] == (fw or eff[0]) and eff[1] == (bp or eff[1])
-        print("tuning", (fw, bp), "effective", eff, flush=True)
+        assert A.batch_widths() == (fu or 8, bu or 5)
+        print("tuning", (fw, bp, fu, bu), "effective", eff, flush=True)
         got = run_all(P, A, x, y, f0, order)
         if ref is None:
             ref = got
@@ -74,7 +77,8 @@ def test_results_are_bitwise_independent_of_tuning(shape):
         for k in ref:
             assert np.array_equal(np.asarray(got[k]), np.asarray(ref[k])), (k, fw, bp)
     tuned = A.tune()
-    print("tuned", tuned, flush=True)
+    print("tuned", tuned, A.batch_widths(), flush=True)
+    assert A.batch_widths()[0] in (4, 6, 8) and A.batch_widths()[1] in (3, 4, 5, 6, 8)
     assert 1 <= tuned[0] <= 31 and 1 <= tuned[1] <= 1024 and tuned[2] > 0 and tuned[3] > 0
     assert A.tuning() == tuned[:2]
     got = run_all(P, A, x, y, f0, order)
@@ -95,6 +99,9 @@ def test_tuning_rejects_out_of_range():
     for bad in ((-1, 0), (32, 0), (0, -1), (0, 1025)):
         with pytest.raises(pkg.SvrError):
             A.set_tuning(*bad)
+    for fu, bu in ((5, 0), (2, 0), (0, 7), (0, 2)):
+        with pytest.raises(pkg.SvrError):
+            A.set_tuning(0, 0, subset_fwd_batch=fu, subset_bp_batch=bu)
     A.set_tuning(31, 1024)
     assert A.tuning() == (31, 1024)
     A.set_tuning(0, 0)
@@ -142,19 +149,21 @@ def test_tuning_cache(tmp_path, monkeypatch):
     A = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32)
     t1 = A.tune()
     lines = path.read_text().splitlines()
-    assert len(lines) == 1 and lines[0].startswith("svr-tune 1 96x96/"), lines
+    assert len(lines) == 1 and lines[0].startswith("svr-tune 2 96x96/"), lines
     B = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32)
     fw = 3 if t1[0] != 3 else 4
-    B.set_tuning(fw, 7)
+    B.set_tuning(fw, 7, subset_fwd_batch=4 if A.batch_widths()[0] != 4 else 6, subset_bp_batch=3)
     t2 = B.tune()
-    assert t2[:2] == t1[:2] and B.tuning() == t1[:2]
+    assert t2[:2] == t1[:2] and B.tuning() == t1[:2] and B.batch_widths() == A.batch_widths()
     assert abs(t2[2] - t1[2]) < 1e-3 and abs(t2[3] - t1[3]) < 1e-3
     assert len(path.read_text().splitlines()) == 1
     Q = datagen.make_problem(64, 64, 2.0, 40, 91, 2.0, 5, 1e5, attenuation=False, seed=22)
     C = pkg.SystemMatrix(Q.geom, Q.n_subsets, pkg.SVR_W_F32)
     C.tune()
     assert len(path.read_text().splitlines()) == 2
-    path.write_text("not a tuning line\nsvr-tune 1 " + lines[0].split()[2] + " fwd 99 bp 1 fwd_us 1 bp_us 1\n"
+    path.write_text("not a tuning line\nsvr-tune 2 " + lines[0].split()[2] + " fwd 99 bp 1 fu 8 bu 5 fwd_us 1 bp_us 1\n"
+                    + "svr-tune 1 " + lines[0].split()[2] + " fwd 5 bp 2 fwd_us 1 bp_us 1\n"
                     + "\n".join(path.read_text().splitlines()) + "\n")
     D = pkg.SystemMatrix(P.geom, P.n_subsets, pkg.SVR_W_F32)
-    assert D.tune()[:2] == t1[:2]   # the out-of-range line is skipped, the valid one used
+    assert D.tune()[:2] == t1[:2]   # the out-of-range and the old-format lines are skipped, the valid one used
+    assert D.batch_widths() == A.batch_widths()
