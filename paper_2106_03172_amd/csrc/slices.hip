@@ -117,6 +117,7 @@ __device__ inline void ms_dot(const IT *__restrict__ idx, const WT *__restrict__
 // ---- penalty with in-plane and optional axial neighbours ---------------------
 // (all neighbour values loaded first, absent ones clamped in bounds and
 // skipped, so the sums are those of the in-plane order then down, up)
+template <int POT>
 __device__ inline void surrogate_at_ms(const float *X, int n, int s, int S, const PenaltyArgs &p, int axial,
                                        double &D, double &E) {
     const int iy = n / p.nx, ix = n - iy * p.nx;
@@ -127,7 +128,7 @@ __device__ inline void surrogate_at_ms(const float *X, int n, int s, int S, cons
     D = 0.0;
     E = 0.0;
     auto add = [&](double fj, double w) {
-        const double d = w * pot_gamma(p.potential, fn - fj, p.delta);
+        const double d = w * pot_gamma(POT, fn - fj, p.delta);
         D = D + d;
         E = E + d * fj;
     };
@@ -299,7 +300,7 @@ __global__ void k_seg_fill(const int *__restrict__ row_ptr, const IT *__restrict
 
 // ---- fused back-projection + OSEM / SVREM update -----------------------------
 // task p of XCD x: pixel region_pixel(x, p / ng), slice group p mod ng
-template <int KIND, int NC, typename WT, typename IT>
+template <int KIND, int NC, typename WT, typename IT, int POT>
 __global__ void __launch_bounds__(MS_THREADS)
 k_ms_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT *__restrict__ valT,
             const float *__restrict__ sens_t, const double *__restrict__ sens, int N, int S, int ng, int axial,
@@ -331,7 +332,7 @@ k_ms_update(const int *__restrict__ ptrT, const IT *__restrict__ rowT, const WT 
                 sh0[c] = u.s_hat[i];
                 tab[c] = u.table[q * S + s];
                 sanc[c] = u.s_anc[i];
-                if (p.beta > 0.0) surrogate_at_ms(u.f, n, s, S, p, axial, D[c], E[c]);
+                if (p.beta > 0.0) surrogate_at_ms<POT>(u.f, n, s, S, p, axial, D[c], E[c]);
             }
         }
     }
@@ -605,16 +606,29 @@ int ms_forward(const Matrix &A, const StackPlan &plan, int t, int mode, int S, c
     return SVR_OK;
 }
 
-template <int KIND, int NC>
-static int ms_update_t(const Matrix &A, const StackPlan &plan, int S, int ng, int axial, const UpdateArgs &u,
+// the potential is a template argument, as in the single-slice stencil, so
+// each neighbour's curvature is the potential's own expression
+template <int KIND, int NC, int POT>
+static int ms_update_p(const Matrix &A, const StackPlan &plan, int S, int ng, int axial, const UpdateArgs &u,
                        unsigned nb, hipStream_t s) {
     return with_types(A, [&](auto wv, auto iv) {
         using WT = decltype(wv);
         using IT = decltype(iv);
-        SVR_HIP(launch_k(k_ms_update<KIND, NC, WT, IT>, nb, MS_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
+        SVR_HIP(launch_k(k_ms_update<KIND, NC, WT, IT, POT>, nb, MS_THREADS, s, A.d_ptrT, (const IT *)A.d_rowT,
                          (const WT *)A.d_valT, A.d_sens_t, A.d_sens, A.N, S, ng, axial, plan.reg, u));
         return SVR_OK;
     });
+}
+
+template <int KIND, int NC>
+static int ms_update_t(const Matrix &A, const StackPlan &plan, int S, int ng, int axial, const UpdateArgs &u,
+                       unsigned nb, hipStream_t s) {
+    switch (u.pen.potential) {
+        case SVR_PEN_HUBER: return ms_update_p<KIND, NC, SVR_PEN_HUBER>(A, plan, S, ng, axial, u, nb, s);
+        case SVR_PEN_LOGCOSH: return ms_update_p<KIND, NC, SVR_PEN_LOGCOSH>(A, plan, S, ng, axial, u, nb, s);
+        case SVR_PEN_HYPERBOLA: return ms_update_p<KIND, NC, SVR_PEN_HYPERBOLA>(A, plan, S, ng, axial, u, nb, s);
+        default: return ms_update_p<KIND, NC, SVR_PEN_QUADRATIC>(A, plan, S, ng, axial, u, nb, s);
+    }
 }
 
 int ms_update(const Matrix &A, const StackPlan &plan, int kind, int S, int axial, const UpdateArgs &u, hipStream_t s) {
