@@ -422,6 +422,10 @@ typedef struct {
     int64_t admitted;          /* requests admitted so far */
     int64_t completed;         /* requests finished so far: done, failed or cancelled */
     int64_t epochs;            /* SVREM epochs run so far, over all requests */
+    int64_t cached_bytes;      /* device blocks of finished requests kept for later admissions
+                                  (used_bytes + cached_bytes stays within the budget; freed by
+                                  svr_serve_destroy or when an admission needs the room) */
+    int64_t block_reuses;      /* allocations served from those kept blocks so far */
 } svr_serve_stats_t;
 /* Errors: SVR_EINVAL (NULL argument). */
 int  svr_serve_stats(const svr_server *S, svr_serve_stats_t *out);

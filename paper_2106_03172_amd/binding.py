@@ -86,7 +86,8 @@ class svr_serve_request(C.Structure):
 class svr_serve_stats_t(C.Structure):
     _fields_ = [("queued", C.c_int32), ("resident", C.c_int32), ("max_slots", C.c_int32),
                 ("done_unpolled", C.c_int32), ("used_bytes", C.c_int64), ("mem_budget_bytes", C.c_int64),
-                ("ticks", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("epochs", C.c_int64)]
+                ("ticks", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("epochs", C.c_int64),
+                ("cached_bytes", C.c_int64), ("block_reuses", C.c_int64)]
 
 
 class svr_serve_result(C.Structure):

@@ -619,6 +619,7 @@ int svr_sensitivity(const svr_matrix *A, int32_t subset, double *out_dev, void *
 
 void svr_matrix_destroy(svr_matrix *A) {
     if (!A) return;
+    TraceRange tr("svr.matrix_destroy");
     (void)hipSetDevice(A->device);
     if (A->proj_scratch) {  // the last projector call that used it has finished with it
         (void)hipEventSynchronize(A->proj_done);
@@ -1114,6 +1115,7 @@ int svr_recon_kernel_times(svr_recon *R, svr_kernel_times_t *out) {
 
 void svr_recon_destroy(svr_recon *R) {
     if (!R) return;
+    TraceRange tr("svr.recon_destroy");
     (void)hipSetDevice(R->device);
     free_recon(R);
 }

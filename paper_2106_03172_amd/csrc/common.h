@@ -4,8 +4,10 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <mutex>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "../../include/svr.h"
@@ -48,6 +50,29 @@ struct AllocStream {
 };
 hipError_t dmalloc(void **p, size_t bytes);
 void dfree(void *p);
+
+// Device blocks that a long-lived owner keeps for reuse instead of freeing them.  While a
+// BlockCacheScope is active on the calling thread, dmalloc first takes an idle block of at least
+// the size asked for and at most 5/4 of it, and records what it allocates; dfree of a recorded
+// block keeps it idle when the scope was opened with keep = true (for objects whose work has
+// completed on every stream), else frees it as usual.  Once more of the runtime's stream-ordered
+// pool is free than in use, the runtime hands large blocks back to the driver as they are freed,
+// at several ms a block with every host thread's calls held up; blocks kept here stay in use as
+// far as the pool is concerned.
+struct BlockCache {
+    std::unordered_map<void *, size_t> out;  // blocks handed out while a scope was active
+    std::multimap<size_t, void *> idle;      // blocks kept, by size
+    int64_t idle_bytes = 0;
+    int64_t reuses = 0;
+};
+struct BlockCacheScope {
+    BlockCache *prev_cache;
+    bool prev_keep;
+    BlockCacheScope(BlockCache *c, bool keep);
+    ~BlockCacheScope();
+};
+// frees idle blocks, largest first, until at most max_idle bytes stay idle
+void block_cache_trim(BlockCache &c, int64_t max_idle);
 template <typename T>
 inline hipError_t dalloc(T **p, size_t count) {
     return dmalloc(reinterpret_cast<void **>(p), count * sizeof(T));

@@ -96,13 +96,20 @@ struct svr_server {
     int64_t used_bytes = 0;
     int device = 0;
     int64_t ticks = 0, admitted = 0, completed = 0, epochs = 0;  // running totals (svr_serve_stats)
+    // the device blocks of finished requests, kept for the requests admitted later (within the
+    // memory budget together with used_bytes)
+    svr::BlockCache cache;
 };
 
 using namespace svr;
 
 namespace {
 
-void release(svr_server *S, Request *q) {
+// Frees q's device objects.  keep: every stream has finished with them, and their blocks stay
+// in the server's cache; else they are freed, stream-ordered on q's stream.
+void release(svr_server *S, Request *q, bool keep) {
+    TraceRange tr("svr.serve.release");
+    BlockCacheScope sc(&S->cache, keep);
     if (q->R) svr_recon_destroy(q->R);
     if (q->A) svr_matrix_destroy(q->A);
     AllocStream as(S->streams[q->stream]);
@@ -123,7 +130,9 @@ __global__ void k_fill(float *x, int64_t n, float v) {
 
 // builds the request's matrix and recon and runs the OSEM initialisation epoch
 int admit(svr_server *S, Request *q, hipStream_t s) {
+    TraceRange tr("svr.serve.admit");
     AllocStream as(s);
+    BlockCacheScope sc(&S->cache, false);
     const svr_serve_request &r = q->req;
     const int64_t M = (int64_t)r.geom.n_views * r.geom.n_bins;
     const int64_t N = (int64_t)r.geom.nx * r.geom.ny;
@@ -162,6 +171,7 @@ int admit(svr_server *S, Request *q, hipStream_t s) {
 // with the same weight and index types (up to BATCH_MAX a launch), all on
 // the first stream.
 void batched_epoch(svr_server *S) {
+    TraceRange tr("svr.serve.batched_epoch");
     hipStream_t s0 = S->streams[0];
     struct Res {
         Request *q;
@@ -222,6 +232,7 @@ void batched_epoch(svr_server *S) {
 }
 
 int finish(svr_server *S, Request *q, hipStream_t s) {
+    TraceRange tr("svr.serve.finish");
     const int64_t N = (int64_t)q->req.geom.nx * q->req.geom.ny;
     double phi = 0.0;
     int rc = svr_objective(q->R, &phi, s);
@@ -240,8 +251,15 @@ int finish(svr_server *S, Request *q, hipStream_t s) {
     }
     q->state = DONE;
     q->t_done = clk::now();
-    release(S, q);
+    release(S, q, true);  // every stream was synchronised before the request finished
     return SVR_OK;
+}
+
+// Keeps the cache within what the budget leaves beside the resident requests.
+void trim_cache(svr_server *S, int64_t room) {
+    if (S->cache.idle_bytes <= room) return;
+    AllocStream as(S->streams[0]);
+    block_cache_trim(S->cache, std::max<int64_t>(room, 0));
 }
 
 }  // namespace
@@ -339,7 +357,9 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
         // OSEM epoch then overlap the resident requests' epochs on the other streams
         while (!S->queue.empty() && (int)S->resident.size() < S->cfg.max_slots) {
             Request *q = S->reqs[S->queue.front()].get();
-            if (S->used_bytes + q->est_bytes > S->cfg.mem_budget_bytes) break;
+            const int64_t room = S->cfg.mem_budget_bytes - S->used_bytes - q->est_bytes;
+            if (room < 0) break;
+            trim_cache(S, room);
             S->queue.pop_front();
             q->stream = (int)(q->ticket % S->streams.size());
             int rc = admit(S, q, S->streams[q->stream]);
@@ -348,14 +368,18 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
                 q->status = rc;
                 q->state = DONE;
                 q->t_admit = q->t_done = clk::now();
-                release(S, q);
+                release(S, q, false);  // work of the failed admission may still be in flight
                 ++S->completed;
                 continue;
             }
             S->resident.push_back(q->ticket);
         }
+        trim_cache(S, S->cfg.mem_budget_bytes - S->used_bytes);  // matrices larger than estimated
         if (S->resident.empty()) return SVR_OK;
-        for (hipStream_t st : S->streams) SVR_HIP(hipStreamSynchronize(st));
+        {
+            TraceRange ts("svr.serve.sync");
+            for (hipStream_t st : S->streams) SVR_HIP(hipStreamSynchronize(st));
+        }
         std::vector<uint64_t> still;
         for (size_t i = 0; i < S->resident.size(); ++i) {
             const uint64_t tk = S->resident[i];
@@ -370,6 +394,7 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
             }
         }
         S->resident.swap(still);
+        trim_cache(S, S->cfg.mem_budget_bytes - S->used_bytes);
         if (max_ticks <= 0 && S->resident.empty() && S->queue.empty()) return SVR_OK;
     }
     return SVR_OK;
@@ -409,8 +434,8 @@ int svr_serve_cancel(svr_server *S, uint64_t ticket) {
             if (*i == ticket) { S->queue.erase(i); break; }
         q->t_admit = clk::now();
     } else {
-        (void)hipStreamSynchronize(S->streams[q->stream]);
-        release(S, q);
+        for (hipStream_t st : S->streams) (void)hipStreamSynchronize(st);
+        release(S, q, true);
         for (auto i = S->resident.begin(); i != S->resident.end(); ++i)
             if (*i == ticket) { S->resident.erase(i); break; }
     }
@@ -431,6 +456,8 @@ int svr_serve_stats(const svr_server *S, svr_serve_stats_t *out) {
     out->max_slots = S->cfg.max_slots;
     out->done_unpolled = done;
     out->used_bytes = S->used_bytes;
+    out->cached_bytes = S->cache.idle_bytes;
+    out->block_reuses = S->cache.reuses;
     out->mem_budget_bytes = S->cfg.mem_budget_bytes;
     out->ticks = S->ticks;
     out->admitted = S->admitted;
@@ -443,7 +470,11 @@ void svr_serve_destroy(svr_server *S) {
     if (!S) return;
     (void)hipSetDevice(S->device);
     for (hipStream_t st : S->streams) (void)hipStreamSynchronize(st);
-    for (auto &kv : S->reqs) release(S, kv.second.get());
+    for (auto &kv : S->reqs) release(S, kv.second.get(), true);
+    if (!S->streams.empty()) {
+        trim_cache(S, 0);
+        (void)hipStreamSynchronize(S->streams[0]);
+    }
     for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
     delete S;
 }

@@ -34,9 +34,29 @@ LaunchEvents &pending_timing() {
 
 static long g_alloc_budget = -2;  // -2: not read yet, -1: unlimited
 static thread_local hipStream_t g_alloc_stream = nullptr;
+static thread_local BlockCache *g_cache = nullptr;
+static thread_local bool g_cache_keep = false;
 
 AllocStream::AllocStream(hipStream_t s) : prev(g_alloc_stream) { g_alloc_stream = s; }
 AllocStream::~AllocStream() { g_alloc_stream = prev; }
+
+BlockCacheScope::BlockCacheScope(BlockCache *c, bool keep) : prev_cache(g_cache), prev_keep(g_cache_keep) {
+    g_cache = c;
+    g_cache_keep = keep;
+}
+BlockCacheScope::~BlockCacheScope() {
+    g_cache = prev_cache;
+    g_cache_keep = prev_keep;
+}
+
+void block_cache_trim(BlockCache &c, int64_t max_idle) {
+    while (c.idle_bytes > max_idle && !c.idle.empty()) {
+        auto it = std::prev(c.idle.end());
+        (void)hipFreeAsync(it->second, g_alloc_stream);
+        c.idle_bytes -= (int64_t)it->first;
+        c.idle.erase(it);
+    }
+}
 
 // keep freed blocks in the device's default pool instead of returning them
 // to the driver at every synchronisation
@@ -63,12 +83,39 @@ hipError_t dmalloc(void **p, size_t bytes) {
     }
     if (g_alloc_budget > 0) --g_alloc_budget;
     if (bytes == 0) bytes = 16;
+    BlockCache *c = g_cache;
+    if (c) {
+        auto it = c->idle.lower_bound(bytes);
+        if (it != c->idle.end() && it->first <= bytes + bytes / 4) {
+            *p = it->second;
+            c->out.emplace(it->second, it->first);
+            c->idle_bytes -= (int64_t)it->first;
+            c->idle.erase(it);
+            ++c->reuses;
+            return hipSuccess;
+        }
+    }
     keep_pool_memory();
-    return hipMallocAsync(p, bytes, g_alloc_stream);
+    const hipError_t e = hipMallocAsync(p, bytes, g_alloc_stream);
+    if (c && e == hipSuccess) c->out.emplace(*p, bytes);
+    return e;
 }
 
 void dfree(void *p) {
-    if (p) (void)hipFreeAsync(p, g_alloc_stream);
+    if (!p) return;
+    if (BlockCache *c = g_cache) {
+        auto it = c->out.find(p);
+        if (it != c->out.end()) {
+            if (g_cache_keep) {
+                c->idle.emplace(it->second, p);
+                c->idle_bytes += (int64_t)it->second;
+                c->out.erase(it);
+                return;
+            }
+            c->out.erase(it);
+        }
+    }
+    (void)hipFreeAsync(p, g_alloc_stream);
 }
 
 // ---------------------------------------------------------------------------

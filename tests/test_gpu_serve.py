@@ -194,3 +194,63 @@ def test_server_stats_track_queue_slots_memory_and_totals(batch):
     assert S.poll(tickets[3])["status"] == pkg.binding.SVR_ECANCELLED
     assert S.stats()["done_unpolled"] == 0
     S.close()
+
+
+@pytest.mark.parametrize("batch", [True, False])
+def test_kept_blocks_are_reused_and_results_do_not_change(batch):
+    """The device blocks of finished requests stay in the server's cache and
+    serve later admissions: a second round of the same requests on the same
+    server (in a different order, so blocks land in other roles) reuses them,
+    holds no more than the budget, and every image and objective is bitwise
+    the first round's (nothing depends on what a reused block held)."""
+    probs = [_req(s) for s in SPECS]
+    budget = 1 << 31
+    S = pkg.Server(budget, max_slots=4, n_streams=2, batch=batch)
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+
+    def round_(order):
+        t = {i: S.submit(probs[i].geom, probs[i].n_subsets, probs[i].g, probs[i].w, prm, EPOCHS, 300 + i)
+             for i in order}
+        S.step(0)
+        return {i: S.poll(t[i]) for i in order}
+
+    first = round_([0, 1, 2, 3])
+    st = S.stats()
+    assert st["used_bytes"] == 0 and st["cached_bytes"] > 0 and st["block_reuses"] == 0
+    assert st["cached_bytes"] <= budget
+    second = round_([3, 1, 0, 2])
+    st = S.stats()
+    assert st["block_reuses"] > 0 and st["used_bytes"] == 0 and st["cached_bytes"] <= budget
+    for i in range(4):
+        assert first[i]["status"] == 0 and second[i]["status"] == 0
+        np.testing.assert_array_equal(first[i]["f"], second[i]["f"])
+        assert first[i]["phi"] == second[i]["phi"]
+    S.close()
+
+
+def test_cache_yields_to_the_budget():
+    """Kept blocks count against the budget: with room for about one request,
+    each admission first frees kept blocks, so used_bytes + cached_bytes stays
+    within the budget after every tick, and every request finishes."""
+    probs = [_req(SPECS[1]), _req(SPECS[3])]
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+    held = []
+    for k, P in enumerate(probs):  # what each request leaves in the cache when run alone
+        S = pkg.Server(1 << 31, max_slots=1, n_streams=1)
+        t = S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS, 1 + k)
+        S.step(0)
+        assert S.poll(t)["status"] == 0
+        held.append(S.stats()["cached_bytes"])
+        S.close()
+    budget = 3 * max(held)  # the admission estimate runs at about twice what a small request holds
+    S = pkg.Server(budget, max_slots=1, n_streams=1)
+    ts = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS, 5 + i) for i, P in enumerate(probs * 2)]
+    peak = 0
+    while S.stats()["completed"] < len(ts):
+        S.step(1)
+        st = S.stats()
+        assert st["used_bytes"] + st["cached_bytes"] <= budget
+        peak = max(peak, st["cached_bytes"])
+    assert peak > 0
+    assert all(S.poll(t)["status"] == 0 for t in ts)
+    S.close()
