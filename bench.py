@@ -767,7 +767,7 @@ def serve_latency(specs, data, alpha):
     def run(arrivals):
         S = pkg.Server(64 << 30, max_slots=16, n_streams=8)
         order = np.argsort(arrivals)
-        done, tickets = {}, {}
+        done, owner = {}, {}  # owner: pending ticket -> request index
         nxt = 0
         t0 = time.perf_counter()
         while len(done) < n:
@@ -775,17 +775,16 @@ def serve_latency(specs, data, alpha):
             while nxt < n and arrivals[order[nxt]] <= now:
                 i = int(order[nxt])
                 P = data[i]
-                tickets[i] = S.submit(P.geom, P.n_subsets, P.g, P.w, prm, specs[i]["epochs"], 1000 + i)
+                owner[S.submit(P.geom, P.n_subsets, P.g, P.w, prm, specs[i]["epochs"], 1000 + i)] = i
                 nxt += 1
-            if tickets:
+            if owner:
                 S.step(1)
             elif nxt < n:
                 time.sleep(max(0.0, arrivals[order[nxt]] - (time.perf_counter() - t0)))
-            for i in list(tickets):
-                res = S.poll(tickets[i])
-                if res is not None:
-                    done[i] = (time.perf_counter() - t0 - arrivals[i], res)
-                    del tickets[i]
+            for t in S.done():
+                i = owner.pop(t)
+                res = S.poll(t)
+                done[i] = (time.perf_counter() - t0 - arrivals[i], res)
         total = time.perf_counter() - t0
         S.close()
         return done, total
@@ -846,13 +845,11 @@ def serve_compare(specs, data, alpha):
         tickets = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, epochs[i], 1000 + i, wtype=wtype)
                    for i, P in enumerate(data)]
         res = {}
+        index = {t: i for i, t in enumerate(tickets)}
         while len(res) < n:
             S.step(1)
-            for i, t in enumerate(tickets):
-                if i not in res:
-                    r = S.poll(t)
-                    if r is not None:
-                        res[i] = r
+            for t in S.done():
+                res[index[t]] = S.poll(t)
         total = time.perf_counter() - t0
         S.close()
         assert all(res[i]["status"] == 0 for i in range(n))

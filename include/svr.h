@@ -402,9 +402,15 @@ int  svr_serve_submit(svr_server *S, const svr_serve_request *req, uint64_t *tic
 /* Runs scheduler ticks for up to max_ticks (0 = until every admitted request
  * has finished) and admits queued requests as memory frees up. */
 int  svr_serve_step(svr_server *S, int32_t max_ticks);
-/* SVR_PENDING until the request is done; then fills *res (f_host must point
- * to N floats) and forgets the ticket. */
+/* SVR_PENDING until the request is done; then fills *res (f_host, if not NULL,
+ * must point to N floats: the final image, zeros for a request cancelled or
+ * failed before it had one) and forgets the ticket. */
 int  svr_serve_poll(svr_server *S, uint64_t ticket, svr_serve_result *res);
+/* Host-only: writes up to cap tickets of finished requests whose results are
+ * not yet polled (ascending ticket order) to tickets[] and their number to *n,
+ * so that a caller polls only those.  Errors: SVR_EINVAL (NULL S or n, cap < 0,
+ * NULL tickets with cap > 0). */
+int  svr_serve_done(const svr_server *S, uint64_t *tickets, int32_t cap, int32_t *n);
 int  svr_serve_cancel(svr_server *S, uint64_t ticket);
 void svr_serve_destroy(svr_server *S);
 

@@ -127,6 +127,7 @@ _SIGS = {
     "svr_serve_cancel": ([_VP, C.c_uint64], C.c_int),
     "svr_serve_destroy": ([_VP], None),
     "svr_serve_stats": ([_VP, C.POINTER(svr_serve_stats_t)], C.c_int),
+    "svr_serve_done": ([_VP, C.POINTER(C.c_uint64), _I32, C.POINTER(_I32)], C.c_int),
 }
 for _e in ("osem", "svrem", "svrg", "saga", "sga", "bsrem", "sem"):
     _SIGS[f"svr_{_e}_epoch"] = ([_VP, _VP, _I32, _VP], C.c_int)
@@ -489,7 +490,7 @@ class Server:
     def poll(self, ticket: int):
         """None while pending, else a dict with the image and timings."""
         n = self._keep.get(ticket, 1)  # unknown tickets are reported by the library
-        f = np.zeros(n, dtype=np.float32)
+        f = np.empty(n, dtype=np.float32)  # the library fills all n floats once the request is done
         res = svr_serve_result(f.ctypes.data_as(C.POINTER(C.c_float)), 0.0, 0.0, 0.0, 0)
         rc = lib().svr_serve_poll(self.h, C.c_uint64(ticket), C.byref(res))
         if rc == SVR_PENDING:
@@ -500,6 +501,13 @@ class Server:
 
     def cancel(self, ticket: int):
         _check(lib().svr_serve_cancel(self.h, C.c_uint64(ticket)))
+
+    def done(self, cap: int = 1024) -> list:
+        """Tickets of finished requests not yet polled (svr_serve_done), ascending."""
+        buf = (C.c_uint64 * cap)()
+        n = C.c_int32()
+        _check(lib().svr_serve_done(self.h, buf, int(cap), C.byref(n)))
+        return list(buf[:n.value])
 
     def stats(self) -> dict:
         """Queue depth, slots in use, device memory held and running totals (svr_serve_stats)."""

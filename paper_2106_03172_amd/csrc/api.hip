@@ -452,6 +452,51 @@ int run_anchor_plan(svr_recon *R, IterPlan &p, hipStream_t s) { return anchor_it
 
 void end_iteration(svr_recon *R) { advance_iteration(R, R->p.algo); }
 
+int objective_enqueue(svr_recon *R, hipStream_t s, ObjectiveHost *out) {
+    const Matrix &A = *R->A;
+    SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
+    int nb = 0, nbp = 0, rc;
+    if (R->S == 1) {
+        FwdArgs fa{R->ft, R->g, R->w, nullptr, R->part, R->bad};
+        fa.eps = ll_eps_of(R);
+        rc = launch_forward(A, 0, A.M, 2, fa, s, &nb);
+    } else {
+        rc = ms_forward(A, R->plan, -1, 2, R->S, R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad, s, &nb);
+    }
+    if (!rc) rc = launch_reduce_sum(R->part, nb, R->scal, s);
+    if (!rc) {
+        if (R->S == 1)
+            rc = launch_penalty_value(A, R->f[R->cur], R->p.penalty, R->p.delta, R->part, &nbp, s);
+        else
+            rc = ms_penalty_value(A, R->S, R->f[R->cur], R->p.penalty, R->p.delta,
+                                  (R->p.flags & SVR_FLAG_AXIAL_PENALTY) ? 1 : 0, R->part, &nbp, s);
+    }
+    if (!rc) rc = launch_reduce_sum(R->part, nbp, R->scal + 1, s);
+    if (rc) return rc;
+    SVR_HIP(hipMemcpyAsync(out->sums, R->scal, sizeof(out->sums), hipMemcpyDeviceToHost, s));
+    SVR_HIP(hipMemcpyAsync(&out->bad, R->bad, sizeof(int), hipMemcpyDeviceToHost, s));
+    SVR_HIP(hipMemcpyAsync(&out->status, R->d_status, sizeof(int), hipMemcpyDeviceToHost, s));
+    return SVR_OK;
+}
+
+int objective_result(svr_recon *R, const ObjectiveHost &o, hipStream_t s, double *phi_host) {
+    if (o.status) {
+        (void)hipMemsetAsync(R->d_status, 0, sizeof(int), s);
+        set_error("a persistent epoch kernel aborted at a grid barrier (time-out); results are invalid");
+        return SVR_EDEVICE;
+    }
+    const double phi = o.bad ? -INFINITY : o.sums[0] - R->p.beta * o.sums[1];
+    *phi_host = phi;
+    if (!std::isfinite(phi)) {
+        R->numeric_error = true;
+        set_error("objective is not finite (%g)", phi);
+        return SVR_ENUMERIC;
+    }
+    return SVR_OK;
+}
+
+const float *current_image(const svr_recon *R) { return R->f[R->cur]; }
+
 }  // namespace svr
 
 // ===========================================================================
@@ -939,41 +984,11 @@ int svr_objective(svr_recon *R, double *phi_host, void *stream) {
     SVR_REQUIRE(R && phi_host, "NULL argument");
     SVR_HIP(hipSetDevice(R->device));
     hipStream_t s = (hipStream_t)stream;
-    const Matrix &A = *R->A;
-    SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));
-    int nb = 0, nbp = 0, rc;
-    if (R->S == 1) {
-        FwdArgs fa{R->ft, R->g, R->w, nullptr, R->part, R->bad};
-        fa.eps = ll_eps_of(R);
-        rc = launch_forward(A, 0, A.M, 2, fa, s, &nb);
-    } else {
-        rc = ms_forward(A, R->plan, -1, 2, R->S, R->f[R->cur], R->g, R->w, nullptr, R->part, R->bad, s, &nb);
-    }
-    if (!rc) rc = launch_reduce_sum(R->part, nb, R->scal, s);
-    if (!rc) {
-        if (R->S == 1)
-            rc = launch_penalty_value(A, R->f[R->cur], R->p.penalty, R->p.delta, R->part, &nbp, s);
-        else
-            rc = ms_penalty_value(A, R->S, R->f[R->cur], R->p.penalty, R->p.delta,
-                                  (R->p.flags & SVR_FLAG_AXIAL_PENALTY) ? 1 : 0, R->part, &nbp, s);
-    }
-    if (!rc) rc = launch_reduce_sum(R->part, nbp, R->scal + 1, s);
+    svr::ObjectiveHost o{};
+    const int rc = svr::objective_enqueue(R, s, &o);
     if (rc) return rc;
-    double h[2];
-    int bad = 0;
-    SVR_HIP(hipMemcpyAsync(h, R->scal, sizeof(h), hipMemcpyDeviceToHost, s));
-    SVR_HIP(hipMemcpyAsync(&bad, R->bad, sizeof(int), hipMemcpyDeviceToHost, s));
     SVR_HIP(hipStreamSynchronize(s));
-    rc = check_status(R, s);
-    if (rc) return rc;
-    const double phi = bad ? -INFINITY : h[0] - R->p.beta * h[1];
-    *phi_host = phi;
-    if (!std::isfinite(phi)) {
-        R->numeric_error = true;
-        set_error("objective is not finite (%g)", phi);
-        return SVR_ENUMERIC;
-    }
-    return SVR_OK;
+    return svr::objective_result(R, o, s, phi_host);
 }
 
 int svr_get_image(const svr_recon *R, float *f_dev, void *stream) {

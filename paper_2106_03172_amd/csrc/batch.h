@@ -72,4 +72,18 @@ void add_update(UpdBatch &b, const IterPlan &p);
 int launch_forward_batch(const Matrix &types, const FwdBatch &b, hipStream_t s);
 int launch_update_batch(const Matrix &types, const UpdBatch &b, hipStream_t s);
 
+// The objective in two halves, so that several recons' objectives share one wait:
+// objective_enqueue enqueues the reductions on s and the copies of their results into *out
+// (pinned host memory for an asynchronous copy); once s has completed, objective_result turns
+// them into the objective, with the errors of svr_objective.
+struct ObjectiveHost {
+    double sums[2];  // log-likelihood, penalty sum
+    int bad;         // entries outside the likelihood's domain
+    int status;      // persistent-kernel abort flag
+};
+int objective_enqueue(svr_recon *R, hipStream_t s, ObjectiveHost *out);
+int objective_result(svr_recon *R, const ObjectiveHost &o, hipStream_t s, double *phi);
+// The current image of a single-slice recon (device, N floats).
+const float *current_image(const svr_recon *R);
+
 }  // namespace svr

@@ -99,6 +99,8 @@ struct svr_server {
     // the device blocks of finished requests, kept for the requests admitted later (within the
     // memory budget together with used_bytes)
     svr::BlockCache cache;
+    char *pin = nullptr;  // pinned staging for the results of the requests finishing in a tick
+    size_t pin_bytes = 0;
 };
 
 using namespace svr;
@@ -231,8 +233,8 @@ void batched_epoch(svr_server *S) {
     S->epochs += (int64_t)rs.size();
 }
 
-int finish(svr_server *S, Request *q, hipStream_t s) {
-    TraceRange tr("svr.serve.finish");
+// One request's objective and image with waits of its own (when no pinned staging is to be had).
+void finish_one(svr_server *S, Request *q, hipStream_t s) {
     const int64_t N = (int64_t)q->req.geom.nx * q->req.geom.ny;
     double phi = 0.0;
     int rc = svr_objective(q->R, &phi, s);
@@ -252,7 +254,70 @@ int finish(svr_server *S, Request *q, hipStream_t s) {
     q->state = DONE;
     q->t_done = clk::now();
     release(S, q, true);  // every stream was synchronised before the request finished
-    return SVR_OK;
+}
+
+// The requests finishing this tick: their objectives and image copies (into pinned staging)
+// are enqueued on their streams, the streams waited for once, then the results read.
+void finish_all(svr_server *S, const std::vector<Request *> &done) {
+    if (done.empty()) return;
+    TraceRange tr("svr.serve.finish");
+    auto al = [](size_t b) { return (b + 255) & ~(size_t)255; };
+    auto n_of = [](const Request *q) { return (size_t)q->req.geom.nx * q->req.geom.ny; };
+    size_t need = 0;
+    for (const Request *q : done) need += al(sizeof(ObjectiveHost)) + al(sizeof(float) * n_of(q));
+    if (need > S->pin_bytes) {
+        if (S->pin) (void)hipHostFree(S->pin);
+        S->pin = nullptr;
+        const size_t cap = std::max(need, 2 * S->pin_bytes);
+        S->pin_bytes = 0;
+        if (hipHostMalloc((void **)&S->pin, cap) == hipSuccess) {
+            S->pin_bytes = cap;
+        } else {
+            S->pin = nullptr;
+            (void)hipGetLastError();
+        }
+    }
+    if (!S->pin) {
+        for (Request *q : done) finish_one(S, q, S->streams[q->stream]);
+        return;
+    }
+    std::vector<ObjectiveHost *> oh(done.size());
+    std::vector<float *> img(done.size());
+    std::vector<int> rcs(done.size());
+    char *p = S->pin;
+    for (size_t k = 0; k < done.size(); ++k) {
+        Request *q = done[k];
+        hipStream_t s = S->streams[q->stream];
+        oh[k] = reinterpret_cast<ObjectiveHost *>(p);
+        p += al(sizeof(ObjectiveHost));
+        img[k] = reinterpret_cast<float *>(p);
+        p += al(sizeof(float) * n_of(q));
+        *oh[k] = ObjectiveHost{};
+        rcs[k] = objective_enqueue(q->R, s, oh[k]);
+        const hipError_t e =
+            hipMemcpyAsync(img[k], current_image(q->R), sizeof(float) * n_of(q), hipMemcpyDeviceToHost, s);
+        if (e != hipSuccess && !rcs[k]) {
+            set_error("image copy failed: %s", hipGetErrorString(e));
+            rcs[k] = SVR_EDEVICE;
+        }
+    }
+    for (hipStream_t st : S->streams) (void)hipStreamSynchronize(st);
+    for (size_t k = 0; k < done.size(); ++k) {
+        Request *q = done[k];
+        hipStream_t s = S->streams[q->stream];
+        double phi = 0.0;
+        int rc = rcs[k];
+        if (!rc) {
+            rc = objective_result(q->R, *oh[k], s, &phi);
+            if (rc == SVR_EDEVICE) (void)hipStreamSynchronize(s);  // its flag reset is in flight
+        }
+        q->phi = phi;
+        q->status = rc;
+        q->f.assign(img[k], img[k] + n_of(q));
+        q->state = DONE;
+        q->t_done = clk::now();
+        release(S, q, true);  // every stream has finished with it
+    }
 }
 
 // Keeps the cache within what the budget leaves beside the resident requests.
@@ -381,17 +446,22 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
             for (hipStream_t st : S->streams) SVR_HIP(hipStreamSynchronize(st));
         }
         std::vector<uint64_t> still;
+        std::vector<Request *> done;
+        std::vector<int> prior;  // an error from the epochs outranks the objective's status
         for (size_t i = 0; i < S->resident.size(); ++i) {
             const uint64_t tk = S->resident[i];
             Request *q = S->reqs[tk].get();
             if (i < running && (q->status != SVR_OK || q->epochs_done >= q->req.epochs)) {
-                int st = q->status;
-                finish(S, q, S->streams[q->stream]);
-                if (st != SVR_OK) q->status = st;
-                ++S->completed;
+                done.push_back(q);
+                prior.push_back(q->status);
             } else {
                 still.push_back(tk);
             }
+        }
+        finish_all(S, done);
+        for (size_t k = 0; k < done.size(); ++k) {
+            if (prior[k] != SVR_OK) done[k]->status = prior[k];
+            ++S->completed;
         }
         S->resident.swap(still);
         trim_cache(S, S->cfg.mem_budget_bytes - S->used_bytes);
@@ -410,12 +480,31 @@ int svr_serve_poll(svr_server *S, uint64_t ticket, svr_serve_result *res) {
     }
     Request *q = it->second.get();
     if (q->state != DONE) return SVR_PENDING;
-    if (res->f_host && !q->f.empty()) memcpy(res->f_host, q->f.data(), sizeof(float) * q->f.size());
+    if (res->f_host) {
+        const size_t n = (size_t)q->req.geom.nx * q->req.geom.ny;
+        if (q->f.size() == n)
+            memcpy(res->f_host, q->f.data(), sizeof(float) * n);
+        else
+            memset(res->f_host, 0, sizeof(float) * n);  // cancelled, or failed before an image existed
+    }
     res->phi = q->phi;
     res->queue_ms = ms_since(q->t_submit, q->t_admit);
     res->run_ms = ms_since(q->t_admit, q->t_done);
     res->status = q->status;
     S->reqs.erase(it);
+    return SVR_OK;
+}
+
+int svr_serve_done(const svr_server *S, uint64_t *tickets, int32_t cap, int32_t *n) {
+    clear_error();
+    SVR_REQUIRE(S && n, "NULL argument");
+    SVR_REQUIRE(cap >= 0 && (tickets || cap == 0), "cap must be >= 0, with a tickets array when > 0");
+    int32_t k = 0;
+    for (const auto &kv : S->reqs) {
+        if (k >= cap) break;
+        if (kv.second->state == DONE) tickets[k++] = kv.first;
+    }
+    *n = k;
     return SVR_OK;
 }
 
@@ -476,6 +565,7 @@ void svr_serve_destroy(svr_server *S) {
         (void)hipStreamSynchronize(S->streams[0]);
     }
     for (hipStream_t st : S->streams) (void)hipStreamDestroy(st);
+    if (S->pin) (void)hipHostFree(S->pin);
     delete S;
 }
 

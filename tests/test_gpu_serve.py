@@ -254,3 +254,26 @@ def test_cache_yields_to_the_budget():
     assert peak > 0
     assert all(S.poll(t)["status"] == 0 for t in ts)
     S.close()
+
+
+def test_done_lists_finished_unpolled_tickets():
+    """svr_serve_done: nothing before a tick; afterwards exactly the finished,
+    unpolled tickets in ascending order (a cancelled one included), capped by
+    cap; a polled ticket leaves the list.  A cancelled request's image polls
+    as zeros."""
+    probs = [_req(s) for s in SPECS[:3]]
+    S = pkg.Server(1 << 31, max_slots=1, n_streams=1)
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+    tk = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, 1, 70 + i) for i, P in enumerate(probs)]
+    assert S.done() == []
+    S.cancel(tk[2])
+    assert S.done() == [tk[2]]
+    r = S.poll(tk[2])
+    assert r["status"] == pkg.binding.SVR_ECANCELLED and not np.any(r["f"])
+    S.step(0)
+    assert S.done() == tk[:2] and S.done(cap=1) == tk[:1] and S.done(cap=0) == []
+    first = S.poll(tk[0])
+    assert first["status"] == 0 and np.all(np.isfinite(first["f"])) and first["f"].max() > 0
+    assert S.done() == [tk[1]]
+    assert S.poll(tk[1])["status"] == 0 and S.done() == []
+    S.close()
