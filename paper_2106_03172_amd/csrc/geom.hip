@@ -382,11 +382,10 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
         k_narrow<<<gn, T, 0, s>>>(col, nnz, c16);
         k_narrow<<<gn, T, 0, s>>>(rowT, nnz, r16);
         SVR_HIP(hipGetLastError());
-        dfree(col);
+        dfree(col);  // stream-ordered: after the narrowing kernels
         dfree(rowT);
         A.d_col = c16;
         A.d_rowT = r16;
-        SVR_HIP(hipStreamSynchronize(s));
     } else {
         A.idx16 = 0;
     }

@@ -210,8 +210,7 @@ int exclusive_scan(const int *in, int64_t n, int *out, int64_t *total, hipStream
     }
     k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, bsum, out);
     SVR_HIP(hipGetLastError());
-    SVR_HIP(hipStreamSynchronize(s));
-    dfree(bsum);
+    dfree(bsum);  // stream-ordered: after k_scan_apply
     return SVR_OK;
 }
 
