@@ -13,6 +13,7 @@
 #include <cmath>
 
 #include "common.h"
+#include "kernels.h"
 #include "util.h"
 
 #pragma clang fp contract(off)
@@ -140,33 +141,37 @@ __global__ void k_siddon_fill(svr_geometry g, int M, const int *row_sino, const 
 }
 
 // ---- transposition (per subset), deterministic ------------------------------
-// entries per (subset, pixel); a wavefront per row of A, lanes over its entries
+// entries per (subset, pixel), and each entry's arrival rank among its
+// transposed row's entries (slot, any order); a wavefront per row of A, lanes
+// over its entries
 __global__ void k_col_count(int M, int B, int Ns, int N, const int *row_sino, const int *row_ptr,
-                            const int *col, int *cnt) {
+                            const int *col, int *cnt, int *slot) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = (int)(gid >> 6), lane = (int)(gid & 63);
     if (r >= M) return;
     const int t = (row_sino[r] / B) % Ns;
     int *c = cnt + (int64_t)t * N;
-    for (int i = row_ptr[r] + lane; i < row_ptr[r + 1]; i += 64) atomicAdd(&c[col[i]], 1);
+    for (int i = row_ptr[r] + lane; i < row_ptr[r + 1]; i += 64) slot[i] = atomicAdd(&c[col[i]], 1);
 }
 
-// every entry of A into its transposed row, in whatever order the atomic
-// cursors give (k_rank_T orders each row afterwards); a wavefront per row of
-// A, lanes over its entries
+// every entry of A into its transposed row at the slot k_col_count gave it
+// (k_rank_T orders each row afterwards); a wavefront per row of A, lanes over
+// its entries.  The rows go to the XCDs in contiguous chunks (launched as
+// xcd_grid blocks): the neighbouring bins of a view cross the same pixels and
+// land next to each other in those pixels' transposed rows, so their scattered
+// writes meet in one L2 instead of leaving partial lines in several.
 template <typename WT>
 __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const int *row_start,
                          const int *row_ptr, const int *col, const WT *val, const int *ptrT,
-                         int *cursor, int *rowT, WT *valT) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                         const int *slot, int *rowT, WT *valT, int per) {
+    const int64_t gid = (int64_t)xcd_chunk(blockIdx.x, per) * blockDim.x + threadIdx.x;
     const int r = (int)(gid >> 6), lane = (int)(gid & 63);
     if (r >= M) return;
     const int t = (row_sino[r] / B) % Ns;
     const int local = r - row_start[t];
     const int64_t base = (int64_t)t * N;
     for (int i = row_ptr[r] + lane; i < row_ptr[r + 1]; i += 64) {
-        int n = col[i];
-        int p = ptrT[base + n] + atomicAdd(&cursor[base + n], 1);
+        const int p = ptrT[base + col[i]] + slot[i];
         rowT[p] = local;
         valT[p] = val[i];
     }
@@ -340,18 +345,20 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     // transposed rows per subset
     SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
     const unsigned gW = (unsigned)(((int64_t)M * 64 + T - 1) / T);  // a wavefront per row
-    k_col_count<<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt);
+    int *slot = rowT;  // rowT is written only by k_rank_T, after the last read of the slots
+    k_col_count<<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt, slot);
     k_max_count<<<(unsigned)std::min<int64_t>((NT + T - 1) / T, MAX_BLOCKS), T, 0, s>>>(NT, cnt, stats);
     SVR_HIP(hipGetLastError());
     int64_t nnzT = 0;
     rc = exclusive_scan(cnt, NT, A.d_ptrT, &nnzT, s);
     if (rc) { cleanup(); return rc; }
     if (nnzT != nnz) { cleanup(); set_error("transpose count mismatch"); return SVR_EDEVICE; }
-    SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
     SVR_HIP(dalloc(&fillR, nnz));
     SVR_HIP(dalloc(&fillV, nnz));
-    k_fill_T<WT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
-                                  val, A.d_ptrT, cnt, fillR, fillV);
+    int per = 0;
+    const int gX = xcd_grid(gW, per);
+    k_fill_T<WT><<<gX, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
+                                  val, A.d_ptrT, slot, fillR, fillV, per);
     k_rank_T<WT><<<(unsigned)((NT * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, fillR, fillV, rowT, valT);
     dfree(fillR);
     dfree(fillV);
