@@ -13,7 +13,6 @@
 #include <cmath>
 
 #include "common.h"
-#include "kernels.h"
 #include "util.h"
 
 #pragma clang fp contract(off)
@@ -156,15 +155,12 @@ __global__ void k_col_count(int M, int B, int Ns, int N, const int *row_sino, co
 
 // every entry of A into its transposed row at the slot k_col_count gave it
 // (k_rank_T orders each row afterwards); a wavefront per row of A, lanes over
-// its entries.  The rows go to the XCDs in contiguous chunks (launched as
-// xcd_grid blocks): the neighbouring bins of a view cross the same pixels and
-// land next to each other in those pixels' transposed rows, so their scattered
-// writes meet in one L2 instead of leaving partial lines in several.
+// its entries
 template <typename WT>
 __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const int *row_start,
                          const int *row_ptr, const int *col, const WT *val, const int *ptrT,
-                         const int *slot, int *rowT, WT *valT, int per) {
-    const int64_t gid = (int64_t)xcd_chunk(blockIdx.x, per) * blockDim.x + threadIdx.x;
+                         const int *slot, int *rowT, WT *valT) {
+    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = (int)(gid >> 6), lane = (int)(gid & 63);
     if (r >= M) return;
     const int t = (row_sino[r] / B) % Ns;
@@ -355,10 +351,8 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     if (nnzT != nnz) { cleanup(); set_error("transpose count mismatch"); return SVR_EDEVICE; }
     SVR_HIP(dalloc(&fillR, nnz));
     SVR_HIP(dalloc(&fillV, nnz));
-    int per = 0;
-    const int gX = xcd_grid(gW, per);
-    k_fill_T<WT><<<gX, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
-                                  val, A.d_ptrT, slot, fillR, fillV, per);
+    k_fill_T<WT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
+                                  val, A.d_ptrT, slot, fillR, fillV);
     k_rank_T<WT><<<(unsigned)((NT * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, fillR, fillV, rowT, valT);
     dfree(fillR);
     dfree(fillV);
