@@ -60,6 +60,7 @@ void dfree(void *p);
 // at several ms a block with every host thread's calls held up; blocks kept here stay in use as
 // far as the pool is concerned.
 struct BlockCache {
+    std::mutex mu;                           // scopes on several threads may share a cache
     std::unordered_map<void *, size_t> out;  // blocks handed out while a scope was active
     std::multimap<size_t, void *> idle;      // blocks kept, by size
     int64_t idle_bytes = 0;

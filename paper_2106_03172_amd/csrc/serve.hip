@@ -17,6 +17,7 @@
 #include <map>
 #include <memory>
 #include <new>
+#include <thread>
 #include <vector>
 
 #include "batch.h"
@@ -52,7 +53,7 @@ struct Request {
     std::vector<float> g, w;
     State state = QUEUED;
     int status = SVR_OK;
-    int64_t est_bytes = 0, est_matrix = 0, held_bytes = 0;
+    int64_t est_bytes = 0, est_matrix = 0, held_bytes = 0, actual_bytes = 0;
     svr_matrix *A = nullptr;
     svr_recon *R = nullptr;
     float *d_g = nullptr, *d_w = nullptr, *d_f0 = nullptr;
@@ -130,7 +131,8 @@ __global__ void k_fill(float *x, int64_t n, float v) {
     if (i < n) x[i] = v;
 }
 
-// builds the request's matrix and recon and runs the OSEM initialisation epoch
+// builds the request's matrix and recon and runs the OSEM initialisation epoch; touches the
+// server only through its block cache (locked), so several admissions may run at once
 int admit(svr_server *S, Request *q, hipStream_t s) {
     TraceRange tr("svr.serve.admit");
     AllocStream as(s);
@@ -138,8 +140,6 @@ int admit(svr_server *S, Request *q, hipStream_t s) {
     const svr_serve_request &r = q->req;
     const int64_t M = (int64_t)r.geom.n_views * r.geom.n_bins;
     const int64_t N = (int64_t)r.geom.nx * r.geom.ny;
-    q->held_bytes = q->est_bytes;
-    S->used_bytes += q->held_bytes;
     int rc = svr_build_system_matrix(&r.geom, r.n_subsets, r.wtype, nullptr, s, &q->A);
     if (rc) return rc;
     SVR_HIP(dalloc(&q->d_g, M));
@@ -155,16 +155,41 @@ int admit(svr_server *S, Request *q, hipStream_t s) {
     for (int t = 0; t < r.n_subsets; ++t) cyc[t] = t;
     rc = svr_osem_epoch(q->R, cyc.data(), r.n_subsets, s);
     if (rc) return rc;
-    // replace the matrix estimate by what the matrix actually holds
+    // the matrix estimate replaced by what the matrix actually holds (applied by the caller)
     svr_matrix_info_t inf;
     svr_matrix_info(q->A, &inf, nullptr);
-    const int64_t actual = q->est_bytes - q->est_matrix + inf.bytes;
-    S->used_bytes += actual - q->held_bytes;
-    q->held_bytes = actual;
+    q->actual_bytes = q->est_bytes - q->est_matrix + inf.bytes;
     q->rng.s = r.order_seed;
     q->t_admit = clk::now();
     q->state = RESIDENT;
     return SVR_OK;
+}
+
+// Admits the requests at once, one host thread each: a matrix build waits on the host for its
+// sizes, and several builds' waits (and their kernels, on different streams) then overlap.
+void admit_all(svr_server *S, const std::vector<Request *> &adm, std::vector<int> &rcs) {
+    rcs.assign(adm.size(), SVR_OK);
+    if (adm.size() == 1) {
+        rcs[0] = admit(S, adm[0], S->streams[adm[0]->stream]);
+        return;
+    }
+    std::vector<std::thread> th;
+    th.reserve(adm.size());
+    for (size_t k = 0; k < adm.size(); ++k) {
+        auto work = [S, &adm, &rcs, k] {
+            if (hipSetDevice(S->device) != hipSuccess) {
+                rcs[k] = SVR_EDEVICE;
+                return;
+            }
+            rcs[k] = admit(S, adm[k], S->streams[adm[k]->stream]);
+        };
+        try {
+            th.emplace_back(work);
+        } catch (const std::exception &) {
+            work();  // no thread to be had: on this one
+        }
+    }
+    for (std::thread &t : th) t.join();
 }
 
 // One epoch of every resident request with the subset iterations batched:
@@ -420,23 +445,33 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
         // admission, FIFO while a slot is free and the estimate fits the budget, after the epochs
         // are enqueued: a new request's matrix build (which waits on the host for its sizes) and
         // OSEM epoch then overlap the resident requests' epochs on the other streams
-        while (!S->queue.empty() && (int)S->resident.size() < S->cfg.max_slots) {
+        std::vector<Request *> adm;
+        while (!S->queue.empty() && (int)(S->resident.size() + adm.size()) < S->cfg.max_slots) {
             Request *q = S->reqs[S->queue.front()].get();
             const int64_t room = S->cfg.mem_budget_bytes - S->used_bytes - q->est_bytes;
             if (room < 0) break;
             trim_cache(S, room);
             S->queue.pop_front();
             q->stream = (int)(q->ticket % S->streams.size());
-            int rc = admit(S, q, S->streams[q->stream]);
+            q->held_bytes = q->est_bytes;  // reserved until the build tells the matrix's size
+            S->used_bytes += q->held_bytes;
+            adm.push_back(q);
+        }
+        std::vector<int> rcs;
+        admit_all(S, adm, rcs);
+        for (size_t k = 0; k < adm.size(); ++k) {
+            Request *q = adm[k];
             ++S->admitted;
-            if (rc) {
-                q->status = rc;
+            if (rcs[k]) {
+                q->status = rcs[k];
                 q->state = DONE;
                 q->t_admit = q->t_done = clk::now();
                 release(S, q, false);  // work of the failed admission may still be in flight
                 ++S->completed;
                 continue;
             }
+            S->used_bytes += q->actual_bytes - q->held_bytes;
+            q->held_bytes = q->actual_bytes;
             S->resident.push_back(q->ticket);
         }
         trim_cache(S, S->cfg.mem_budget_bytes - S->used_bytes);  // matrices larger than estimated

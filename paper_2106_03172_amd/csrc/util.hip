@@ -1,5 +1,6 @@
 // Small device utilities: exclusive scan, deterministic FP64 reduction,
 // row permutation, input validation counters.
+#include <atomic>
 #include <cstdarg>
 #include <cstdio>
 #include <cstdlib>
@@ -32,7 +33,7 @@ LaunchEvents &pending_timing() {
     return t;
 }
 
-static long g_alloc_budget = -2;  // -2: not read yet, -1: unlimited
+static std::atomic<long> g_alloc_budget{-2};  // -2: not read yet, -1: unlimited
 static thread_local hipStream_t g_alloc_stream = nullptr;
 static thread_local BlockCache *g_cache = nullptr;
 static thread_local bool g_cache_keep = false;
@@ -50,6 +51,7 @@ BlockCacheScope::~BlockCacheScope() {
 }
 
 void block_cache_trim(BlockCache &c, int64_t max_idle) {
+    std::lock_guard<std::mutex> lk(c.mu);
     while (c.idle_bytes > max_idle && !c.idle.empty()) {
         auto it = std::prev(c.idle.end());
         (void)hipFreeAsync(it->second, g_alloc_stream);
@@ -73,18 +75,22 @@ static void keep_pool_memory() {
 }
 
 hipError_t dmalloc(void **p, size_t bytes) {
-    if (g_alloc_budget == -2) {
+    long b = g_alloc_budget.load();
+    if (b == -2) {
         const char *e = getenv("SVR_FAULT_ALLOC_AFTER");
-        g_alloc_budget = e ? atol(e) : -1;
+        g_alloc_budget.compare_exchange_strong(b, e ? atol(e) : -1);
+        b = g_alloc_budget.load();
     }
-    if (g_alloc_budget == 0) {
+    while (b > 0 && !g_alloc_budget.compare_exchange_weak(b, b - 1)) {
+    }
+    if (b == 0) {
         *p = nullptr;
         return hipErrorOutOfMemory;
     }
-    if (g_alloc_budget > 0) --g_alloc_budget;
     if (bytes == 0) bytes = 16;
     BlockCache *c = g_cache;
     if (c) {
+        std::lock_guard<std::mutex> lk(c->mu);
         auto it = c->idle.lower_bound(bytes);
         if (it != c->idle.end() && it->first <= bytes + bytes / 4) {
             *p = it->second;
@@ -97,13 +103,17 @@ hipError_t dmalloc(void **p, size_t bytes) {
     }
     keep_pool_memory();
     const hipError_t e = hipMallocAsync(p, bytes, g_alloc_stream);
-    if (c && e == hipSuccess) c->out.emplace(*p, bytes);
+    if (c && e == hipSuccess) {
+        std::lock_guard<std::mutex> lk(c->mu);
+        c->out.emplace(*p, bytes);
+    }
     return e;
 }
 
 void dfree(void *p) {
     if (!p) return;
     if (BlockCache *c = g_cache) {
+        std::lock_guard<std::mutex> lk(c->mu);
         auto it = c->out.find(p);
         if (it != c->out.end()) {
             if (g_cache_keep) {
