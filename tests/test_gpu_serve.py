@@ -277,3 +277,25 @@ def test_done_lists_finished_unpolled_tickets():
     assert S.done() == [tk[1]]
     assert S.poll(tk[1])["status"] == 0 and S.done() == []
     S.close()
+
+
+@pytest.mark.parametrize("batch", [True, False])
+def test_many_concurrent_admissions_match_requests_alone(batch):
+    """Twelve requests admitted in one tick (one host thread each, four
+    threads to a stream on three streams) end bitwise as each does served
+    alone."""
+    specs = [(nx, V, B, Ns, c, 400 + k) for k, (nx, V, B, Ns, c, _) in enumerate(SPECS * 3)]
+    probs = [_req(s) for s in specs]
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+    S = pkg.Server(1 << 31, max_slots=12, n_streams=3, batch=batch)
+    tk = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS, 600 + i) for i, P in enumerate(probs)]
+    S.step(1)
+    assert S.stats()["admitted"] == 12
+    S.step(0)
+    mixed = [S.poll(t) for t in tk]
+    S.close()
+    for i, P in enumerate(probs):
+        alone = _serve([P], seeds=[600 + i])[0]
+        assert mixed[i]["status"] == 0 and alone["status"] == 0
+        np.testing.assert_array_equal(mixed[i]["f"], alone["f"])
+        assert mixed[i]["phi"] == alone["phi"]
