@@ -175,36 +175,74 @@ __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const
 
 // Each transposed row in subset-local row order (view, then bin), read from
 // the unordered fill (keys, vals) and written to (rowT, valT): a 32-lane group
-// per row, two rows per wavefront; the lane holding an entry counts the keys
-// of its row that are smaller (every key broadcast lane by lane) and writes
-// the entry at beg + that rank.  Keys of a row are unique, so the ranks are a
-// permutation and the order is the ascending one, whatever order the fill
-// left.  Every lane of a wavefront runs the loops (their bounds are the
-// longer of the wavefront's two rows).
-template <typename WT>
+// per R consecutive rows, two groups per wavefront; the lane holding an entry
+// counts the keys of its row that are smaller (every key broadcast lane by
+// lane) and writes the entry at beg + that rank.  Keys of a row are unique, so
+// the ranks are a permutation and the order is the ascending one, whatever
+// order the fill left.  The group loads its R rows' bounds and first 32
+// entries before ranking any of them, so that R rows' loads are in flight at
+// once (the kernel waits on memory, not on its compares); a row longer than 32
+// (in either group of the wavefront) is ranked from memory in 32-entry chunks.
+// Every lane of a wavefront runs the loops (their bounds are the longer of the
+// wavefront's two rows).
+#ifndef SVR_RANK_ROWS
+#define SVR_RANK_ROWS 4
+#endif
+constexpr int RANK_ROWS = SVR_RANK_ROWS;
+template <typename WT, int R>
 __global__ void __launch_bounds__(256)
 k_rank_T(int64_t nrows, const int *ptrT, const int *keys, const WT *vals, int *rowT, WT *valT) {
     const int lane = threadIdx.x & 63, h = lane >> 5, gl = lane & 31;
-    const int64_t q = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5;
-    const bool has_row = q < nrows;
-    const int beg = has_row ? ptrT[q] : 0, len = has_row ? ptrT[q + 1] - beg : 0;
-    const int lmax = max(__builtin_amdgcn_readlane(len, 0), __builtin_amdgcn_readlane(len, 32));
-    for (int c = 0; c < lmax; c += 32) {
-        const int e = c + gl;
-        const bool has = e < len;
-        const int key = has ? keys[beg + e] : INT_MAX;
-        int rank = 0;
-        for (int d = 0; d < lmax; d += 32) {
-            const int kd = d + gl < len ? keys[beg + d + gl] : INT_MAX;
-#pragma unroll 8
-            for (int j = 0; j < 32; ++j) {
-                const int k0 = __builtin_amdgcn_readlane(kd, j), k1 = __builtin_amdgcn_readlane(kd, 32 + j);
-                rank += (h ? k1 : k0) < key;
+    const int64_t q0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5) * R;
+    const int pv = (gl <= R && q0 + gl <= nrows) ? ptrT[q0 + gl] : 0;  // row bounds, one per lane
+    int beg[R], len[R], key[R];
+    WT val[R];
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int b = __shfl(pv, (h << 5) + r), e = __shfl(pv, (h << 5) + r + 1);
+        const bool has_row = q0 + r < nrows;
+        beg[r] = has_row ? b : 0;
+        len[r] = has_row ? e - b : 0;
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const bool has = gl < len[r];
+        key[r] = has ? keys[beg[r] + gl] : INT_MAX;
+        val[r] = has ? vals[beg[r] + gl] : WT{};
+    }
+#pragma unroll
+    for (int r = 0; r < R; ++r) {
+        const int lmax = max(__builtin_amdgcn_readlane(len[r], 0), __builtin_amdgcn_readlane(len[r], 32));
+        if (lmax <= 32) {
+            int rank = 0;
+#pragma unroll 4
+            for (int j = 0; j < lmax; ++j) {
+                const int k0 = __builtin_amdgcn_readlane(key[r], j), k1 = __builtin_amdgcn_readlane(key[r], 32 + j);
+                rank += (h ? k1 : k0) < key[r];
             }
+            if (gl < len[r]) {
+                rowT[beg[r] + rank] = key[r];
+                valT[beg[r] + rank] = val[r];
+            }
+            continue;
         }
-        if (has) {
-            rowT[beg + rank] = key;
-            valT[beg + rank] = vals[beg + e];
+        for (int c = 0; c < lmax; c += 32) {
+            const int e = c + gl;
+            const bool has = e < len[r];
+            const int k = has ? keys[beg[r] + e] : INT_MAX;
+            int rank = 0;
+            for (int d = 0; d < lmax; d += 32) {
+                const int kd = d + gl < len[r] ? keys[beg[r] + d + gl] : INT_MAX;
+#pragma unroll 8
+                for (int j = 0; j < 32; ++j) {
+                    const int k0 = __builtin_amdgcn_readlane(kd, j), k1 = __builtin_amdgcn_readlane(kd, 32 + j);
+                    rank += (h ? k1 : k0) < k;
+                }
+            }
+            if (has) {
+                rowT[beg[r] + rank] = k;
+                valT[beg[r] + rank] = vals[beg[r] + e];
+            }
         }
     }
 }
@@ -353,7 +391,9 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     SVR_HIP(dalloc(&fillV, nnz));
     k_fill_T<WT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
                                   val, A.d_ptrT, slot, fillR, fillV);
-    k_rank_T<WT><<<(unsigned)((NT * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, fillR, fillV, rowT, valT);
+    const int64_t groups = (NT + RANK_ROWS - 1) / RANK_ROWS;
+    k_rank_T<WT, RANK_ROWS><<<(unsigned)((groups * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, fillR, fillV, rowT,
+                                                                               valT);
     dfree(fillR);
     dfree(fillV);
     fillR = nullptr;
