@@ -193,7 +193,7 @@ def main():
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the size-based run lengths instead of autotuning them (a profiled run uses this so "
                          "that its kernels do not depend on timings taken under the profiler)")
-    ap.add_argument("--workload", choices=("headline", "multislice", "serve", "serve-compare", "copy",
+    ap.add_argument("--workload", choices=("headline", "multislice", "serve", "serve-scanner", "serve-compare", "copy",
                                            "convergence", "algos", "small", "projectors", "precision"),
                     default="headline",
                         help="headline: the JSON line below; multislice / serve / serve-compare / convergence / "
@@ -230,6 +230,8 @@ def main():
         return bench_serve(args)
     if args.workload == "serve-compare":
         return bench_serve_compare(args)
+    if args.workload == "serve-scanner":
+        return bench_serve_scanner(args)
     if args.workload == "convergence":
         return bench_convergence(args)
     if args.workload == "copy":
@@ -754,10 +756,11 @@ def _serving_data(n):
     return specs, data
 
 
-def serve_latency(specs, data, alpha):
+def serve_latency(specs, data, alpha, share=True, rate=None):
     """Continuous batching with Poisson arrivals: capacity from all requests at
-    once (the second of two such runs), then a Poisson stream at 0.8 of it;
-    latency from arrival to completion."""
+    once (the second of two such runs), then a Poisson stream at ``rate``
+    (default 0.8 of the capacity); latency from arrival to completion.
+    ``share``: requests of one geometry share a matrix."""
     import numpy as np
 
     import paper_2106_03172_amd as pkg
@@ -765,7 +768,7 @@ def serve_latency(specs, data, alpha):
     prm = pkg.params("svrem", alpha=alpha, eta=1, beta=1e-3)
 
     def run(arrivals):
-        S = pkg.Server(64 << 30, max_slots=16, n_streams=8)
+        S = pkg.Server(64 << 30, max_slots=16, n_streams=8, share_matrices=share)
         order = np.argsort(arrivals)
         done, owner = {}, {}  # owner: pending ticket -> request index
         nxt = 0
@@ -793,7 +796,8 @@ def serve_latency(specs, data, alpha):
     done, total = run(np.zeros(n))
     capacity = n / total
     log(f"capacity {capacity:.2f} requests/s (all {n} at t=0, {total:.2f} s)")
-    rate = 0.8 * capacity
+    if rate is None:
+        rate = 0.8 * capacity
     gaps = np.random.Generator(np.random.PCG64(4001)).exponential(1.0 / rate, n)
     arrivals = np.cumsum(gaps)
     done, total = run(arrivals)
@@ -886,6 +890,24 @@ def bench_serve(args):
     out = serve_latency(specs, data, args.alpha)
     print(json.dumps({"workload": "serve", "metric": "p50/p99 recon latency and requests/s (Poisson arrivals)",
                       **out}), flush=True)
+
+
+def bench_serve_scanner(args):
+    """Requests from one scanner (one geometry, different data): capacity and
+    Poisson-arrival latency with the requests sharing one matrix and with each
+    building its own, both at 0.8 of the latter's capacity."""
+    import datagen
+    specs = datagen.scanner_requests(args.requests)
+    log(f"generating {len(specs)} requests of one geometry")
+    data = [datagen.make_problem(r["nx"], r["ny"], r["pixel_mm"], r["n_views"], r["n_bins"], r["bin_mm"],
+                                 r["n_subsets"], r["counts"], seed=r["seed"]) for r in specs]
+    own = serve_latency(specs, data, args.alpha, share=False)
+    shared = serve_latency(specs, data, args.alpha, share=True, rate=own["offered_rps"])
+    print(json.dumps({"workload": "serve-scanner",
+                      "metric": "p50/p99 recon latency and requests/s, one scanner geometry (256^2, 252 x 344, "
+                                "21 subsets), shared matrix against one matrix per request",
+                      "shared": shared, "own_matrix": own,
+                      "capacity_ratio": round(shared["capacity_rps"] / own["capacity_rps"], 3)}), flush=True)
 
 
 def bench_serve_compare(args):

@@ -18,6 +18,7 @@ from .phantoms import (  # noqa: F401
     make_problem,
     make_multislice_problem,
     make_order,
+    scanner_requests,
     serving_requests,
     CONFIG_SMALL,
     CONFIG_HEADLINE,

@@ -301,3 +301,14 @@ def serving_requests(n: int, rate_per_s: float, seed: int = 0,
                         bin_mm=2.0, n_subsets=ns, counts=counts, epochs=epochs,
                         seed=100 + i))
     return out
+
+
+def scanner_requests(n: int, seed: int = 0, epochs: int = 30) -> List[dict]:
+    """A seeded stream of ``n`` requests from one scanner: the headline
+    geometry (256 x 256, 2 mm; 252 views x 344 bins, 21 subsets) for every
+    request, counts log-uniform in [1e5, 1e7], SVREM for ``epochs`` epochs
+    (seed ``5000+seed``)."""
+    rng = np.random.Generator(np.random.PCG64(5000 + seed))
+    return [dict(id=i, nx=256, ny=256, pixel_mm=2.0, n_views=252, n_bins=344, bin_mm=2.0, n_subsets=21,
+                 counts=float(10.0 ** rng.uniform(5.0, 7.0)), epochs=epochs, seed=300 + i) for i in range(n)]
+

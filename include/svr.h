@@ -374,6 +374,11 @@ typedef struct {
     int32_t n_streams;         /* device streams (>= 1): matrix builds, and per-request epochs when batch = 0 */
     int32_t batch;             /* 1: batched subset iterations (requests may not set
                                   SVR_FLAG_PERSISTENT_EPOCH); 0: one request's epoch per stream */
+    int32_t share_matrices;    /* 1: requests with the same geometry, subset count and weight
+                                  type use one matrix, built once and kept on the device after
+                                  its last user finishes while the budget allows (a later
+                                  request of that key skips the build); 0: each request builds
+                                  its own */
 } svr_serve_config;
 
 typedef struct {
@@ -421,17 +426,20 @@ typedef struct {
     int32_t resident;          /* admitted and iterating (<= max_slots) */
     int32_t max_slots;
     int32_t done_unpolled;     /* finished (any status), result not yet polled */
-    int64_t used_bytes;        /* device bytes held by resident requests (the admission estimate,
-                                  then the matrix's actual size plus the recon's estimate) */
+    int64_t used_bytes;        /* device bytes held by resident requests: the recons' estimates
+                                  and the matrices they use, each matrix once (its estimate until
+                                  it is built, then its actual size) */
     int64_t mem_budget_bytes;
     int64_t ticks;             /* scheduler ticks run */
     int64_t admitted;          /* requests admitted so far */
     int64_t completed;         /* requests finished so far: done, failed or cancelled */
     int64_t epochs;            /* SVREM epochs run so far, over all requests */
-    int64_t cached_bytes;      /* device blocks of finished requests kept for later admissions
+    int64_t cached_bytes;      /* device memory kept for later admissions: blocks of finished
+                                  requests and matrices no resident request uses
                                   (used_bytes + cached_bytes stays within the budget; freed by
                                   svr_serve_destroy or when an admission needs the room) */
     int64_t block_reuses;      /* allocations served from those kept blocks so far */
+    int64_t matrix_reuses;     /* admissions that used a matrix already built (share_matrices) */
 } svr_serve_stats_t;
 /* Errors: SVR_EINVAL (NULL argument). */
 int  svr_serve_stats(const svr_server *S, svr_serve_stats_t *out);

@@ -73,7 +73,7 @@ class svr_tuning_t(C.Structure):
 
 class svr_serve_config(C.Structure):
     _fields_ = [("mem_budget_bytes", C.c_int64), ("max_slots", C.c_int32), ("n_streams", C.c_int32),
-                ("batch", C.c_int32)]
+                ("batch", C.c_int32), ("share_matrices", C.c_int32)]
 
 
 class svr_serve_request(C.Structure):
@@ -87,7 +87,7 @@ class svr_serve_stats_t(C.Structure):
     _fields_ = [("queued", C.c_int32), ("resident", C.c_int32), ("max_slots", C.c_int32),
                 ("done_unpolled", C.c_int32), ("used_bytes", C.c_int64), ("mem_budget_bytes", C.c_int64),
                 ("ticks", C.c_int64), ("admitted", C.c_int64), ("completed", C.c_int64), ("epochs", C.c_int64),
-                ("cached_bytes", C.c_int64), ("block_reuses", C.c_int64)]
+                ("cached_bytes", C.c_int64), ("block_reuses", C.c_int64), ("matrix_reuses", C.c_int64)]
 
 
 class svr_serve_result(C.Structure):
@@ -463,8 +463,10 @@ class Recon:
 class Server:
     """Continuous-batching SVREM server (``svr_serve_*``)."""
 
-    def __init__(self, mem_budget_bytes: int, max_slots: int = 8, n_streams: int = 4, batch: bool = True):
-        cfg = svr_serve_config(int(mem_budget_bytes), int(max_slots), int(n_streams), 1 if batch else 0)
+    def __init__(self, mem_budget_bytes: int, max_slots: int = 8, n_streams: int = 4, batch: bool = True,
+                 share_matrices: bool = True):
+        cfg = svr_serve_config(int(mem_budget_bytes), int(max_slots), int(n_streams), 1 if batch else 0,
+                               1 if share_matrices else 0)
         self.h = C.c_void_p()
         _check(lib().svr_serve_create(C.byref(cfg), C.byref(self.h)))
         self._keep = {}

@@ -14,10 +14,12 @@
 #include <cmath>
 #include <cstring>
 #include <deque>
+#include <list>
 #include <map>
 #include <memory>
 #include <new>
 #include <thread>
+#include <tuple>
 #include <vector>
 
 #include "batch.h"
@@ -47,14 +49,45 @@ struct SplitMix64 {
 
 enum State { QUEUED, RESIDENT, DONE };
 
+// Requests with the same geometry, subset count and weight type share one matrix.
+struct MatrixKey {
+    int nx, ny, n_views, n_bins, n_subsets, wtype;
+    double pixel_mm, bin_mm, arc_rad;
+    bool operator<(const MatrixKey &o) const {
+        return std::tie(nx, ny, n_views, n_bins, n_subsets, wtype, pixel_mm, bin_mm, arc_rad) <
+               std::tie(o.nx, o.ny, o.n_views, o.n_bins, o.n_subsets, o.wtype, o.pixel_mm, o.bin_mm, o.arc_rad);
+    }
+};
+MatrixKey key_of(const svr_serve_request &r) {
+    const svr_geometry &g = r.geom;
+    return MatrixKey{g.nx, g.ny, g.n_views, g.n_bins, r.n_subsets, r.wtype, g.pixel_mm, g.bin_mm, g.arc_rad};
+}
+
+// A matrix on the device and the resident requests that use it.  While refs > 0 its bytes are
+// in used_bytes; at refs == 0 it stays on the device (idle, in idle_matrix_bytes) for later
+// requests of its key until the budget needs the room.  Without sharing every request has an
+// entry of its own, outside the index.
+struct SharedMatrix {
+    MatrixKey key{};
+    bool indexed = false;     // in the server's index by key (sharing on)
+    svr_matrix *A = nullptr;  // null until its build has succeeded
+    int refs = 0;
+    int64_t bytes = 0;        // the estimate until the build, then what the matrix holds
+    int64_t built_bytes = 0;  // written by the build
+    int build_rc = SVR_OK;
+    int64_t last_tick = 0;
+};
+
 struct Request {
     uint64_t ticket = 0;
     svr_serve_request req{};
     std::vector<float> g, w;
     State state = QUEUED;
     int status = SVR_OK;
-    int64_t est_bytes = 0, est_matrix = 0, held_bytes = 0, actual_bytes = 0;
+    int64_t est_bytes = 0, est_matrix = 0, held_bytes = 0;
     svr_matrix *A = nullptr;
+    SharedMatrix *shared = nullptr;  // the server's entry for A (A is the entry's)
+    bool builds = false;                    // this admission builds the entry's matrix
     svr_recon *R = nullptr;
     float *d_g = nullptr, *d_w = nullptr, *d_f0 = nullptr;
     int stream = 0;
@@ -100,6 +133,10 @@ struct svr_server {
     // the device blocks of finished requests, kept for the requests admitted later (within the
     // memory budget together with used_bytes)
     svr::BlockCache cache;
+    std::list<SharedMatrix> mats;                   // every matrix entry (stable addresses)
+    std::map<MatrixKey, SharedMatrix *> mat_index;  // the shared ones, by key
+    int64_t idle_matrix_bytes = 0;
+    int64_t matrix_reuses = 0;
     char *pin = nullptr;  // pinned staging for the results of the requests finishing in a tick
     size_t pin_bytes = 0;
 };
@@ -110,11 +147,50 @@ namespace {
 
 // Frees q's device objects.  keep: every stream has finished with them, and their blocks stay
 // in the server's cache; else they are freed, stream-ordered on q's stream.
+void destroy_matrix_entry(svr_server *S, SharedMatrix *m, bool keep) {
+    BlockCacheScope sc(&S->cache, keep);
+    if (m->A) svr_matrix_destroy(m->A);
+    if (m->indexed) S->mat_index.erase(m->key);
+    for (auto it = S->mats.begin(); it != S->mats.end(); ++it)
+        if (&*it == m) {
+            S->mats.erase(it);
+            break;
+        }
+}
+
+// Drops q's use of its matrix: the matrix goes idle (kept for later requests of its key) or, with
+// sharing off or after a failed admission (keep false), is destroyed.
+void unref_matrix(svr_server *S, Request *q, bool keep) {
+    SharedMatrix *m = q->shared;
+    q->shared = nullptr;
+    q->A = nullptr;
+    if (!m || --m->refs > 0) return;
+    S->used_bytes -= m->bytes;
+    if (keep && m->indexed && m->A) {
+        m->last_tick = S->ticks;
+        S->idle_matrix_bytes += m->bytes;
+    } else {
+        destroy_matrix_entry(S, m, keep);
+    }
+}
+
+// Destroys the least recently used idle matrix other than `except` (its blocks go to the block
+// cache); false if there is none.
+bool evict_idle_matrix(svr_server *S, const SharedMatrix *except) {
+    SharedMatrix *lru = nullptr;
+    for (SharedMatrix &m : S->mats)
+        if (m.refs == 0 && m.A && &m != except && (!lru || m.last_tick < lru->last_tick)) lru = &m;
+    if (!lru) return false;
+    S->idle_matrix_bytes -= lru->bytes;
+    destroy_matrix_entry(S, lru, true);
+    return true;
+}
+
 void release(svr_server *S, Request *q, bool keep) {
     TraceRange tr("svr.serve.release");
     BlockCacheScope sc(&S->cache, keep);
     if (q->R) svr_recon_destroy(q->R);
-    if (q->A) svr_matrix_destroy(q->A);
+    unref_matrix(S, q, keep);
     AllocStream as(S->streams[q->stream]);
     dfree(q->d_g);
     dfree(q->d_w);
@@ -131,8 +207,31 @@ __global__ void k_fill(float *x, int64_t n, float v) {
     if (i < n) x[i] = v;
 }
 
-// builds the request's matrix and recon and runs the OSEM initialisation epoch; touches the
-// server only through its block cache (locked), so several admissions may run at once
+// Builds the matrix of the entry q->shared on q's stream and waits for it (requests on other
+// streams use it next).  Touches the server only through its block cache (locked) and the
+// entry, so several builds may run at once.
+int build_shared(svr_server *S, Request *q, hipStream_t s) {
+    TraceRange tr("svr.serve.build");
+    AllocStream as(s);
+    BlockCacheScope sc(&S->cache, false);
+    const svr_serve_request &r = q->req;
+    svr_matrix *A = nullptr;
+    int rc = svr_build_system_matrix(&r.geom, r.n_subsets, r.wtype, nullptr, s, &A);
+    if (rc) return rc;
+    if (hipStreamSynchronize(s) != hipSuccess) {
+        svr_matrix_destroy(A);
+        set_error("matrix build failed on the device");
+        return SVR_EDEVICE;
+    }
+    svr_matrix_info_t inf;
+    svr_matrix_info(A, &inf, nullptr);
+    q->shared->A = A;
+    q->shared->built_bytes = inf.bytes;
+    return SVR_OK;
+}
+
+// The request's recon on its (built) matrix and the OSEM initialisation epoch; touches the
+// server only through its block cache (locked), so several admissions may run at once.
 int admit(svr_server *S, Request *q, hipStream_t s) {
     TraceRange tr("svr.serve.admit");
     AllocStream as(s);
@@ -140,8 +239,7 @@ int admit(svr_server *S, Request *q, hipStream_t s) {
     const svr_serve_request &r = q->req;
     const int64_t M = (int64_t)r.geom.n_views * r.geom.n_bins;
     const int64_t N = (int64_t)r.geom.nx * r.geom.ny;
-    int rc = svr_build_system_matrix(&r.geom, r.n_subsets, r.wtype, nullptr, s, &q->A);
-    if (rc) return rc;
+    int rc = SVR_OK;
     SVR_HIP(dalloc(&q->d_g, M));
     SVR_HIP(dalloc(&q->d_w, M));
     SVR_HIP(dalloc(&q->d_f0, N));
@@ -155,33 +253,31 @@ int admit(svr_server *S, Request *q, hipStream_t s) {
     for (int t = 0; t < r.n_subsets; ++t) cyc[t] = t;
     rc = svr_osem_epoch(q->R, cyc.data(), r.n_subsets, s);
     if (rc) return rc;
-    // the matrix estimate replaced by what the matrix actually holds (applied by the caller)
-    svr_matrix_info_t inf;
-    svr_matrix_info(q->A, &inf, nullptr);
-    q->actual_bytes = q->est_bytes - q->est_matrix + inf.bytes;
     q->rng.s = r.order_seed;
     q->t_admit = clk::now();
     q->state = RESIDENT;
     return SVR_OK;
 }
 
-// Admits the requests at once, one host thread each: a matrix build waits on the host for its
-// sizes, and several builds' waits (and their kernels, on different streams) then overlap.
-void admit_all(svr_server *S, const std::vector<Request *> &adm, std::vector<int> &rcs) {
+// Runs fn(S, q, q's stream) for every request at once, one host thread each: a matrix build
+// waits on the host for its sizes, and several builds' waits (and their kernels, on different
+// streams) then overlap.
+void run_each(svr_server *S, const std::vector<Request *> &adm, std::vector<int> &rcs,
+              int (*fn)(svr_server *, Request *, hipStream_t)) {
     rcs.assign(adm.size(), SVR_OK);
     if (adm.size() == 1) {
-        rcs[0] = admit(S, adm[0], S->streams[adm[0]->stream]);
+        rcs[0] = fn(S, adm[0], S->streams[adm[0]->stream]);
         return;
     }
     std::vector<std::thread> th;
     th.reserve(adm.size());
     for (size_t k = 0; k < adm.size(); ++k) {
-        auto work = [S, &adm, &rcs, k] {
+        auto work = [S, &adm, &rcs, k, fn] {
             if (hipSetDevice(S->device) != hipSuccess) {
                 rcs[k] = SVR_EDEVICE;
                 return;
             }
-            rcs[k] = admit(S, adm[k], S->streams[adm[k]->stream]);
+            rcs[k] = fn(S, adm[k], S->streams[adm[k]->stream]);
         };
         try {
             th.emplace_back(work);
@@ -352,6 +448,13 @@ void trim_cache(svr_server *S, int64_t room) {
     block_cache_trim(S->cache, std::max<int64_t>(room, 0));
 }
 
+// Idle matrices, then kept blocks, give way until what the server holds fits the budget.
+void fit_budget(svr_server *S) {
+    while (S->used_bytes + S->idle_matrix_bytes > S->cfg.mem_budget_bytes && evict_idle_matrix(S, nullptr)) {
+    }
+    trim_cache(S, S->cfg.mem_budget_bytes - S->used_bytes - S->idle_matrix_bytes);
+}
+
 }  // namespace
 
 extern "C" {
@@ -362,6 +465,7 @@ int svr_serve_create(const svr_serve_config *cfg, svr_server **out) {
     SVR_REQUIRE(cfg->mem_budget_bytes > 0 && cfg->max_slots >= 1 && cfg->n_streams >= 1,
                 "mem_budget_bytes > 0, max_slots >= 1 and n_streams >= 1 are required");
     SVR_REQUIRE(cfg->batch == 0 || cfg->batch == 1, "batch must be 0 or 1");
+    SVR_REQUIRE(cfg->share_matrices == 0 || cfg->share_matrices == 1, "share_matrices must be 0 or 1");
     *out = nullptr;
     svr_server *S = new (std::nothrow) svr_server();
     SVR_REQUIRE(S, "host allocation failed");
@@ -445,20 +549,77 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
         // admission, FIFO while a slot is free and the estimate fits the budget, after the epochs
         // are enqueued: a new request's matrix build (which waits on the host for its sizes) and
         // OSEM epoch then overlap the resident requests' epochs on the other streams
-        std::vector<Request *> adm;
+        std::vector<Request *> adm, builders;
         while (!S->queue.empty() && (int)(S->resident.size() + adm.size()) < S->cfg.max_slots) {
             Request *q = S->reqs[S->queue.front()].get();
-            const int64_t room = S->cfg.mem_budget_bytes - S->used_bytes - q->est_bytes;
-            if (room < 0) break;
-            trim_cache(S, room);
+            const MatrixKey key = key_of(q->req);
+            SharedMatrix *m = nullptr;
+            if (S->cfg.share_matrices) {
+                auto it = S->mat_index.find(key);
+                if (it != S->mat_index.end()) m = it->second;
+            }
+            // a matrix in use or idle costs nothing more; a new one its estimate
+            const int64_t rest = q->est_bytes - q->est_matrix, need = rest + (m ? 0 : q->est_matrix);
+            auto room = [&] { return S->cfg.mem_budget_bytes - S->used_bytes - S->idle_matrix_bytes - need; };
+            while (room() < 0 && evict_idle_matrix(S, m)) {
+            }
+            if (room() < 0) break;
+            trim_cache(S, room());
             S->queue.pop_front();
             q->stream = (int)(q->ticket % S->streams.size());
-            q->held_bytes = q->est_bytes;  // reserved until the build tells the matrix's size
-            S->used_bytes += q->held_bytes;
+            q->held_bytes = rest;
+            S->used_bytes += rest;
+            if (m) {
+                if (m->refs == 0 && m->A) {  // idle until now
+                    S->idle_matrix_bytes -= m->bytes;
+                    S->used_bytes += m->bytes;
+                }
+                ++S->matrix_reuses;
+            } else {
+                S->mats.emplace_back();
+                m = &S->mats.back();
+                m->key = key;
+                m->bytes = q->est_matrix;  // reserved until the build tells the matrix's size
+                S->used_bytes += m->bytes;
+                if (S->cfg.share_matrices) {
+                    S->mat_index[key] = m;
+                    m->indexed = true;
+                }
+                q->builds = true;
+                builders.push_back(q);
+            }
+            ++m->refs;
+            q->shared = m;
             adm.push_back(q);
         }
-        std::vector<int> rcs;
-        admit_all(S, adm, rcs);
+        // the new matrices first (each on its builder's stream, waited for), then every admitted
+        // request's recon and OSEM epoch on its own stream
+        std::vector<int> brc, rcs(adm.size(), SVR_OK);
+        run_each(S, builders, brc, build_shared);
+        for (size_t k = 0; k < builders.size(); ++k) {
+            SharedMatrix *m = builders[k]->shared;
+            if (brc[k]) {
+                m->build_rc = brc[k];
+            } else {
+                S->used_bytes += m->built_bytes - m->bytes;
+                m->bytes = m->built_bytes;
+            }
+        }
+        std::vector<Request *> ready;
+        std::vector<size_t> ready_at;
+        for (size_t k = 0; k < adm.size(); ++k) {
+            Request *q = adm[k];
+            if (!q->shared->A) {
+                rcs[k] = q->shared->build_rc ? q->shared->build_rc : SVR_EDEVICE;
+                continue;
+            }
+            q->A = q->shared->A;
+            ready.push_back(q);
+            ready_at.push_back(k);
+        }
+        std::vector<int> arc;
+        run_each(S, ready, arc, admit);
+        for (size_t k = 0; k < ready.size(); ++k) rcs[ready_at[k]] = arc[k];
         for (size_t k = 0; k < adm.size(); ++k) {
             Request *q = adm[k];
             ++S->admitted;
@@ -466,15 +627,15 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
                 q->status = rcs[k];
                 q->state = DONE;
                 q->t_admit = q->t_done = clk::now();
-                release(S, q, false);  // work of the failed admission may still be in flight
+                // its stream may still run the failed admission's work, which reads the matrix
+                (void)hipStreamSynchronize(S->streams[q->stream]);
+                release(S, q, true);
                 ++S->completed;
                 continue;
             }
-            S->used_bytes += q->actual_bytes - q->held_bytes;
-            q->held_bytes = q->actual_bytes;
             S->resident.push_back(q->ticket);
         }
-        trim_cache(S, S->cfg.mem_budget_bytes - S->used_bytes);  // matrices larger than estimated
+        fit_budget(S);  // matrices larger than estimated
         if (S->resident.empty()) return SVR_OK;
         {
             TraceRange ts("svr.serve.sync");
@@ -499,7 +660,7 @@ int svr_serve_step(svr_server *S, int32_t max_ticks) {
             ++S->completed;
         }
         S->resident.swap(still);
-        trim_cache(S, S->cfg.mem_budget_bytes - S->used_bytes);
+        fit_budget(S);
         if (max_ticks <= 0 && S->resident.empty() && S->queue.empty()) return SVR_OK;
     }
     return SVR_OK;
@@ -580,8 +741,9 @@ int svr_serve_stats(const svr_server *S, svr_serve_stats_t *out) {
     out->max_slots = S->cfg.max_slots;
     out->done_unpolled = done;
     out->used_bytes = S->used_bytes;
-    out->cached_bytes = S->cache.idle_bytes;
+    out->cached_bytes = S->cache.idle_bytes + S->idle_matrix_bytes;
     out->block_reuses = S->cache.reuses;
+    out->matrix_reuses = S->matrix_reuses;
     out->mem_budget_bytes = S->cfg.mem_budget_bytes;
     out->ticks = S->ticks;
     out->admitted = S->admitted;
@@ -595,6 +757,10 @@ void svr_serve_destroy(svr_server *S) {
     (void)hipSetDevice(S->device);
     for (hipStream_t st : S->streams) (void)hipStreamSynchronize(st);
     for (auto &kv : S->reqs) release(S, kv.second.get(), true);
+    while (!S->mats.empty()) {  // the idle matrices
+        S->idle_matrix_bytes -= S->mats.front().bytes;
+        destroy_matrix_entry(S, &S->mats.front(), true);
+    }
     if (!S->streams.empty()) {
         trim_cache(S, 0);
         (void)hipStreamSynchronize(S->streams[0]);

@@ -299,3 +299,38 @@ def test_many_concurrent_admissions_match_requests_alone(batch):
         assert mixed[i]["status"] == 0 and alone["status"] == 0
         np.testing.assert_array_equal(mixed[i]["f"], alone["f"])
         assert mixed[i]["phi"] == alone["phi"]
+
+
+@pytest.mark.parametrize("batch", [True, False])
+def test_requests_of_one_geometry_share_a_matrix(batch):
+    """Requests with the same geometry, subset count and weight type (one
+    scanner, different data) use one matrix: built once, kept idle after its
+    last user finishes and used again by a later request, while each image and
+    objective stays bitwise what a server without sharing gives."""
+    nx, V, B, Ns = 48, 40, 67, 8
+    probs = [datagen.make_problem(nx, nx, 2.0, V, B, 2.0, Ns, c, seed=700 + k)
+             for k, c in enumerate([3e4, 5e4, 8e4, 2e4, 6e4])]
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+
+    def serve(share):
+        S = pkg.Server(1 << 31, max_slots=3, n_streams=2, batch=batch, share_matrices=share)
+        tk = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS, 800 + i) for i, P in enumerate(probs[:4])]
+        S.step(0)
+        out = [S.poll(t) for t in tk]
+        st = S.stats()
+        late = S.submit(probs[4].geom, probs[4].n_subsets, probs[4].g, probs[4].w, prm, EPOCHS, 804)
+        S.step(0)
+        out.append(S.poll(late))
+        st2 = S.stats()
+        S.close()
+        return out, st, st2
+
+    shared, st, st2 = serve(True)
+    own, st_own, st_own2 = serve(False)
+    assert st["matrix_reuses"] == 3 and st2["matrix_reuses"] == 4  # one build for all five
+    assert st["used_bytes"] == 0 and st["cached_bytes"] > 0
+    assert st_own["matrix_reuses"] == 0 and st_own2["matrix_reuses"] == 0
+    for a, b in zip(shared, own):
+        assert a["status"] == 0 and b["status"] == 0
+        np.testing.assert_array_equal(a["f"], b["f"])
+        assert a["phi"] == b["phi"]
