@@ -4,11 +4,16 @@
 // updates for every resident request (batched: one forward and one update
 // launch per iteration for all requests of the same storage types; else each
 // request on one of the server's streams), then admits queued requests (FIFO)
-// while a slot is free and their device footprint fits the memory budget
-// (their matrix builds and initial epochs overlap the enqueued epochs).  A request's kernels touch only its own
-// buffers and every reduction has a fixed order, so its result is the same
-// whichever requests share the device with it.  Finished requests release
-// their memory, which lets the next queued ones in.
+// while a slot is free and their device footprint fits the memory budget.
+// The admissions of a tick run on host threads, one per request, so their
+// matrix builds (which wait on the host for their sizes) and initial epochs
+// overlap each other and the enqueued epochs; requests of one geometry,
+// subset count and weight type share one matrix, built once.  A request's
+// kernels write only its own buffers and every reduction has a fixed order,
+// so its result is the same whichever requests share the device (or its
+// matrix) with it.  Finished requests hand their blocks to the server's block
+// cache and their matrix, once unused, stays idle for later requests of its
+// key; both give way when an admission needs the room in the budget.
 #include <algorithm>
 #include <chrono>
 #include <cmath>
@@ -145,8 +150,7 @@ using namespace svr;
 
 namespace {
 
-// Frees q's device objects.  keep: every stream has finished with them, and their blocks stay
-// in the server's cache; else they are freed, stream-ordered on q's stream.
+// Destroys the entry's matrix (blocks kept in the server's cache when keep) and drops the entry.
 void destroy_matrix_entry(svr_server *S, SharedMatrix *m, bool keep) {
     BlockCacheScope sc(&S->cache, keep);
     if (m->A) svr_matrix_destroy(m->A);
@@ -158,8 +162,8 @@ void destroy_matrix_entry(svr_server *S, SharedMatrix *m, bool keep) {
         }
 }
 
-// Drops q's use of its matrix: the matrix goes idle (kept for later requests of its key) or, with
-// sharing off or after a failed admission (keep false), is destroyed.
+// Drops q's use of its matrix; the last user's drop leaves the matrix idle (kept for later
+// requests of its key) or, without sharing, destroys it.
 void unref_matrix(svr_server *S, Request *q, bool keep) {
     SharedMatrix *m = q->shared;
     q->shared = nullptr;
@@ -186,6 +190,8 @@ bool evict_idle_matrix(svr_server *S, const SharedMatrix *except) {
     return true;
 }
 
+// Frees q's device objects.  keep: every stream has finished with them, and their blocks stay
+// in the server's cache; else they are freed, stream-ordered on q's stream.
 void release(svr_server *S, Request *q, bool keep) {
     TraceRange tr("svr.serve.release");
     BlockCacheScope sc(&S->cache, keep);
