@@ -37,6 +37,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+def settle_gc():
+    """Collects garbage and moves every object alive now (modules, the set-up's
+    data) out of the collector's generations (gc.freeze), so that a full
+    collection inside a timed region scans only what the region itself
+    creates.  With torch and numpy loaded a full collection otherwise takes
+    35-45 ms, as long as 150 headline steps, and whether one lands in the
+    region depends on how many objects the process has made before it."""
+    import gc
+    gc.collect()
+    gc.freeze()
+
+
 def kernel_source_hash():
     """Hash of the kernel sources and the device compile flags: a profile taken
     under another hash describes other machine code."""
@@ -278,6 +290,7 @@ def main():
     total = args.warmup + 2 * args.steps
     orders = [datagen.make_order(Ns, per, seed=100 + i) for i in range(total)]
 
+    settle_gc()
     for i in range(args.warmup):
         R.svrem_epoch(orders[i])
     torch.cuda.synchronize()
@@ -447,6 +460,7 @@ def bench_algos(args):
         for i in range(5):
             R.epoch(algo, orders[i])
         times = []
+        settle_gc()
         for r in range(reps):
             torch.cuda.synchronize()
             t0 = time.perf_counter()
@@ -497,6 +511,7 @@ def bench_small(args):
     R = pkg.Recon(A, P.g, P.w, np.ones((1, N), np.float32), pkg.params("svrem", alpha=0.7, eta=1, beta=1e-2))
     for _ in range(5):
         R.osem_epoch(cyc)
+    settle_gc()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(calls):
@@ -506,6 +521,7 @@ def bench_small(args):
     orders = [datagen.make_order(Ns, Ns, seed=500 + i) for i in range(calls + 5)]
     for i in range(5):
         R.svrem_epoch(orders[i])
+    settle_gc()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(calls):
@@ -629,6 +645,7 @@ def bench_precision(args):
         extra = [datagen.make_order(Ns, Ns, seed=8000 + i) for i in range(steps + 5)]
         for o in extra[:5]:
             R.svrem_epoch(o)
+        settle_gc()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for o in extra[5:]:
@@ -707,6 +724,7 @@ def bench_multislice(args):
     orders = [datagen.make_order(Ns, per, seed=700 + i) for i in range(args.warmup + 2 * steps)]
     for i in range(args.warmup):
         R.svrem_epoch(orders[i])
+    settle_gc()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for i in range(steps):
@@ -772,6 +790,7 @@ def serve_latency(specs, data, alpha, share=True, rate=None):
         order = np.argsort(arrivals)
         done, owner = {}, {}  # owner: pending ticket -> request index
         nxt = 0
+        settle_gc()
         t0 = time.perf_counter()
         while len(done) < n:
             now = time.perf_counter() - t0
@@ -830,6 +849,7 @@ def serve_compare(specs, data, alpha):
 
     def per_request():
         out = []
+        settle_gc()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for i, P in enumerate(data):
@@ -844,6 +864,7 @@ def serve_compare(specs, data, alpha):
 
     def served(wtype, batch=True):
         S = pkg.Server(64 << 30, max_slots=16, n_streams=8, batch=batch)
+        settle_gc()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         tickets = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, epochs[i], 1000 + i, wtype=wtype)
