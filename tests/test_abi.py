@@ -56,6 +56,19 @@ def test_null_arguments_are_rejected(L):
     L.svr_serve_destroy(None)
 
 
+def test_invalid_server_config_is_rejected(L):
+    """svr_serve_create checks its configuration before it touches a device:
+    budget, slots, streams, and the 0/1 switches batch and share_matrices."""
+    h = C.c_void_p()
+    good = dict(mem_budget_bytes=1 << 30, max_slots=2, n_streams=1, batch=1, share_matrices=1)
+    for field, bad in [("mem_budget_bytes", 0), ("max_slots", 0), ("n_streams", 0), ("batch", 2),
+                       ("share_matrices", 2), ("share_matrices", -1)]:
+        cfg = binding.svr_serve_config(**dict(good, **{field: bad}))
+        assert L.svr_serve_create(C.byref(cfg), C.byref(h)) == binding.SVR_EINVAL, field
+        assert h.value is None
+        assert L.svr_last_error()
+
+
 def test_invalid_geometry_is_rejected(L):
     h = C.c_void_p()
     for g in (binding.svr_geometry(0, 4, 1.0, 4, 5, 1.0, 3.14),
