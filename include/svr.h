@@ -364,7 +364,8 @@ int svr_recon_kernel_times(svr_recon *R, svr_kernel_times_t *out);
  * subset iterations of all resident requests with the same weight and index
  * types run as one forward and one update launch per iteration (work items
  * (request, row block) and (request, pixel block), up to 8 requests a launch;
- * anchor iterations run per request); with batch = 0 each request's epoch is
+ * the requests at an anchor as one whole forward, one table and one
+ * anchor-sums + update launch); with batch = 0 each request's epoch is
  * enqueued on one of the streams so that requests overlap.  A request's
  * result does not depend on which other requests share the device, nor on
  * batch. */

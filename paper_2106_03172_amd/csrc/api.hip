@@ -452,6 +452,30 @@ int run_anchor_plan(svr_recon *R, IterPlan &p, hipStream_t s) { return anchor_it
 
 void end_iteration(svr_recon *R) { advance_iteration(R, R->p.algo); }
 
+int plan_anchor(svr_recon *R, IterPlan &p, SnapArgs *sa) {
+    SVR_REQUIRE(R && sa && p.anchor && p.kind == UPD_SVREM,
+                "batched anchor passes are for SVREM iteration plans at an anchor");
+    const Matrix &A = *R->A;
+    // the arguments anchor_iteration gives its whole forward pass, table and sums
+    p.fa = FwdArgs{R->ft, R->g, R->w, R->ratio, nullptr, nullptr};
+    p.fa.eps = ll_eps_of(R, p.kind);
+    p.r0 = 0;
+    p.r1 = A.M;
+    p.pair = forward_pairs_for(A.M, A.pair_rows_eff());
+    *sa = SnapArgs{};
+    sa->ratio_all = R->ratio;
+    sa->f = R->f[R->cur];
+    sa->table = R->table;
+    sa->s_anc = R->s_anc;
+    sa->s_hat = R->s_hat;
+    sa->init_shat = (R->k == 0) || (R->p.flags & SVR_FLAG_RESET_SHAT_AT_ANCHOR);
+    sa->g_tilde = R->g_tilde;
+    sa->Q = R->Q;
+    sa->pen = pen_of(R);
+    R->n_snap++;
+    return SVR_OK;
+}
+
 int objective_enqueue(svr_recon *R, hipStream_t s, ObjectiveHost *out) {
     const Matrix &A = *R->A;
     SVR_HIP(hipMemsetAsync(R->bad, 0, sizeof(int), s));

@@ -13,14 +13,14 @@ struct svr_recon;
 namespace svr {
 
 // The next iteration of a single-slice recon on subset t: either an anchor
-// (or table fill), which runs on its own (run_anchor_plan), or the arguments
-// of the subset forward and update.  end_iteration advances the recon after
-// either.
+// (or table fill; run_anchor_plan runs it on its own, plan_anchor below
+// prepares an SVREM one for the batched launches), or the arguments of the
+// subset forward and update.  end_iteration advances the recon after either.
 struct IterPlan {
     const Matrix *A;
     int kind;
     bool anchor;
-    int r0, r1;  // rows of subset t
+    int r0, r1;  // rows of subset t (all rows once plan_anchor has run)
     bool pair;   // the forward pass runs a pair of rows per wavefront
     FwdArgs fa;
     UpdateArgs u;
@@ -63,6 +63,44 @@ struct UpdBatch {
     int blocks;
     UpdItem it[BATCH_MAX];
 };
+
+// SVREM anchors, batched the same way: plan_anchor turns an iteration plan at an anchor into the
+// whole forward pass (p.fa, p.r0 = 0, p.r1 = M, p.pair; add_forward takes it) and the anchor's
+// table and sums arguments; the table (one BP_G-lane group per (subset, pixel)) and the anchor
+// sums + first update (a thread per pixel) then run as one launch each for several requests,
+// through the device functions of the request's own anchor pass.
+struct AncTabItem {
+    const int *ptrT;
+    const void *rowT;
+    const void *valT;
+    const int *row_start;
+    int Ns, N;
+    int blk0;
+    SnapArgs a;
+};
+struct AncTabBatch {
+    int n;
+    int blocks;
+    AncTabItem it[BATCH_MAX];
+};
+struct AncSumItem {
+    const float *sens_t;
+    const double *sens;
+    int Ns, N;
+    int blk0;
+    SnapArgs a;
+    UpdateArgs u;
+};
+struct AncSumBatch {
+    int n;
+    int blocks;
+    AncSumItem it[BATCH_MAX];
+};
+int plan_anchor(svr_recon *R, IterPlan &p, SnapArgs *sa);
+void add_anchor_table(AncTabBatch &b, const IterPlan &p, const SnapArgs &sa);
+void add_anchor_sum(AncSumBatch &b, const IterPlan &p, const SnapArgs &sa);
+int launch_anchor_table_batch(const Matrix &types, const AncTabBatch &b, hipStream_t s);
+int launch_anchor_sum_batch(const AncSumBatch &b, hipStream_t s);
 
 // Appends the plan's forward (update) work to the batch; the matrices of one
 // batch share their weight and index types.

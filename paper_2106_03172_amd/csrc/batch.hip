@@ -45,6 +45,69 @@ __global__ void __launch_bounds__(BP_THREADS) k_update_batch(UpdBatch b) {
                                     n, lig);
 }
 
+// SVREM anchor table of each item: one BP_G-lane group per (subset, pixel)
+template <typename WT, typename IT>
+__global__ void __launch_bounds__(BP_THREADS) k_anchor_table_batch(AncTabBatch b) {
+    const AncTabItem &it = b.it[item_of(b)];
+    const int64_t gid = (int64_t)((int)blockIdx.x - it.blk0) * BP_THREADS + threadIdx.x;
+    const int64_t q = gid / BP_G;
+    const int lig = (int)(gid % BP_G);
+    if (q >= (int64_t)it.Ns * it.N) return;  // whole groups leave together
+    anchor_entry<UPD_SVREM, WT, IT>(it.ptrT, (const IT *)it.rowT, (const WT *)it.valT, it.row_start, it.Ns, it.N,
+                                    it.a, q, lig);
+}
+
+// SVREM anchor sums + the first update of each item: a thread per pixel
+__global__ void __launch_bounds__(256) k_anchor_sum_batch(AncSumBatch b) {
+    const AncSumItem &it = b.it[item_of(b)];
+    const int n = ((int)blockIdx.x - it.blk0) * 256 + threadIdx.x;
+    if (n >= it.N) return;
+    anchor_sum_update_pixel<UPD_SVREM>(it.sens_t, it.sens, it.Ns, it.N, it.a, it.u, n);
+}
+
+void add_anchor_table(AncTabBatch &b, const IterPlan &p, const SnapArgs &sa) {
+    const Matrix &A = *p.A;
+    AncTabItem &it = b.it[b.n++];
+    it.ptrT = A.d_ptrT;
+    it.rowT = A.d_rowT;
+    it.valT = A.d_valT;
+    it.row_start = A.d_row_start;
+    it.Ns = A.Ns;
+    it.N = A.N;
+    it.blk0 = b.blocks;
+    it.a = sa;
+    b.blocks += (int)(((int64_t)A.Ns * A.N * BP_G + BP_THREADS - 1) / BP_THREADS);
+}
+
+void add_anchor_sum(AncSumBatch &b, const IterPlan &p, const SnapArgs &sa) {
+    const Matrix &A = *p.A;
+    AncSumItem &it = b.it[b.n++];
+    it.sens_t = A.d_sens_t;
+    it.sens = A.d_sens;
+    it.Ns = A.Ns;
+    it.N = A.N;
+    it.blk0 = b.blocks;
+    it.a = sa;
+    it.u = p.u;
+    b.blocks += (A.N + 255) / 256;
+}
+
+int launch_anchor_table_batch(const Matrix &types, const AncTabBatch &b, hipStream_t s) {
+    if (b.n == 0 || b.blocks == 0) return SVR_OK;
+    return with_types(types, [&](auto w, auto i) {
+        using WT = decltype(w);
+        using IT = decltype(i);
+        SVR_HIP(launch_k(k_anchor_table_batch<WT, IT>, b.blocks, BP_THREADS, s, b));
+        return SVR_OK;
+    });
+}
+
+int launch_anchor_sum_batch(const AncSumBatch &b, hipStream_t s) {
+    if (b.n == 0 || b.blocks == 0) return SVR_OK;
+    SVR_HIP(launch_k(k_anchor_sum_batch, b.blocks, 256, s, b));
+    return SVR_OK;
+}
+
 void add_forward(FwdBatch &b, const IterPlan &p) {
     const Matrix &A = *p.A;
     FwdItem &it = b.it[b.n++];

@@ -295,10 +295,11 @@ void run_each(svr_server *S, const std::vector<Request *> &adm, std::vector<int>
 }
 
 // One epoch of every resident request with the subset iterations batched:
-// for each iteration index, the requests at an anchor take it on their own;
-// the others run as one forward and one update launch per group of requests
-// with the same weight and index types (up to BATCH_MAX a launch), all on
-// the first stream.
+// for each iteration index, the requests at an anchor run as one whole-matrix
+// forward, one table and one anchor-sums + update launch per group of requests
+// with the same weight and index types, the others as one forward and one
+// update launch per group (up to BATCH_MAX requests a launch), all on the
+// first stream.
 void batched_epoch(svr_server *S) {
     TraceRange tr("svr.serve.batched_epoch");
     hipStream_t s0 = S->streams[0];
@@ -317,7 +318,8 @@ void batched_epoch(svr_server *S) {
         rs.push_back(std::move(r));
     }
     for (int j = 0; j < max_ns; ++j) {
-        std::map<int, std::vector<std::pair<Request *, IterPlan>>> groups;  // key: weight type, index width
+        // key: weight type, index width
+        std::map<int, std::vector<std::pair<Request *, IterPlan>>> groups, anchors;
         for (Res &r : rs) {
             Request *q = r.q;
             if (j >= (int)r.order.size() || q->status != SVR_OK) continue;
@@ -327,13 +329,38 @@ void batched_epoch(svr_server *S) {
                 q->status = rc;
                 continue;
             }
-            if (pl.anchor) {
-                rc = run_anchor_plan(q->R, pl, s0);
-                if (rc) q->status = rc;
-                end_iteration(q->R);
-                continue;
+            (pl.anchor ? anchors : groups)[pl.A->wtype * 2 + pl.A->idx16].push_back({q, pl});
+        }
+        // the requests at an anchor: the whole forward pass, the table and the anchor sums with
+        // the first update, each one launch per group (up to BATCH_MAX requests)
+        for (auto &kv : anchors) {
+            auto &v = kv.second;
+            for (size_t c = 0; c < v.size(); c += BATCH_MAX) {
+                const size_t e = std::min(v.size(), c + BATCH_MAX);
+                FwdBatch fb{};
+                AncTabBatch tb{};
+                AncSumBatch sb{};
+                std::vector<Request *> in;
+                for (size_t i = c; i < e; ++i) {
+                    SnapArgs sa;
+                    const int rc = plan_anchor(v[i].first->R, v[i].second, &sa);
+                    if (rc) {
+                        v[i].first->status = rc;
+                        continue;
+                    }
+                    add_forward(fb, v[i].second);
+                    add_anchor_table(tb, v[i].second, sa);
+                    add_anchor_sum(sb, v[i].second, sa);
+                    in.push_back(v[i].first);
+                }
+                const Matrix &types = *v[c].second.A;
+                int rc = launch_forward_batch(types, fb, s0);
+                if (!rc) rc = launch_anchor_table_batch(types, tb, s0);
+                if (!rc) rc = launch_anchor_sum_batch(sb, s0);
+                if (rc)
+                    for (Request *q : in) q->status = rc;
             }
-            groups[pl.A->wtype * 2 + pl.A->idx16].push_back({q, pl});
+            for (auto &qp : v) end_iteration(qp.first->R);
         }
         for (auto &kv : groups) {
             auto &v = kv.second;
