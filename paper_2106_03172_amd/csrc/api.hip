@@ -448,8 +448,6 @@ int plan_iteration(svr_recon *R, int t, IterPlan *p) {
     return SVR_OK;
 }
 
-int run_anchor_plan(svr_recon *R, IterPlan &p, hipStream_t s) { return anchor_iteration(R, p.kind, p.u, s); }
-
 void end_iteration(svr_recon *R) { advance_iteration(R, R->p.algo); }
 
 int plan_anchor(svr_recon *R, IterPlan &p, SnapArgs *sa) {

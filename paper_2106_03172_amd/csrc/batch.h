@@ -13,9 +13,9 @@ struct svr_recon;
 namespace svr {
 
 // The next iteration of a single-slice recon on subset t: either an anchor
-// (or table fill; run_anchor_plan runs it on its own, plan_anchor below
-// prepares an SVREM one for the batched launches), or the arguments of the
-// subset forward and update.  end_iteration advances the recon after either.
+// (or table fill; plan_anchor below prepares an SVREM one for the batched
+// launches), or the arguments of the subset forward and update.
+// end_iteration advances the recon after either.
 struct IterPlan {
     const Matrix *A;
     int kind;
@@ -26,7 +26,6 @@ struct IterPlan {
     UpdateArgs u;
 };
 int plan_iteration(svr_recon *R, int t, IterPlan *p);
-int run_anchor_plan(svr_recon *R, IterPlan &p, hipStream_t s);
 void end_iteration(svr_recon *R);
 
 // Requests per batched launch (their arguments travel in the kernel
