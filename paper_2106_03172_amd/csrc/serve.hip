@@ -298,11 +298,13 @@ void run_each(svr_server *S, const std::vector<Request *> &adm, std::vector<int>
 // for each iteration index, the requests at an anchor run as one whole-matrix
 // forward, one table and one anchor-sums + update launch per group of requests
 // with the same weight and index types, the others as one forward and one
-// update launch per group (up to BATCH_MAX requests a launch), all on the
-// first stream.
+// update launch per group (up to BATCH_MAX requests a launch); each group's
+// launches go to one stream, the groups' to different ones.
 void batched_epoch(svr_server *S) {
     TraceRange tr("svr.serve.batched_epoch");
-    hipStream_t s0 = S->streams[0];
+    // each storage-type group on a stream of its own (the same one all tick, so a request's
+    // iterations stay in order), so that the groups' launches overlap
+    auto stream_of = [S](int key) { return S->streams[key % (int)S->streams.size()]; };
     struct Res {
         Request *q;
         std::vector<int32_t> order;
@@ -354,9 +356,10 @@ void batched_epoch(svr_server *S) {
                     in.push_back(v[i].first);
                 }
                 const Matrix &types = *v[c].second.A;
-                int rc = launch_forward_batch(types, fb, s0);
-                if (!rc) rc = launch_anchor_table_batch(types, tb, s0);
-                if (!rc) rc = launch_anchor_sum_batch(sb, s0);
+                hipStream_t sg = stream_of(kv.first);
+                int rc = launch_forward_batch(types, fb, sg);
+                if (!rc) rc = launch_anchor_table_batch(types, tb, sg);
+                if (!rc) rc = launch_anchor_sum_batch(sb, sg);
                 if (rc)
                     for (Request *q : in) q->status = rc;
             }
@@ -368,7 +371,7 @@ void batched_epoch(svr_server *S) {
                 const size_t e = std::min(v.size(), c + BATCH_MAX);
                 FwdBatch fb{};
                 for (size_t i = c; i < e; ++i) add_forward(fb, v[i].second);
-                const int rc = launch_forward_batch(*v[c].second.A, fb, s0);
+                const int rc = launch_forward_batch(*v[c].second.A, fb, stream_of(kv.first));
                 if (rc)
                     for (size_t i = c; i < e; ++i) v[i].first->status = rc;
             }
@@ -376,7 +379,7 @@ void batched_epoch(svr_server *S) {
                 const size_t e = std::min(v.size(), c + BATCH_MAX);
                 UpdBatch ub{};
                 for (size_t i = c; i < e; ++i) add_update(ub, v[i].second);
-                const int rc = launch_update_batch(*v[c].second.A, ub, s0);
+                const int rc = launch_update_batch(*v[c].second.A, ub, stream_of(kv.first));
                 if (rc)
                     for (size_t i = c; i < e; ++i) v[i].first->status = rc;
             }
