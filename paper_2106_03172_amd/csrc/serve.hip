@@ -298,27 +298,35 @@ void run_each(svr_server *S, const std::vector<Request *> &adm, std::vector<int>
 // for each iteration index, the requests at an anchor run as one whole-matrix
 // forward, one table and one anchor-sums + update launch per group of requests
 // with the same weight and index types, the others as one forward and one
-// update launch per group (up to BATCH_MAX requests a launch); each group's
-// launches go to one stream, the groups' to different ones.
+// update launch per batch (the requests of one storage type, up to BATCH_MAX a
+// batch); each batch's launches go to one stream, different batches' to
+// different ones.
 void batched_epoch(svr_server *S) {
     TraceRange tr("svr.serve.batched_epoch");
-    // each storage-type group on a stream of its own (the same one all tick, so a request's
-    // iterations stay in order), so that the groups' launches overlap
-    auto stream_of = [S](int key) { return S->streams[key % (int)S->streams.size()]; };
+    // The requests of one storage type (weight type, index width) split into batches of up to
+    // BATCH_MAX, fixed for the tick; each batch takes a stream of its own for the whole tick, so
+    // a request's iterations stay in order while different batches' launches overlap.
     struct Res {
         Request *q;
         std::vector<int32_t> order;
+        int batch;  // key: storage type * 64 + the batch's index within its storage type
     };
     std::vector<Res> rs;
+    std::map<int, int> per_type;
+    std::map<int, int> stream_of_batch;
     int max_ns = 0;
     for (uint64_t tk : S->resident) {
         Request *q = S->reqs[tk].get();
         const int Ns = q->req.n_subsets;
-        Res r{q, std::vector<int32_t>(Ns)};
+        const Matrix &A = *q->A;
+        const int type = A.wtype * 2 + A.idx16;
+        Res r{q, std::vector<int32_t>(Ns), type * 64 + per_type[type]++ / BATCH_MAX};
         for (int i = 0; i < Ns; ++i) r.order[i] = q->rng.below(Ns);
+        if (!stream_of_batch.count(r.batch)) stream_of_batch[r.batch] = (int)stream_of_batch.size();
         max_ns = std::max(max_ns, Ns);
         rs.push_back(std::move(r));
     }
+    auto stream_of = [&](int batch) { return S->streams[stream_of_batch[batch] % (int)S->streams.size()]; };
     for (int j = 0; j < max_ns; ++j) {
         // key: weight type, index width
         std::map<int, std::vector<std::pair<Request *, IterPlan>>> groups, anchors;
@@ -331,7 +339,7 @@ void batched_epoch(svr_server *S) {
                 q->status = rc;
                 continue;
             }
-            (pl.anchor ? anchors : groups)[pl.A->wtype * 2 + pl.A->idx16].push_back({q, pl});
+            (pl.anchor ? anchors : groups)[r.batch].push_back({q, pl});
         }
         // the requests at an anchor: the whole forward pass, the table and the anchor sums with
         // the first update, each one launch per group (up to BATCH_MAX requests)
