@@ -334,3 +334,29 @@ def test_requests_of_one_geometry_share_a_matrix(batch):
         assert a["status"] == 0 and b["status"] == 0
         np.testing.assert_array_equal(a["f"], b["f"])
         assert a["phi"] == b["phi"]
+
+
+@pytest.mark.parametrize("eta", [1, 2])
+def test_batched_anchors_equal_direct_recons(eta):
+    """Three requests of one storage type (so their anchors run as shared
+    batched launches) with anchors every eta epochs end bitwise as the same
+    requests run through the direct epoch calls with the server's subset
+    sequences (the anchor of the first iteration of every eta-th epoch)."""
+    specs = [SPECS[0], SPECS[1], SPECS[3]]
+    probs = [_req(s) for s in specs]
+    prm = pkg.params("svrem", alpha=ALPHA, eta=eta, beta=BETA)
+    epochs = 2 * eta + 1
+    S = pkg.Server(1 << 31, max_slots=3, n_streams=2)
+    tk = [S.submit(P.geom, P.n_subsets, P.g, P.w, prm, epochs, 910 + i) for i, P in enumerate(probs)]
+    S.step(0)
+    served = [S.poll(t) for t in tk]
+    S.close()
+    for i, P in enumerate(probs):
+        A = pkg.SystemMatrix(P.geom, P.n_subsets)
+        R = pkg.Recon(A, P.g, P.w, np.ones((1, P.geom.n_pixels)), prm)
+        R.osem_epoch(list(range(P.n_subsets)))
+        for o in pkg.splitmix64_orders(910 + i, P.n_subsets, epochs):
+            R.svrem_epoch(o)
+        assert served[i]["status"] == 0
+        np.testing.assert_array_equal(served[i]["f"], R.image().cpu().numpy()[0])
+        assert served[i]["phi"] == R.objective()
