@@ -444,6 +444,12 @@ typedef struct {
 } svr_serve_stats_t;
 /* Errors: SVR_EINVAL (NULL argument). */
 int  svr_serve_stats(const svr_server *S, svr_serve_stats_t *out);
+/* Gives back device memory the server keeps for later admissions: with
+ * drop_matrices = 1 every idle matrix (a later request of its key builds it
+ * again; its blocks join the kept blocks), then kept blocks beyond keep_bytes
+ * (freed stream-ordered).  Memory of resident requests is untouched.
+ * Errors: SVR_EINVAL (NULL server, drop_matrices not 0/1, keep_bytes < 0). */
+int  svr_serve_trim(svr_server *S, int32_t drop_matrices, int64_t keep_bytes);
 
 #ifdef __cplusplus
 }

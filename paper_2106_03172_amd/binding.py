@@ -128,6 +128,7 @@ _SIGS = {
     "svr_serve_destroy": ([_VP], None),
     "svr_serve_stats": ([_VP, C.POINTER(svr_serve_stats_t)], C.c_int),
     "svr_serve_done": ([_VP, C.POINTER(C.c_uint64), _I32, C.POINTER(_I32)], C.c_int),
+    "svr_serve_trim": ([_VP, _I32, _I64], C.c_int),
 }
 for _e in ("osem", "svrem", "svrg", "saga", "sga", "bsrem", "sem"):
     _SIGS[f"svr_{_e}_epoch"] = ([_VP, _VP, _I32, _VP], C.c_int)
@@ -510,6 +511,11 @@ class Server:
         n = C.c_int32()
         _check(lib().svr_serve_done(self.h, buf, int(cap), C.byref(n)))
         return list(buf[:n.value])
+
+    def trim(self, drop_matrices: bool = True, keep_bytes: int = 0):
+        """Gives back kept device memory (svr_serve_trim): idle matrices, then kept blocks beyond
+        ``keep_bytes``."""
+        _check(lib().svr_serve_trim(self.h, 1 if drop_matrices else 0, int(keep_bytes)))
 
     def stats(self) -> dict:
         """Queue depth, slots in use, device memory held and running totals (svr_serve_stats)."""

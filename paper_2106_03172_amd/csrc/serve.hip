@@ -775,6 +775,19 @@ int svr_serve_cancel(svr_server *S, uint64_t ticket) {
     return SVR_OK;
 }
 
+int svr_serve_trim(svr_server *S, int32_t drop_matrices, int64_t keep_bytes) {
+    clear_error();
+    SVR_REQUIRE(S, "NULL server");
+    SVR_REQUIRE(drop_matrices == 0 || drop_matrices == 1, "drop_matrices must be 0 or 1");
+    SVR_REQUIRE(keep_bytes >= 0, "keep_bytes must be >= 0");
+    SVR_HIP(hipSetDevice(S->device));
+    if (drop_matrices)
+        while (evict_idle_matrix(S, nullptr)) {
+        }
+    trim_cache(S, keep_bytes);
+    return SVR_OK;
+}
+
 int svr_serve_stats(const svr_server *S, svr_serve_stats_t *out) {
     clear_error();
     SVR_REQUIRE(S && out, "NULL argument");

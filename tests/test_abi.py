@@ -50,6 +50,7 @@ def test_null_arguments_are_rejected(L):
     assert L.svr_serve_stats(None, None) == binding.SVR_EINVAL
     n = C.c_int32(7)
     assert L.svr_serve_done(None, None, 0, C.byref(n)) == binding.SVR_EINVAL
+    assert L.svr_serve_trim(None, 1, 0) == binding.SVR_EINVAL
     assert L.svr_osem_epoch(None, None, 0, None) == binding.SVR_EINVAL
     L.svr_matrix_destroy(None)
     L.svr_recon_destroy(None)

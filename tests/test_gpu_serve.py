@@ -360,3 +360,30 @@ def test_batched_anchors_equal_direct_recons(eta):
         assert served[i]["status"] == 0
         np.testing.assert_array_equal(served[i]["f"], R.image().cpu().numpy()[0])
         assert served[i]["phi"] == R.objective()
+
+
+def test_trim_drops_idle_matrices_and_kept_blocks():
+    """svr_serve_trim: dropping the idle matrices makes the next request of
+    that key build its own (no reuse counted) with the same result; trimming
+    the kept blocks to 0 leaves nothing cached; bad arguments are rejected."""
+    P = _req(SPECS[1])
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+    S = pkg.Server(1 << 31, max_slots=2, n_streams=2)
+    t = S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS, 5)
+    S.step(0)
+    first = S.poll(t)
+    assert S.stats()["cached_bytes"] > 0
+    S.trim(drop_matrices=True, keep_bytes=1 << 40)
+    st = S.stats()
+    assert st["cached_bytes"] > 0 and st["matrix_reuses"] == 0  # the matrix's blocks now kept as blocks
+    t = S.submit(P.geom, P.n_subsets, P.g, P.w, prm, EPOCHS, 5)
+    S.step(0)
+    again = S.poll(t)
+    st = S.stats()
+    assert st["matrix_reuses"] == 0 and st["block_reuses"] > 0
+    np.testing.assert_array_equal(first["f"], again["f"])
+    S.trim(drop_matrices=True, keep_bytes=0)
+    assert S.stats()["cached_bytes"] == 0
+    with pytest.raises(pkg.binding.SvrError):
+        S.trim(drop_matrices=True, keep_bytes=-1)
+    S.close()
