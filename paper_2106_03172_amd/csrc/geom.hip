@@ -153,13 +153,31 @@ __global__ void k_col_count(int M, int B, int Ns, int N, const int *row_sino, co
     for (int i = row_ptr[r] + lane; i < row_ptr[r + 1]; i += 64) slot[i] = atomicAdd(&c[col[i]], 1);
 }
 
+// A transposed entry between the fill and the ranking: its subset-local row
+// in the low 32 bits, its weight's bits in the high ones, so that the fill's
+// scattered writes are one 8-byte store per entry
+template <typename WT>
+__device__ inline uint64_t pack_entry(int row, WT v) {
+    uint32_t bits;
+    if constexpr (sizeof(WT) == 4) bits = __builtin_bit_cast(uint32_t, v);
+    else bits = (uint32_t)__builtin_bit_cast(uint16_t, v);
+    return (uint64_t)(uint32_t)row | ((uint64_t)bits << 32);
+}
+__device__ inline int entry_row(uint64_t e) { return (int)(uint32_t)e; }
+template <typename WT>
+__device__ inline WT entry_val(uint64_t e) {
+    const uint32_t bits = (uint32_t)(e >> 32);
+    if constexpr (sizeof(WT) == 4) return __builtin_bit_cast(WT, bits);
+    else return __builtin_bit_cast(WT, (uint16_t)bits);
+}
+
 // every entry of A into its transposed row at the slot k_col_count gave it
 // (k_rank_T orders each row afterwards); a wavefront per row of A, lanes over
 // its entries
 template <typename WT>
 __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const int *row_start,
                          const int *row_ptr, const int *col, const WT *val, const int *ptrT,
-                         const int *slot, int *rowT, WT *valT) {
+                         const int *slot, uint64_t *fill) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = (int)(gid >> 6), lane = (int)(gid & 63);
     if (r >= M) return;
@@ -167,9 +185,7 @@ __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const
     const int local = r - row_start[t];
     const int64_t base = (int64_t)t * N;
     for (int i = row_ptr[r] + lane; i < row_ptr[r + 1]; i += 64) {
-        const int p = ptrT[base + col[i]] + slot[i];
-        rowT[p] = local;
-        valT[p] = val[i];
+        fill[ptrT[base + col[i]] + slot[i]] = pack_entry(local, val[i]);
     }
 }
 
@@ -191,7 +207,7 @@ __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const
 constexpr int RANK_ROWS = SVR_RANK_ROWS;
 template <typename WT, int R>
 __global__ void __launch_bounds__(256)
-k_rank_T(int64_t nrows, const int *ptrT, const int *keys, const WT *vals, int *rowT, WT *valT) {
+k_rank_T(int64_t nrows, const int *ptrT, const uint64_t *fill, int *rowT, WT *valT) {
     const int lane = threadIdx.x & 63, h = lane >> 5, gl = lane & 31;
     const int64_t q0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5) * R;
     const int pv = (gl <= R && q0 + gl <= nrows) ? ptrT[q0 + gl] : 0;  // row bounds, one per lane
@@ -207,8 +223,9 @@ k_rank_T(int64_t nrows, const int *ptrT, const int *keys, const WT *vals, int *r
 #pragma unroll
     for (int r = 0; r < R; ++r) {
         const bool has = gl < len[r];
-        key[r] = has ? keys[beg[r] + gl] : INT_MAX;
-        val[r] = has ? vals[beg[r] + gl] : WT{};
+        const uint64_t ent = has ? fill[beg[r] + gl] : 0;
+        key[r] = has ? entry_row(ent) : INT_MAX;
+        val[r] = entry_val<WT>(ent);
     }
 #pragma unroll
     for (int r = 0; r < R; ++r) {
@@ -229,10 +246,11 @@ k_rank_T(int64_t nrows, const int *ptrT, const int *keys, const WT *vals, int *r
         for (int c = 0; c < lmax; c += 32) {
             const int e = c + gl;
             const bool has = e < len[r];
-            const int k = has ? keys[beg[r] + e] : INT_MAX;
+            const uint64_t ent = has ? fill[beg[r] + e] : 0;
+            const int k = has ? entry_row(ent) : INT_MAX;
             int rank = 0;
             for (int d = 0; d < lmax; d += 32) {
-                const int kd = d + gl < len[r] ? keys[beg[r] + d + gl] : INT_MAX;
+                const int kd = d + gl < len[r] ? entry_row(fill[beg[r] + d + gl]) : INT_MAX;
 #pragma unroll 8
                 for (int j = 0; j < 32; ++j) {
                     const int k0 = __builtin_amdgcn_readlane(kd, j), k1 = __builtin_amdgcn_readlane(kd, 32 + j);
@@ -241,7 +259,7 @@ k_rank_T(int64_t nrows, const int *ptrT, const int *keys, const WT *vals, int *r
             }
             if (has) {
                 rowT[beg[r] + rank] = k;
-                valT[beg[r] + rank] = vals[beg[r] + e];
+                valT[beg[r] + rank] = entry_val<WT>(ent);
             }
         }
     }
@@ -336,14 +354,13 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     const int T = 256;
     const int gM = (M + T - 1) / T;
     const int64_t NT = (int64_t)Ns * N;
-    int *counts = nullptr, *cnt = nullptr, *stats = nullptr, *fillR = nullptr;
-    WT *fillV = nullptr;
+    int *counts = nullptr, *cnt = nullptr, *stats = nullptr;
+    uint64_t *fill = nullptr;
     auto cleanup = [&]() {
         dfree(counts);
         dfree(cnt);
         dfree(stats);
-        dfree(fillR);
-        dfree(fillV);
+        dfree(fill);
     };
     SVR_HIP(dalloc(&counts, M));
     SVR_HIP(dalloc(&stats, Ns + 3));
@@ -387,17 +404,14 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     rc = exclusive_scan(cnt, NT, A.d_ptrT, &nnzT, s);
     if (rc) { cleanup(); return rc; }
     if (nnzT != nnz) { cleanup(); set_error("transpose count mismatch"); return SVR_EDEVICE; }
-    SVR_HIP(dalloc(&fillR, nnz));
-    SVR_HIP(dalloc(&fillV, nnz));
+    SVR_HIP(dalloc(&fill, nnz));
     k_fill_T<WT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
-                                  val, A.d_ptrT, slot, fillR, fillV);
+                                  val, A.d_ptrT, slot, fill);
     const int64_t groups = (NT + RANK_ROWS - 1) / RANK_ROWS;
-    k_rank_T<WT, RANK_ROWS><<<(unsigned)((groups * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, fillR, fillV, rowT,
+    k_rank_T<WT, RANK_ROWS><<<(unsigned)((groups * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, fill, rowT,
                                                                                valT);
-    dfree(fillR);
-    dfree(fillV);
-    fillR = nullptr;
-    fillV = nullptr;
+    dfree(fill);
+    fill = nullptr;
     k_sens<WT><<<(N + T - 1) / T, T, 0, s>>>(Ns, N, A.d_ptrT, valT, A.d_sens_t, A.d_sens);
     SVR_HIP(hipGetLastError());
     std::vector<int> h(Ns + 3);
