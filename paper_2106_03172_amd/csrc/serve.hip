@@ -777,6 +777,7 @@ int svr_serve_cancel(svr_server *S, uint64_t ticket) {
 
 int svr_serve_trim(svr_server *S, int32_t drop_matrices, int64_t keep_bytes) {
     clear_error();
+    TraceRange tr("svr.serve.trim");
     SVR_REQUIRE(S, "NULL server");
     SVR_REQUIRE(drop_matrices == 0 || drop_matrices == 1, "drop_matrices must be 0 or 1");
     SVR_REQUIRE(keep_bytes >= 0, "keep_bytes must be >= 0");
