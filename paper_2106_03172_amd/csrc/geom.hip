@@ -114,9 +114,9 @@ __global__ void k_siddon_count(svr_geometry g, int M, const int *row_sino, int *
     counts[r] = c;
 }
 
-template <typename WT>
+template <typename WT, typename IT>
 __global__ void k_siddon_fill(svr_geometry g, int M, const int *row_sino, const int *row_ptr,
-                              const float *mu, int *col, WT *val) {
+                              const float *mu, IT *col, WT *val) {
     int r = blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= M) return;
     int m = row_sino[r];
@@ -133,7 +133,7 @@ __global__ void k_siddon_fill(svr_geometry g, int M, const int *row_sino, const 
     trace(g, ray, [&](int pix, double seg) {
         double len = seg * pmm;
         if (mu) len = len * att;
-        col[pos] = pix;
+        col[pos] = (IT)pix;
         val[pos] = store_w<WT>(len);
         ++pos;
     });
@@ -143,8 +143,9 @@ __global__ void k_siddon_fill(svr_geometry g, int M, const int *row_sino, const 
 // entries per (subset, pixel), and each entry's arrival rank among its
 // transposed row's entries (slot, any order); a wavefront per row of A, lanes
 // over its entries
+template <typename IT>
 __global__ void k_col_count(int M, int B, int Ns, int N, const int *row_sino, const int *row_ptr,
-                            const int *col, int *cnt, int *slot) {
+                            const IT *col, int *cnt, int *slot) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = (int)(gid >> 6), lane = (int)(gid & 63);
     if (r >= M) return;
@@ -174,9 +175,9 @@ __device__ inline WT entry_val(uint64_t e) {
 // every entry of A into its transposed row at the slot k_col_count gave it
 // (k_rank_T orders each row afterwards); a wavefront per row of A, lanes over
 // its entries
-template <typename WT>
+template <typename WT, typename IT>
 __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const int *row_start,
-                         const int *row_ptr, const int *col, const WT *val, const int *ptrT,
+                         const int *row_ptr, const IT *col, const WT *val, const int *ptrT,
                          const int *slot, uint64_t *fill) {
     const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int r = (int)(gid >> 6), lane = (int)(gid & 63);
@@ -205,9 +206,9 @@ __global__ void k_fill_T(int M, int B, int Ns, int N, const int *row_sino, const
 #define SVR_RANK_ROWS 4
 #endif
 constexpr int RANK_ROWS = SVR_RANK_ROWS;
-template <typename WT, int R>
+template <typename WT, typename IT, int R>
 __global__ void __launch_bounds__(256)
-k_rank_T(int64_t nrows, const int *ptrT, const uint64_t *fill, int *rowT, WT *valT) {
+k_rank_T(int64_t nrows, const int *ptrT, const uint64_t *fill, IT *rowT, WT *valT) {
     const int lane = threadIdx.x & 63, h = lane >> 5, gl = lane & 31;
     const int64_t q0 = (((int64_t)blockIdx.x * blockDim.x + threadIdx.x) >> 5) * R;
     const int pv = (gl <= R && q0 + gl <= nrows) ? ptrT[q0 + gl] : 0;  // row bounds, one per lane
@@ -238,7 +239,7 @@ k_rank_T(int64_t nrows, const int *ptrT, const uint64_t *fill, int *rowT, WT *va
                 rank += (h ? k1 : k0) < key[r];
             }
             if (gl < len[r]) {
-                rowT[beg[r] + rank] = key[r];
+                rowT[beg[r] + rank] = (IT)key[r];
                 valT[beg[r] + rank] = val[r];
             }
             continue;
@@ -258,7 +259,7 @@ k_rank_T(int64_t nrows, const int *ptrT, const uint64_t *fill, int *rowT, WT *va
                 }
             }
             if (has) {
-                rowT[beg[r] + rank] = k;
+                rowT[beg[r] + rank] = (IT)k;
                 valT[beg[r] + rank] = entry_val<WT>(ent);
             }
         }
@@ -279,11 +280,6 @@ __global__ void k_sens(int Ns, int N, const int *ptrT, const WT *valT, float *se
         tot = tot + s;
     }
     sens[n] = tot;
-}
-
-__global__ void k_narrow(const int *src, int64_t n, uint16_t *dst) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) dst[i] = (uint16_t)src[i];
 }
 
 // stats[0] = longest row, stats[1] = longest transposed row, stats[2 + t] =
@@ -348,20 +344,27 @@ int launch_tile_image(const Matrix &A, const float *f, float *ft, hipStream_t s)
     return SVR_OK;
 }
 
-template <typename WT>
-static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
+// The build, with its index arrays (col, rowT and the tiled copy of col) of
+// type IT from the start: uint16 when every pixel index and every subset-local
+// row fits in 16 bits (the geometry fixes both before any ray is traced)
+template <typename WT, typename IT>
+static int build_indexed(Matrix &A, const float *mu, hipStream_t s) {
     const int M = A.M, N = A.N, Ns = A.Ns, B = A.geom.n_bins;
     const int T = 256;
     const int gM = (M + T - 1) / T;
     const int64_t NT = (int64_t)Ns * N;
-    int *counts = nullptr, *cnt = nullptr, *stats = nullptr;
-    uint64_t *fill = nullptr;
-    auto cleanup = [&]() {
-        dfree(counts);
-        dfree(cnt);
-        dfree(stats);
-        dfree(fill);
-    };
+    struct Temps {  // the build's temporaries, freed (stream-ordered) on every return
+        int *counts = nullptr, *cnt = nullptr, *stats = nullptr, *slot = nullptr;
+        uint64_t *fill = nullptr;
+        ~Temps() {
+            dfree(counts);
+            dfree(cnt);
+            dfree(stats);
+            dfree(slot);
+            dfree(fill);
+        }
+    } tmp;
+    int *&counts = tmp.counts, *&cnt = tmp.cnt, *&stats = tmp.stats;
     SVR_HIP(dalloc(&counts, M));
     SVR_HIP(dalloc(&stats, Ns + 3));
     SVR_HIP(hipMemsetAsync(stats, 0, sizeof(int) * (Ns + 3), s));
@@ -370,17 +373,17 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     SVR_HIP(dalloc(&A.d_row_ptr, M + 1));
     int64_t nnz = 0;
     int rc = exclusive_scan(counts, M, A.d_row_ptr, &nnz, s);  // synchronises: nnz sizes the arrays
-    if (rc) { cleanup(); return rc; }
+    if (rc) return rc;
     A.nnz = nnz;
     WT *val = nullptr, *valT = nullptr;
-    int *col = nullptr, *rowT = nullptr;
+    IT *col = nullptr, *rowT = nullptr, *colt = nullptr;
     SVR_HIP(dalloc(&col, nnz + NNZ_PAD));
     SVR_HIP(dalloc(&val, nnz + NNZ_PAD));
     SVR_HIP(dalloc(&rowT, nnz + NNZ_PAD));
     SVR_HIP(dalloc(&valT, nnz + NNZ_PAD));
-    SVR_HIP(hipMemsetAsync(col + nnz, 0, sizeof(int) * NNZ_PAD, s));
+    SVR_HIP(hipMemsetAsync(col + nnz, 0, sizeof(IT) * NNZ_PAD, s));
     SVR_HIP(hipMemsetAsync(val + nnz, 0, sizeof(WT) * NNZ_PAD, s));
-    SVR_HIP(hipMemsetAsync(rowT + nnz, 0, sizeof(int) * NNZ_PAD, s));
+    SVR_HIP(hipMemsetAsync(rowT + nnz, 0, sizeof(IT) * NNZ_PAD, s));
     SVR_HIP(hipMemsetAsync(valT + nnz, 0, sizeof(WT) * NNZ_PAD, s));
     A.d_col = col;
     A.d_rowT = rowT;
@@ -390,29 +393,42 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     SVR_HIP(dalloc(&A.d_sens, N));
     A.d_val = val;
     A.d_valT = valT;
-    k_siddon_fill<WT><<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, A.d_row_ptr, mu, col, val);
+    k_siddon_fill<WT, IT><<<gM, T, 0, s>>>(A.geom, M, A.d_row_sino, A.d_row_ptr, mu, col, val);
     k_row_stats<<<std::min<unsigned>(gM, MAX_BLOCKS), T, 0, s>>>(M, A.d_row_ptr, stats);
     k_subset_offsets<<<(Ns + 1 + T - 1) / T, T, 0, s>>>(Ns, A.d_row_start, A.d_row_ptr, stats);
     // transposed rows per subset
     SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
     const unsigned gW = (unsigned)(((int64_t)M * 64 + T - 1) / T);  // a wavefront per row
-    int *slot = rowT;  // rowT is written only by k_rank_T, after the last read of the slots
-    k_col_count<<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt, slot);
+    // each entry's slot: in rowT when that holds int32 (k_rank_T writes rowT
+    // after the last read of the slots), else in a buffer of its own
+    int *slot = nullptr;
+    if constexpr (sizeof(IT) == sizeof(int)) {
+        slot = (int *)rowT;
+    } else {
+        SVR_HIP(dalloc(&tmp.slot, nnz));
+        slot = tmp.slot;
+    }
+    k_col_count<IT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt, slot);
     k_max_count<<<(unsigned)std::min<int64_t>((NT + T - 1) / T, MAX_BLOCKS), T, 0, s>>>(NT, cnt, stats);
     SVR_HIP(hipGetLastError());
     int64_t nnzT = 0;
     rc = exclusive_scan(cnt, NT, A.d_ptrT, &nnzT, s);
-    if (rc) { cleanup(); return rc; }
-    if (nnzT != nnz) { cleanup(); set_error("transpose count mismatch"); return SVR_EDEVICE; }
-    SVR_HIP(dalloc(&fill, nnz));
-    k_fill_T<WT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
-                                  val, A.d_ptrT, slot, fill);
+    if (rc) return rc;
+    if (nnzT != nnz) { set_error("transpose count mismatch"); return SVR_EDEVICE; }
+    SVR_HIP(dalloc(&tmp.fill, nnz));
+    k_fill_T<WT, IT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_start, A.d_row_ptr, col,
+                                      val, A.d_ptrT, slot, tmp.fill);
     const int64_t groups = (NT + RANK_ROWS - 1) / RANK_ROWS;
-    k_rank_T<WT, RANK_ROWS><<<(unsigned)((groups * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, fill, rowT,
-                                                                               valT);
-    dfree(fill);
-    fill = nullptr;
+    k_rank_T<WT, IT, RANK_ROWS><<<(unsigned)((groups * 32 + T - 1) / T), T, 0, s>>>(NT, A.d_ptrT, tmp.fill,
+                                                                                   rowT, valT);
+    dfree(tmp.fill);  // stream-ordered: after the ranking
+    tmp.fill = nullptr;
     k_sens<WT><<<(N + T - 1) / T, T, 0, s>>>(Ns, N, A.d_ptrT, valT, A.d_sens_t, A.d_sens);
+    // the forward indices in tiled pixel order
+    SVR_HIP(dalloc(&colt, nnz + NNZ_PAD));
+    k_tile_cols<IT><<<(unsigned)((nnz + NNZ_PAD + T - 1) / T), T, 0, s>>>(col, nnz + NNZ_PAD, nnz, A.geom.nx,
+                                                                         A.tx, colt);
+    A.d_colt = colt;
     SVR_HIP(hipGetLastError());
     std::vector<int> h(Ns + 3);
     SVR_HIP(hipMemcpyAsync(h.data(), stats, sizeof(int) * (Ns + 3), hipMemcpyDeviceToHost, s));
@@ -421,46 +437,19 @@ static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
     A.max_col_nnz = h[1];
     A.nnz_sub.assign(Ns, 0);
     for (int t = 0; t < Ns; ++t) A.nnz_sub[t] = (int64_t)h[2 + t + 1] - h[2 + t];
-    cleanup();
-    // 16-bit indices when every pixel index and every subset-local row fits
-    int max_rows = 0;
-    for (int t = 0; t < Ns; ++t) max_rows = std::max(max_rows, A.rows_of(t));
-    A.tx = tiles_x(A.geom.nx);
-    A.Nt = tiled_count(A.geom.nx, A.geom.ny);
-    if (A.idx16 && A.Nt <= 65536 && max_rows <= 65536 && nnz > 0) {
-        uint16_t *c16 = nullptr, *r16 = nullptr;
-        SVR_HIP(dalloc(&c16, nnz + NNZ_PAD));
-        SVR_HIP(dalloc(&r16, nnz + NNZ_PAD));
-        SVR_HIP(hipMemsetAsync(c16 + nnz, 0, sizeof(uint16_t) * NNZ_PAD, s));
-        SVR_HIP(hipMemsetAsync(r16 + nnz, 0, sizeof(uint16_t) * NNZ_PAD, s));
-        const unsigned gn = (unsigned)((nnz + T - 1) / T);
-        k_narrow<<<gn, T, 0, s>>>(col, nnz, c16);
-        k_narrow<<<gn, T, 0, s>>>(rowT, nnz, r16);
-        SVR_HIP(hipGetLastError());
-        dfree(col);  // stream-ordered: after the narrowing kernels
-        dfree(rowT);
-        A.d_col = c16;
-        A.d_rowT = r16;
-    } else {
-        A.idx16 = 0;
-    }
-    // the forward indices in tiled pixel order
-    const unsigned gp = (unsigned)((nnz + NNZ_PAD + T - 1) / T);
-    if (A.idx16) {
-        uint16_t *ct = nullptr;
-        SVR_HIP(dalloc(&ct, nnz + NNZ_PAD));
-        k_tile_cols<uint16_t><<<gp, T, 0, s>>>((const uint16_t *)A.d_col, nnz + NNZ_PAD, nnz, A.geom.nx, A.tx, ct);
-        A.d_colt = ct;
-    } else {
-        int *ct = nullptr;
-        SVR_HIP(dalloc(&ct, nnz + NNZ_PAD));
-        k_tile_cols<int><<<gp, T, 0, s>>>((const int *)A.d_col, nnz + NNZ_PAD, nnz, A.geom.nx, A.tx, ct);
-        A.d_colt = ct;
-    }
-    SVR_HIP(hipGetLastError());
-    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + NT + 1 + (Ns + 1)) + (int64_t)A.ibytes() * 3 * (nnz + NNZ_PAD) +
+    A.bytes = (int64_t)sizeof(int) * (2 * (M + 1) + NT + 1 + (Ns + 1)) + (int64_t)sizeof(IT) * 3 * (nnz + NNZ_PAD) +
               (int64_t)A.wbytes() * 2 * (nnz + NNZ_PAD) + (int64_t)sizeof(float) * NT + (int64_t)sizeof(double) * N;
     return SVR_OK;
+}
+
+template <typename WT>
+static int build_typed(Matrix &A, const float *mu, hipStream_t s) {
+    int max_rows = 0;
+    for (int t = 0; t < A.Ns; ++t) max_rows = std::max(max_rows, A.rows_of(t));
+    A.tx = tiles_x(A.geom.nx);
+    A.Nt = tiled_count(A.geom.nx, A.geom.ny);
+    A.idx16 = A.idx16 && A.Nt <= 65536 && max_rows <= 65536;
+    return A.idx16 ? build_indexed<WT, uint16_t>(A, mu, s) : build_indexed<WT, int>(A, mu, s);
 }
 
 int build_matrix(Matrix &A, const float *mu_dev, hipStream_t s) {
