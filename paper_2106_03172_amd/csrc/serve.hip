@@ -5,7 +5,7 @@
 // launch per iteration for all requests of the same storage types; else each
 // request on one of the server's streams), then admits queued requests (FIFO)
 // while a slot is free and their device footprint fits the memory budget.
-// The admissions of a tick run on host threads, one per request, so their
+// The admissions of a tick run on a pool of host threads (up to 16), so their
 // matrix builds (which wait on the host for their sizes) and initial epochs
 // overlap each other and the enqueued epochs; requests of one geometry,
 // subset count and weight type share one matrix, built once.  A request's
@@ -15,6 +15,7 @@
 // cache and their matrix, once unused, stays idle for later requests of its
 // key; both give way when an admission needs the room in the budget.
 #include <algorithm>
+#include <atomic>
 #include <chrono>
 #include <cmath>
 #include <cstring>
@@ -25,6 +26,7 @@
 #include <new>
 #include <thread>
 #include <tuple>
+#include <utility>
 #include <vector>
 
 #include "batch.h"
@@ -265,32 +267,34 @@ int admit(svr_server *S, Request *q, hipStream_t s) {
     return SVR_OK;
 }
 
-// Runs fn(S, q, q's stream) for every request at once, one host thread each: a matrix build
-// waits on the host for its sizes, and several builds' waits (and their kernels, on different
-// streams) then overlap.
+// Runs fn(S, q, q's stream) for every request, on up to ADMIT_THREADS host threads that take
+// the requests in turn: a matrix build waits on the host for its sizes, and several builds'
+// waits (and their kernels, on different streams) then overlap.
+constexpr size_t ADMIT_THREADS = 16;
 void run_each(svr_server *S, const std::vector<Request *> &adm, std::vector<int> &rcs,
               int (*fn)(svr_server *, Request *, hipStream_t)) {
     rcs.assign(adm.size(), SVR_OK);
+    if (adm.empty()) return;
     if (adm.size() == 1) {
         rcs[0] = fn(S, adm[0], S->streams[adm[0]->stream]);
         return;
     }
+    std::atomic<size_t> next{0};
+    auto work = [S, &adm, &rcs, &next, fn] {
+        const bool on_device = hipSetDevice(S->device) == hipSuccess;
+        for (size_t k; (k = next.fetch_add(1)) < adm.size();)
+            rcs[k] = on_device ? fn(S, adm[k], S->streams[adm[k]->stream]) : SVR_EDEVICE;
+    };
     std::vector<std::thread> th;
-    th.reserve(adm.size());
-    for (size_t k = 0; k < adm.size(); ++k) {
-        auto work = [S, &adm, &rcs, k, fn] {
-            if (hipSetDevice(S->device) != hipSuccess) {
-                rcs[k] = SVR_EDEVICE;
-                return;
-            }
-            rcs[k] = fn(S, adm[k], S->streams[adm[k]->stream]);
-        };
+    const size_t n_threads = std::min(adm.size(), ADMIT_THREADS) - 1;  // and this one
+    for (size_t k = 0; k < n_threads; ++k) {
         try {
             th.emplace_back(work);
         } catch (const std::exception &) {
-            work();  // no thread to be had: on this one
+            break;  // no more threads to be had: the ones running (and this one) take the rest
         }
     }
+    work();
     for (std::thread &t : th) t.join();
 }
 
@@ -306,30 +310,30 @@ void batched_epoch(svr_server *S) {
     // The requests of one storage type (weight type, index width) split into batches of up to
     // BATCH_MAX, fixed for the tick; each batch takes a stream of its own for the whole tick, so
     // a request's iterations stay in order while different batches' launches overlap.
+    using BatchKey = std::pair<int, int>;  // storage type, the batch's index within its type
     struct Res {
         Request *q;
         std::vector<int32_t> order;
-        int batch;  // key: storage type * 64 + the batch's index within its storage type
+        BatchKey batch;
     };
     std::vector<Res> rs;
     std::map<int, int> per_type;
-    std::map<int, int> stream_of_batch;
+    std::map<BatchKey, int> stream_of_batch;
     int max_ns = 0;
     for (uint64_t tk : S->resident) {
         Request *q = S->reqs[tk].get();
         const int Ns = q->req.n_subsets;
         const Matrix &A = *q->A;
         const int type = A.wtype * 2 + A.idx16;
-        Res r{q, std::vector<int32_t>(Ns), type * 64 + per_type[type]++ / BATCH_MAX};
+        Res r{q, std::vector<int32_t>(Ns), BatchKey(type, per_type[type]++ / BATCH_MAX)};
         for (int i = 0; i < Ns; ++i) r.order[i] = q->rng.below(Ns);
         if (!stream_of_batch.count(r.batch)) stream_of_batch[r.batch] = (int)stream_of_batch.size();
         max_ns = std::max(max_ns, Ns);
         rs.push_back(std::move(r));
     }
-    auto stream_of = [&](int batch) { return S->streams[stream_of_batch[batch] % (int)S->streams.size()]; };
+    auto stream_of = [&](const BatchKey &batch) { return S->streams[stream_of_batch[batch] % (int)S->streams.size()]; };
     for (int j = 0; j < max_ns; ++j) {
-        // key: weight type, index width
-        std::map<int, std::vector<std::pair<Request *, IterPlan>>> groups, anchors;
+        std::map<BatchKey, std::vector<std::pair<Request *, IterPlan>>> groups, anchors;
         for (Res &r : rs) {
             Request *q = r.q;
             if (j >= (int)r.order.size() || q->status != SVR_OK) continue;

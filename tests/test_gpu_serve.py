@@ -387,3 +387,32 @@ def test_trim_drops_idle_matrices_and_kept_blocks():
     with pytest.raises(pkg.binding.SvrError):
         S.trim(drop_matrices=True, keep_bytes=-1)
     S.close()
+
+
+def test_storage_types_batch_apart_past_sixty_four_batches():
+    """517 resident requests of one tiny geometry (two subsets, so each epoch
+    has an anchor and a plain iteration): 516 with int32 indices (65 batches
+    of that storage type) and one with 16-bit indices.  Each
+    batch holds one storage type however many batches a type has (a key of
+    type * 64 + batch index once put the 16-bit request into the 65th int32
+    batch); the two kinds of request end bitwise as each does served alone."""
+    P = datagen.make_problem(8, 8, 2.0, 4, 12, 2.0, 2, 1e3, seed=77)
+    prm = pkg.params("svrem", alpha=ALPHA, eta=1, beta=BETA)
+    i32 = pkg.SVR_W_F32 | pkg.binding.SVR_W_INDEX32
+    kinds = [i32] * 516 + [pkg.SVR_W_F32]
+    S = pkg.Server(4 << 30, max_slots=600, n_streams=3)
+    tk = [S.submit(P.geom, 2, P.g, P.w, prm, 2, 900 + i, wtype=wt) for i, wt in enumerate(kinds)]
+    S.step(1)
+    assert S.stats()["admitted"] == len(kinds) and S.stats()["resident"] == len(kinds)
+    S.step(0)
+    res = {i: S.poll(tk[i]) for i in (0, 515, 516)}
+    S.close()
+    for i, r in res.items():
+        A = pkg.Server(1 << 30, max_slots=1, n_streams=1)
+        t = A.submit(P.geom, 2, P.g, P.w, prm, 2, 900 + i, wtype=kinds[i])
+        A.step(0)
+        alone = A.poll(t)
+        A.close()
+        assert r["status"] == 0 and alone["status"] == 0
+        np.testing.assert_array_equal(r["f"], alone["f"])
+        assert r["phi"] == alone["phi"]
