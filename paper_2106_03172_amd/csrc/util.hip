@@ -94,7 +94,7 @@ hipError_t dmalloc(void **p, size_t bytes) {
         auto it = c->idle.lower_bound(bytes);
         if (it != c->idle.end() && it->first <= bytes + bytes / 4) {
             *p = it->second;
-            c->out.emplace(it->second, it->first);
+            c->out[it->second] = it->first;
             c->idle_bytes -= (int64_t)it->first;
             c->idle.erase(it);
             ++c->reuses;
@@ -104,8 +104,10 @@ hipError_t dmalloc(void **p, size_t bytes) {
     keep_pool_memory();
     const hipError_t e = hipMallocAsync(p, bytes, g_alloc_stream);
     if (c && e == hipSuccess) {
+        // assigned, not inserted: an entry left by a block the cache handed out but that was
+        // freed outside its scope may name the same address with another size
         std::lock_guard<std::mutex> lk(c->mu);
-        c->out.emplace(*p, bytes);
+        c->out[*p] = bytes;
     }
     return e;
 }
