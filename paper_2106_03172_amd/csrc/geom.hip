@@ -140,18 +140,41 @@ __global__ void k_siddon_fill(svr_geometry g, int M, const int *row_sino, const 
 }
 
 // ---- transposition (per subset), deterministic ------------------------------
-// entries per (subset, pixel), and each entry's arrival rank among its
-// transposed row's entries (slot, any order); a wavefront per row of A, lanes
-// over its entries
+// Entries per (subset, pixel), and each entry's arrival rank among its
+// transposed row's entries (slot, any order).  A subset's rows, hence its
+// entries, are one contiguous range of A, so a workgroup per (subset, chunk of
+// CC_PIX pixels) reads that range once, counts the entries of its chunk in an
+// LDS histogram (the atomic's return value is the slot) and writes the
+// chunk's counts: no global atomics, and every count is written once, so the
+// counts need no clearing.
+constexpr int CC_PIX = 16384;  // 64 KB of int counts per workgroup
+constexpr int CC_THREADS = 1024;
+constexpr int CC_ILP = 8;
 template <typename IT>
-__global__ void k_col_count(int M, int B, int Ns, int N, const int *row_sino, const int *row_ptr,
-                            const IT *col, int *cnt, int *slot) {
-    const int64_t gid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const int r = (int)(gid >> 6), lane = (int)(gid & 63);
-    if (r >= M) return;
-    const int t = (row_sino[r] / B) % Ns;
-    int *c = cnt + (int64_t)t * N;
-    for (int i = row_ptr[r] + lane; i < row_ptr[r + 1]; i += 64) slot[i] = atomicAdd(&c[col[i]], 1);
+__global__ void __launch_bounds__(CC_THREADS)
+k_col_count(int N, int chunks, const int *row_start, const int *row_ptr, const IT *col, int *cnt, int *slot) {
+    __shared__ int hist[CC_PIX];
+    const int t = (int)blockIdx.x / chunks, c = (int)blockIdx.x - t * chunks;
+    const int n0 = c * CC_PIX, n1 = min(N, n0 + CC_PIX);
+    for (int k = threadIdx.x; k < CC_PIX; k += CC_THREADS) hist[k] = 0;
+    __syncthreads();
+    const int i0 = row_ptr[row_start[t]], i1 = row_ptr[row_start[t + 1]];
+    // CC_ILP entries a thread per pass, all loaded before any is used, so that
+    // the pass waits on one memory latency, not CC_ILP of them
+    for (int base = i0 + (int)threadIdx.x; base < i1; base += CC_THREADS * CC_ILP) {
+        int n[CC_ILP];
+#pragma unroll
+        for (int k = 0; k < CC_ILP; ++k) {
+            const int i = base + k * CC_THREADS;
+            n[k] = i < i1 ? (int)col[i] : -1;
+        }
+#pragma unroll
+        for (int k = 0; k < CC_ILP; ++k)
+            if (n[k] >= n0 && n[k] < n1) slot[base + k * CC_THREADS] = atomicAdd(&hist[n[k] - n0], 1);
+    }
+    __syncthreads();
+    int *out = cnt + (int64_t)t * N;
+    for (int n = n0 + (int)threadIdx.x; n < n1; n += CC_THREADS) out[n] = hist[n - n0];
 }
 
 // A transposed entry between the fill and the ranking: its subset-local row
@@ -397,7 +420,6 @@ static int build_indexed(Matrix &A, const float *mu, hipStream_t s) {
     k_row_stats<<<std::min<unsigned>(gM, MAX_BLOCKS), T, 0, s>>>(M, A.d_row_ptr, stats);
     k_subset_offsets<<<(Ns + 1 + T - 1) / T, T, 0, s>>>(Ns, A.d_row_start, A.d_row_ptr, stats);
     // transposed rows per subset
-    SVR_HIP(hipMemsetAsync(cnt, 0, sizeof(int) * NT, s));
     const unsigned gW = (unsigned)(((int64_t)M * 64 + T - 1) / T);  // a wavefront per row
     // each entry's slot: in rowT when that holds int32 (k_rank_T writes rowT
     // after the last read of the slots), else in a buffer of its own
@@ -408,7 +430,9 @@ static int build_indexed(Matrix &A, const float *mu, hipStream_t s) {
         SVR_HIP(dalloc(&tmp.slot, nnz));
         slot = tmp.slot;
     }
-    k_col_count<IT><<<gW, T, 0, s>>>(M, B, Ns, N, A.d_row_sino, A.d_row_ptr, col, cnt, slot);
+    const int chunks = (N + CC_PIX - 1) / CC_PIX;
+    k_col_count<IT><<<(unsigned)((int64_t)Ns * chunks), CC_THREADS, 0, s>>>(N, chunks, A.d_row_start, A.d_row_ptr,
+                                                                         col, cnt, slot);
     k_max_count<<<(unsigned)std::min<int64_t>((NT + T - 1) / T, MAX_BLOCKS), T, 0, s>>>(NT, cnt, stats);
     SVR_HIP(hipGetLastError());
     int64_t nnzT = 0;

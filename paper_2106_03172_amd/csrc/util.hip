@@ -215,9 +215,11 @@ int exclusive_scan(const int *in, int64_t n, int *out, int64_t *total, hipStream
     k_scan_blocksums<<<1, 1024, 0, s>>>(bsum, nb);
     SVR_HIP(hipMemcpyAsync(total, bsum + nb, sizeof(int64_t), hipMemcpyDeviceToHost, s));
     SVR_HIP(hipStreamSynchronize(s));
-    if (*total < 0 || *total > INT32_MAX) {
+    // headroom below INT32_MAX: the kernels that walk a range of these offsets step an int
+    // index up to a few workgroups past its end
+    if (*total < 0 || *total > INT32_MAX - 65536) {
         dfree(bsum);
-        set_error("scan total %lld exceeds int32", (long long)*total);
+        set_error("scan total %lld exceeds the int32 index range", (long long)*total);
         return SVR_EINVAL;
     }
     k_scan_apply<<<nb, SCAN_T, 0, s>>>(in, n, bsum, out);
