@@ -149,7 +149,10 @@ __global__ void k_siddon_fill(svr_geometry g, int M, const int *row_sino, const 
 // counts need no clearing.
 constexpr int CC_PIX = 16384;  // 64 KB of int counts per workgroup
 constexpr int CC_THREADS = 1024;
-constexpr int CC_ILP = 8;
+#ifndef SVR_CC_ILP
+#define SVR_CC_ILP 16
+#endif
+constexpr int CC_ILP = SVR_CC_ILP;
 template <typename IT>
 __global__ void __launch_bounds__(CC_THREADS)
 k_col_count(int N, int chunks, const int *row_start, const int *row_ptr, const IT *col, int *cnt, int *slot) {
