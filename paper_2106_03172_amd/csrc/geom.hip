@@ -301,7 +301,17 @@ __global__ void k_sens(int Ns, int N, const int *ptrT, const WT *valT, float *se
     for (int t = 0; t < Ns; ++t) {
         int64_t q = (int64_t)t * N + n;
         double s = 0.0;
-        for (int i = ptrT[q]; i < ptrT[q + 1]; ++i) s = s + (double)load_w(valT[i]);
+        const int e = ptrT[q + 1];
+        // eight loads in flight, summed in entry order (valT's zero padding past its last
+        // non-zero keeps the loads past e in bounds)
+        for (int i = ptrT[q]; i < e; i += 8) {
+            WT v[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) v[k] = valT[i + k];
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (i + k < e) s = s + (double)load_w(v[k]);
+        }
         sens_t[q] = (float)s;
         tot = tot + s;
     }
