@@ -355,11 +355,25 @@ __global__ void k_subset_offsets(int Ns, const int *row_start, const int *row_pt
 }
 
 // forward indices in tiled pixel order; the pad entries stay 0
+// (8 bytes of indices a thread: one load and one store)
+template <typename IT>
+constexpr int TILE_COLS_V = 8 / (int)sizeof(IT);
 template <typename IT>
 __global__ void k_tile_cols(const IT *col, int64_t n_all, int64_t nnz, int nx, int tx, IT *colt) {
-    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n_all) return;
-    colt[i] = i < nnz ? (IT)tiled_index((int)col[i], nx, tx) : (IT)0;
+    constexpr int V = TILE_COLS_V<IT>;
+    struct alignas(8) Pack {
+        IT v[V];
+    };
+    const int64_t i0 = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) * V;
+    if (i0 >= n_all) return;
+    if (i0 + V <= n_all) {  // the arrays' bases are 256-byte aligned, i0 a multiple of V
+        Pack p = *(const Pack *)(col + i0);
+#pragma unroll
+        for (int k = 0; k < V; ++k) p.v[k] = i0 + k < nnz ? (IT)tiled_index((int)p.v[k], nx, tx) : (IT)0;
+        *(Pack *)(colt + i0) = p;
+    } else {
+        for (int64_t i = i0; i < n_all; ++i) colt[i] = i < nnz ? (IT)tiled_index((int)col[i], nx, tx) : (IT)0;
+    }
 }
 
 // Every slot p of the tiled copy: the pixel it holds (the inverse of
@@ -463,8 +477,8 @@ static int build_indexed(Matrix &A, const float *mu, hipStream_t s) {
     k_sens<WT><<<(N + T - 1) / T, T, 0, s>>>(Ns, N, A.d_ptrT, valT, A.d_sens_t, A.d_sens);
     // the forward indices in tiled pixel order
     SVR_HIP(dalloc(&colt, nnz + NNZ_PAD));
-    k_tile_cols<IT><<<(unsigned)((nnz + NNZ_PAD + T - 1) / T), T, 0, s>>>(col, nnz + NNZ_PAD, nnz, A.geom.nx,
-                                                                         A.tx, colt);
+    const int64_t packs = (nnz + NNZ_PAD + TILE_COLS_V<IT> - 1) / TILE_COLS_V<IT>;
+    k_tile_cols<IT><<<(unsigned)((packs + T - 1) / T), T, 0, s>>>(col, nnz + NNZ_PAD, nnz, A.geom.nx, A.tx, colt);
     A.d_colt = colt;
     SVR_HIP(hipGetLastError());
     std::vector<int> h(Ns + 3);
